@@ -1,0 +1,184 @@
+"""Pins of the oracle's random numbers and walk estimators (Sec. 4.3)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import laplacian as olap
+from oracle import poly as opoly
+from oracle import rng as orng
+from oracle import walk as owalk
+from paper_2207_14589_amd import synth
+
+# Known-answer vectors published with the Random123 library for Philox4x32-10:
+# (counter, key) -> output.  Stored in tests/golden/philox4x32_10_kat.txt.
+import os
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+
+
+def _kat():
+    rows = []
+    for line in open(GOLD):
+        line = line.split("#")[0].strip()
+        if line:
+            rows.append([int(x, 16) for x in line.split()])
+    return rows
+
+
+def test_philox_known_answers():
+    rows = _kat()
+    assert len(rows) >= 3
+    for r in rows:
+        ctr, key, out = r[0:4], r[4:6], r[6:10]
+        got = orng.philox4x32_10(*ctr, *key)
+        assert [int(x) for x in got] == out
+
+
+def test_lemire_power_of_two_is_top_bits():
+    """For s = 2^b no word is rejected and the draw is the top b bits of word 0."""
+    c0 = np.arange(5000)
+    for b in (1, 7, 20, 31):
+        draw = orng.bounded(123, c0, 4, 9, 3, 1 << b)
+        w = orng.stream_words(123, c0, 4, 9, 3, 0)[0]
+        np.testing.assert_array_equal(draw, (w >> np.uint64(32 - b)).astype(np.int64))
+
+
+def test_lemire_rejection_makes_uniform():
+    """s = 3 * 2^30: plain multiply-shift would give residue 0 mod 3 half the
+    time; with the rejection step every residue has probability 1/3."""
+    s = 3 << 30
+    draw = orng.bounded(7, np.arange(60000), 1, 2, 0, s)
+    assert draw.min() >= 0 and draw.max() < s
+    frac0 = np.mean(draw % 3 == 0)
+    assert abs(frac0 - 1 / 3) < 0.01
+
+
+def test_lemire_small_bounds_uniform():
+    draw = orng.bounded(99, np.arange(90000), 0, 0, 1, 9)
+    counts = np.bincount(draw, minlength=9)
+    chi2 = np.sum((counts - 10000.0) ** 2 / 10000.0)
+    assert chi2 < 30.0   # 8 dof, p ~ 3e-4
+
+
+def test_uniform53():
+    u = orng.uniform53(5, np.arange(50000), 0, 0, 0)
+    assert u.min() >= 0.0 and u.max() < 1.0
+    assert abs(u.mean() - 0.5) < 0.01
+
+
+def _tiny_graph(kind, weighted):
+    src = [0, 0, 1, 1, 2, 3, 4, 2]
+    dst = [1, 2, 2, 3, 4, 4, 5, 5]
+    w = synth.random_weights(len(src), 3) if weighted else None
+    return olap.laplacian(6, src, dst, w, kind=kind)
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_walk_summand_brute_force(kind):
+    """eq. (walk_summand): sum over all chains in E^l of alpha_c x_e1 x_el^T
+    equals L^l; checked by enumerating E^l on an 8-edge graph."""
+    lap = _tiny_graph(kind, weighted=True)
+    m = lap.eu.shape[0]
+    X = np.zeros((m, lap.n))
+    for e in range(m):
+        X[e, lap.eu[e]] = np.sqrt(lap.ew[e]) * lap.scale[lap.eu[e]]
+        X[e, lap.ev[e]] = -np.sqrt(lap.ew[e]) * lap.scale[lap.ev[e]]
+    G = X @ X.T   # edge-pair inner products x_e^T x_f
+    for ell in (1, 2, 3):
+        acc = np.zeros((lap.n, lap.n))
+        for c in itertools.product(range(m), repeat=ell):
+            alpha = 1.0
+            for a, b in zip(c[:-1], c[1:]):
+                alpha *= G[a, b]
+            if alpha != 0.0:
+                acc += alpha * np.outer(X[c[0]], X[c[-1]])
+        np.testing.assert_allclose(acc, np.linalg.matrix_power(lap.dense(), ell), atol=1e-12)
+
+
+def _exact_poly(lap, c, V):
+    Ld = lap.dense()
+    return sum(ci * np.linalg.matrix_power(Ld, i) @ V for i, ci in enumerate(c))
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_importance_sampler_exact_expectation(kind, weighted):
+    """Enumerate every draw sequence of the importance sampler with its
+    probability; the expectation must equal sum_i c_i L^i V exactly."""
+    lap = _tiny_graph(kind, weighted)
+    W = owalk._Walker(lap)
+    V = synth.gaussian_block(lap.n, 3, 8)
+    c = np.array([0.3, -0.7, 0.4, 0.25])
+    ell = len(c) - 1
+    expect = c[0] * V.copy()
+    for r in range(lap.n):
+        dr = W.deg[r]
+
+        def rec(pos, omega, prob, i):
+            contrib = c[i] * omega * W.edge_dot_V(np.array([pos]), V)[0]
+            expect[r] += prob * contrib
+            if i == ell:
+                return
+            a = W.row_of[pos]
+            dh = W.deg[a] + W.deg[W.col[pos]] - 1
+            for t in range(dh):
+                q, dot, degH = W.step(np.array([pos]), np.array([t]))
+                rec(int(q[0]), omega * float(dot[0]) * int(degH[0]), prob / dh, i + 1)
+
+        for t0 in range(dr):
+            pos = W.rowptr[r] + t0
+            rec(pos, dr * float(W.h(np.array([pos]), np.array([r]))[0]), 1.0 / dr, 1)
+    np.testing.assert_allclose(expect, _exact_poly(lap, c, V), atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_importance_monte_carlo(kind):
+    """The sampler with its Philox draws is unbiased: z-scores over seeds."""
+    lap = _tiny_graph(kind, weighted=True)
+    V = synth.gaussian_block(lap.n, 2, 1)
+    c = opoly.limit_exp(4).coeffs
+    exact = opoly.apply_terms(lap.L, opoly.limit_exp(4), V)
+    est = np.stack([owalk.estimate_importance(lap, c, V, 3000, seed=s) for s in range(24)])
+    mean, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(est.shape[0])
+    z = np.abs(mean - exact) / np.maximum(se, 1e-15)
+    assert z.max() < 5.0
+    # the same seed gives the same walks
+    np.testing.assert_array_equal(est[3], owalk.estimate_importance(lap, c, V, 3000, seed=3))
+
+
+def test_importance_first_power_exact_per_walk_average():
+    """For l = 1 the estimate of row r averages d_r (x_e1)_r x_e1^T V over
+    uniform e_1; with every incident edge visited it equals (L V)_r."""
+    lap = _tiny_graph(olap.SYM_NORMALIZED, weighted=True)
+    V = synth.gaussian_block(lap.n, 2, 4)
+    est = owalk.estimate_importance(lap, [0.0, 1.0], V, 20000, seed=1)
+    np.testing.assert_allclose(est, lap.L @ V, atol=0.05 * np.abs(lap.L @ V).max())
+
+
+def test_reject_regular_graph_accepts_all():
+    """On a cycle every edge has deg_H = 3 = 2 deg* - 1, so every prefix is
+    accepted (acceptance probability prod deg_H / deg*_inc = 1)."""
+    n, s, d = synth.cycle_graph(7)
+    lap = olap.laplacian(n, s, d, kind=olap.COMBINATORIAL)
+    V = synth.gaussian_block(n, 2, 2)
+    _, counts = owalk.estimate_reject(lap, [0, 1, 1, 1, 1], V, 1000, seed=4)
+    assert list(counts) == [1000] * 4
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_reject_monte_carlo(kind):
+    lap = _tiny_graph(kind, weighted=False)
+    V = synth.gaussian_block(lap.n, 2, 6)
+    c = np.array([0.5, -0.5, 0.25, -0.125])
+    exact = _exact_poly(lap, c, V)
+    ests, accs = [], []
+    for s in range(16):
+        y, cnt = owalk.estimate_reject(lap, c, V, 40000, seed=s)
+        ests.append(y)
+        accs.append(cnt)
+    est = np.stack(ests)
+    mean, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(est.shape[0])
+    z = np.abs(mean - exact) / np.maximum(se, 1e-15)
+    assert z.max() < 5.0
+    accs = np.array(accs)
+    assert np.all(accs[:, 0] == 40000) and np.all(accs[:, 1:] < 40000) and np.all(accs > 0)

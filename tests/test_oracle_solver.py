@@ -1,0 +1,131 @@
+"""Pins of the oracle's solver, metrics, k-means and gradient."""
+import numpy as np
+import pytest
+
+from oracle import grad as ograd
+from oracle import kmeans as okm
+from oracle import laplacian as olap
+from oracle import poly as opoly
+from oracle import solver as osol
+from paper_2207_14589_amd import synth
+
+
+def _rotated_pair(n, angles, seed=0):
+    """Two k-dim subspaces whose principal angles are exactly `angles`."""
+    g = np.random.default_rng(seed)
+    k = len(angles)
+    Q, _ = np.linalg.qr(g.standard_normal((n, 2 * k)))
+    A = Q[:, :k]
+    B = np.cos(angles) * Q[:, :k] + np.sin(angles) * Q[:, k:]
+    return A, B
+
+
+def test_metrics_known_angles():
+    ang = np.array([1e-9, 3e-7, 0.2, 0.7])
+    A, B = _rotated_pair(50, ang)
+    assert osol.max_principal_angle(A, B) == pytest.approx(0.7, rel=1e-12)
+    assert osol.subspace_error(A, B) == pytest.approx(np.mean(np.sin(ang) ** 2), rel=1e-10)
+    A2, B2 = _rotated_pair(50, np.array([2e-8, 1e-9]))
+    assert osol.max_principal_angle(A2, B2) == pytest.approx(2e-8, rel=1e-6)
+    np.testing.assert_allclose(osol.vector_angles(A, B), ang, rtol=1e-6, atol=1e-15)
+    assert osol.eigenvector_streak(A, B, eps=0.5) == 3
+
+
+@pytest.fixture(scope="module")
+def sbm2000():
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    lap = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, full = osol.dense_bottom_k(lap.dense(), 10)
+    return lap, labels, lam, U, full
+
+
+def test_solver_matches_dense_eigh(sbm2000):
+    lap, labels, lam, U, full = sbm2000
+    k = 10
+    p = opoly.limit_exp(8)
+    V0 = synth.gaussian_block(lap.n, k + 4, 2)
+    res = osol.subspace_iteration(lap.L, lambda Q: opoly.apply_terms(lap.L, p, Q), k, V0,
+                                  max_iters=400, tol=1e-10, guard=4, Vstar=U)
+    assert res.converged
+    assert osol.max_principal_angle(U, res.Q) < 1e-8
+    np.testing.assert_allclose(res.evals[1:], lam[1:], rtol=1e-9)
+    assert abs(res.evals[0]) < 1e-9
+
+
+def test_sped_fewer_steps_than_plain(sbm2000):
+    """Sec. 5: the dilated operator needs fewer solver steps than the identity
+    transform (plain L reversed by eq. reveig)."""
+    lap, labels, lam, U, full = sbm2000
+    k = 10
+    V0 = synth.gaussian_block(lap.n, k + 4, 2)
+    steps = {}
+    for name, p in (("plain", opoly.plain(2.0)), ("sped", opoly.limit_exp(8))):
+        r = osol.subspace_iteration(lap.L, lambda Q, p=p: opoly.apply_terms(lap.L, p, Q), k, V0,
+                                    max_iters=2000, tol=1e-8, guard=4)
+        assert r.converged
+        steps[name] = r.iters
+    assert steps["sped"] * 1.5 < steps["plain"]
+
+
+def test_oja_step_converges(sbm2000):
+    lap, labels, lam, U, full = sbm2000
+    k = 10
+    p = opoly.limit_exp(8)
+    V0 = synth.gaussian_block(lap.n, k + 4, 5)
+    r = osol.subspace_iteration(lap.L, lambda Q: opoly.apply_terms(lap.L, p, Q), k, V0,
+                                max_iters=600, tol=1e-8, guard=4, eta=1.0)
+    assert r.converged and osol.max_principal_angle(U, r.Q) < 1e-6
+
+
+def test_kmeans_recovers_cliques_and_sbm(sbm2000):
+    n, s, d, labels = synth.disjoint_cliques(5, 8)
+    lap = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    _, U, _ = osol.dense_bottom_k(lap.dense(), 5)
+    X = okm.normalize_rows(U)
+    C0 = okm.kmeans_pp(X, 5, seed=0)
+    lab, C, inertia, it = okm.lloyd(X, C0)
+    assert okm.adjusted_rand_index(lab, labels) == pytest.approx(1.0)
+    assert inertia < 1e-20
+    lap2, labels2, lam, U2, full = sbm2000
+    X2 = okm.normalize_rows(U2)
+    best = min((okm.lloyd(X2, okm.kmeans_pp(X2, 10, seed=s)) for s in range(4)), key=lambda r: r[2])
+    assert okm.adjusted_rand_index(best[0], labels2) > 0.99
+
+
+def test_ari_textbook_values():
+    assert okm.adjusted_rand_index([0, 0, 1, 1], [1, 1, 0, 0]) == pytest.approx(1.0)
+    # by hand: contingency [[2,1],[1,2]]: sum C(nij,2) = 2, row sums 2*C(3,2) = 6,
+    # column sums 6, C(6,2) = 15 -> (2 - 36/15) / (6 - 36/15) = -1/9
+    assert okm.adjusted_rand_index([0, 0, 0, 1, 1, 1], [0, 0, 1, 0, 1, 1]) == pytest.approx(-1 / 9)
+    assert list(okm.canonical_labels([3, 3, 1, 2, 1])) == [0, 0, 1, 2, 1]
+
+
+def test_gradient_finite_differences_and_adjoint():
+    n, s, d, _ = synth.sbm_bernoulli([15, 20], 0.4, 0.05, seed=3)
+    lap = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    g = np.random.default_rng(0)
+    theta = g.standard_normal(6)
+    X = g.standard_normal((n, 3))
+    G = g.standard_normal((n, 3))
+    dtheta, dX = ograd.backward(lap.L, theta, X, G)
+    Ld = lap.dense()
+    # d theta_j = <G, L^j X> from dense matrix powers
+    ref = [np.sum(G * (np.linalg.matrix_power(Ld, j) @ X)) for j in range(6)]
+    np.testing.assert_allclose(dtheta, ref, rtol=1e-12, atol=1e-12)
+    # loss <G, p(L) X> is linear in theta: central differences are exact up to rounding
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = 0.5
+        fd = (np.sum(G * ograd.forward(lap.L, theta + e, X)) - np.sum(G * ograd.forward(lap.L, theta - e, X)))
+        assert fd == pytest.approx(dtheta[j], rel=1e-10, abs=1e-10)
+    # adjoint: <G, p(L) X> = <p(L) G, X>
+    assert np.sum(G * ograd.forward(lap.L, theta, X)) == pytest.approx(np.sum(dX * X), rel=1e-12)
+    # dX by finite differences of a nonlinear loss sum(p(L)X)^2/2 in one entry
+    Y = ograd.forward(lap.L, theta, X)
+    _, dX2 = ograd.backward(lap.L, theta, X, Y)
+    h = 1e-6
+    Xp, Xm = X.copy(), X.copy()
+    Xp[4, 1] += h
+    Xm[4, 1] -= h
+    fd = (0.5 * np.sum(ograd.forward(lap.L, theta, Xp) ** 2) - 0.5 * np.sum(ograd.forward(lap.L, theta, Xm) ** 2)) / (2 * h)
+    assert fd == pytest.approx(dX2[4, 1], rel=1e-6)
