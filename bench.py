@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPED hot path on one MI355X.
+
+Workload: stochastic block model, 10^6 nodes in 100 equal blocks, mean degree
+20 with 5% of edges between blocks, symmetric normalised Laplacian (float32
+values, int32 columns, int64 row pointers), a 32-column float32 block and the
+degree-16 limit polynomial M = (I - L/16)^16.
+
+One step = one pass of the whole hot path over the resident block Q:
+  1. W = M Q exactly: 16 fused sparse-times-block launches;
+  2. the walk estimate of M Q, 8 importance-sampled walks per row;
+  3. Cholesky QR2 of W (float64 Gram on the matrix cores, 32x32 Cholesky);
+  4. Rayleigh-Ritz on L with residuals (one more sparse product, Gram,
+     Jacobi, two rotations); Q <- Ritz vectors.
+`value` is the p(L)V bandwidth: algorithmic bytes of one exact application
+divided by its time, measured with events around step 1 inside every timed
+step.  The roofline object prices one sparse step launch; `cpu_baseline` times
+the float64 oracle on the host on one full application of the same workload.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                  [--no-solve]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "p(L)·V GB/s (% HBM peak); time to bottom-k at 1e-6, SPED vs plain L"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmm_sbm1m_k32_traffic.json")
+SPMM_SRC = os.path.join(ROOT, "paper_2207_14589_amd", "csrc", "spmm.hip")
+
+
+def spmm_step_bytes(n, nnz, k, horner=False, b_val=4, b_u=4):
+    """Compulsory bytes of one fused step: row pointers, column ids and values
+    once, the block read once and written once (Horner also reads X once),
+    plus the diagonal."""
+    return 8 * (n + 1) + nnz * (4 + b_val) + 4 * n + n * k * (2 * b_u + (b_u if horner else 0))
+
+
+def kernel_source_hash():
+    with open(SPMM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_alg):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline_leg(n, s, d, X, ell, alg_bytes):
+    import numpy as np
+
+    from oracle import laplacian as olap
+    from oracle import poly as opoly
+
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    Xd = X.astype(np.float64)
+    t0 = time.perf_counter()
+    opoly.apply_limit_product(ref.L, ell, Xd)
+    dt = time.perf_counter() - t0
+    return {"value": round(ell * alg_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 3),
+            "sample": f"one full degree-{ell} application (I - L/{ell})^{ell} V on the same {n}-node graph, "
+                      f"{X.shape[1]} columns, float64 scipy CSR products (single thread)"}
+
+
+def time_to_tolerance(sped, synth, torch, np):
+    """SPED (limit, l = 8) against the plain operator 2I - L, same solver,
+    cadence and precision: 2,000-node SBM with 10 blocks, bottom 10."""
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    out = {"workload": "SBM n=2000, 10 blocks, p_in=0.05, p_out=0.0005, k=10 (+4 guard), tol 1e-6"}
+    for name, p in (("sped_limit8", sped.transform("limit", 8)), ("plain", None)):
+        sped.bottomk(L, 10, p, V0=V0, guard=4, tol=1e-6, max_iters=5000)  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=1e-6, max_iters=5000)
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": round(dt, 5), "iters": r.stats["iters"], "spmm": r.stats["spmm_count"],
+                     "converged": bool(r.converged), "bound": r.stats["bound"]}
+    out["speedup_sped_vs_plain"] = round(out["plain"]["seconds"] / out["sped_limit8"]["seconds"], 3)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(collectives and sharding are out of scope); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2207_14589_amd import sped, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    k, ell, walks = 32, 16, 8
+    t0 = time.perf_counter()
+    n, s, d, _ = synth.sbm_from_degrees(1_000_000, 100, 19.0, 1.0, seed=1)
+    gen_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = sped.Laplacian(n, s, d, kind="sym")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    X = synth.gaussian_block(n, k, 2).astype(np.float32)
+    Q = torch.from_numpy(X).cuda()
+    sped.orthonormalize(Q, passes=2)
+    W = torch.empty_like(Q)
+    S = torch.empty_like(Q)
+    p = sped.transform("limit", ell)
+    coeffs = p.monomial()
+    stream = torch.cuda.current_stream()
+
+    def step(i, ev):
+        nonlocal Q, W
+        ev[0].record(stream)
+        sped.apply_poly(L, p, Q, out=W)
+        ev[1].record(stream)
+        if args.chain_only:
+            return
+        sped.apply_poly_stochastic(L, coeffs, Q, walks=walks, seed=3, counter=i, out=S)
+        ev[2].record(stream)
+        sped.orthonormalize(W, passes=2)
+        ev[3].record(stream)
+        sped.rayleigh_ritz(L, W)
+        ev[4].record(stream)
+        Q, W = W, Q
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    for i in range(args.warmup):
+        step(i, mk())
+    torch.cuda.synchronize()
+    evs = [mk() for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    chain_ms = np.mean([e[0].elapsed_time(e[1]) for e in evs])
+    parts = {"exact_pLV_ms": round(float(chain_ms), 4)}
+    if not args.chain_only:
+        parts["walk_estimate_ms"] = round(float(np.mean([e[1].elapsed_time(e[2]) for e in evs])), 4)
+        parts["cholqr2_ms"] = round(float(np.mean([e[2].elapsed_time(e[3]) for e in evs])), 4)
+        parts["rayleigh_ritz_ms"] = round(float(np.mean([e[3].elapsed_time(e[4]) for e in evs])), 4)
+    per_launch = spmm_step_bytes(L.n, L.nnz, k)
+    app_bytes = ell * per_launch
+    value = app_bytes / (chain_ms * 1e-3) / 1e9
+    launch_s = chain_ms * 1e-3 / ell
+    achieved = per_launch / launch_s / 1e9
+    traffic = measured_traffic(per_launch)
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "SBM n=1e6, 100 blocks, mean degree 20, 5% cross edges; sym-normalised L; "
+                               f"k={k} float32 block; limit polynomial degree {ell}; {walks} walks/row",
+                   "n": L.n, "nnz": L.nnz, "k": k, "degree": ell, "walks_per_row": walks,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "spmm_light (fused sparse step)",
+                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": per_launch, "avg_launch_us": round(launch_s * 1e6, 3)},
+        "step_breakdown": parts,
+        "pLV_per_s": round(1e3 / chain_ms, 2),
+        "walk_steps_per_s": (round(L.n * walks * ell / (parts["walk_estimate_ms"] * 1e-3), 1)
+                             if "walk_estimate_ms" in parts else None),
+        "setup": {"graph_gen_s": round(gen_s, 3), "laplacian_build_s": round(build_s, 3)},
+    }
+    if not args.no_solve and not args.chain_only:
+        line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
+    if not args.no_cpu_baseline and not args.chain_only:
+        line["cpu_baseline"] = cpu_baseline_leg(n, s, d, X, ell, per_launch)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,333 @@
+/*
+ * sped.h -- C ABI of libsped: eigengap dilation (SPED) of graph Laplacians on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The paper is van der Pol, Gemp, Bachrach, Everett, "Stochastic Parallelizable
+ * Eigengap Dilation for Large Graph Clustering" (arXiv 2207.14589).  Every entry
+ * point below names the passage that defines the operation it computes.
+ *
+ * Conventions for every call
+ *  - Pointers documented as DEVICE point to memory on the current HIP device,
+ *    allocated and owned by the caller; HOST pointers point to host memory.
+ *    The library never allocates device memory: calls that need scratch take a
+ *    caller workspace (ws, ws_bytes).  Calling with ws == NULL and ws_bytes
+ *    != NULL stores the required size in *ws_bytes and returns SPED_OK
+ *    without launching work; calling with ws != NULL and *ws_bytes below that
+ *    size returns SPED_E_WORKSPACE.  A call whose required size is 0 runs
+ *    with ws == NULL and ws_bytes == NULL.  Workspace must be 256-byte aligned.
+ *  - Dense blocks are row-major: element (r, c) of an n x k block with leading
+ *    dimension ld sits at base[r * ld + c]; ld >= k.  A node's k values are
+ *    contiguous.  Element types are given by sped_dtype.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    Calls return without synchronising unless documented otherwise.
+ *  - Arguments are validated on the host before any launch.  On a non-OK
+ *    status nothing has been launched unless documented otherwise, outputs are
+ *    unspecified, and sped_last_error() returns a message for this thread.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef SPED_H
+#define SPED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *sped_stream_t; /* hipStream_t */
+
+typedef enum {
+  SPED_OK = 0,
+  SPED_E_INVALID = 1,       /* bad argument, shape, pointer or value */
+  SPED_E_WORKSPACE = 2,     /* workspace smaller than required */
+  SPED_E_DEVICE = 3,        /* a HIP runtime call failed */
+  SPED_E_NUMERIC = 4,       /* NaN/Inf, or Cholesky breakdown after the shift fallback */
+  SPED_E_NOT_CONVERGED = 5, /* iteration cap reached before the tolerance */
+  SPED_E_UNSUPPORTED = 6    /* valid but not implemented combination */
+} sped_status;
+
+typedef enum { SPED_F32 = 0, SPED_BF16 = 1, SPED_F64 = 2 } sped_dtype;
+
+typedef enum {
+  SPED_LAP_COMBINATORIAL = 0,  /* L = D - A = X^T W X (Sec. 2) */
+  SPED_LAP_SYM_NORMALIZED = 1  /* D^{-1/2} L D^{-1/2} (normalised Laplacian, Sec. 4.1) */
+} sped_lap_kind;
+
+/*
+ * The Laplacian in split CSR form: L = diag(diag) - S, S the off-diagonal
+ * part with S_ij >= 0.  Built by sped_laplacian_csr; all arrays DEVICE.
+ *  rowptr [n+1] int64   row r's entries are [rowptr[r], rowptr[r+1])
+ *  col    [nnz] int32   neighbour ids, strictly ascending within a row
+ *  val    [nnz] float   S_ij = w_ij (combinatorial) or w_ij s_i s_j (normalised)
+ *  rev    [nnz] int64   position of the transposed entry (j, i) of entry (i, j)
+ *  diag   [n]   float   L_ii = d_i (combinatorial) or 1 (normalised; 0 if d_i = 0)
+ *  scale  [n]   float   s_i = 1 (combinatorial) or d_i^{-1/2} (normalised; 0 if d_i = 0)
+ *  bins   [n]   int32   rows with more than SPED_LIGHT_MAX entries, medium rows
+ *                       (<= SPED_MEDIUM_MAX entries) first, then heavy rows
+ * d_i is the weighted degree; nnz = 2 x the number of distinct undirected edges.
+ */
+#define SPED_LIGHT_MAX 128
+#define SPED_MEDIUM_MAX 8192
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  int64_t *rowptr;
+  int32_t *col;
+  float *val;
+  int64_t *rev;
+  float *diag;
+  float *scale;
+  int32_t *bins;
+  int64_t n_medium;
+  int64_t n_heavy;
+  int32_t max_degree;   /* largest number of neighbours of any node (deg* of Sec. 4.3) */
+  int32_t kind;         /* sped_lap_kind */
+  double lambda_bound;  /* 2 (normalised) or 2 max_i d_i (combinatorial): >= lambda_max */
+} sped_csr;
+
+/*
+ * sped_laplacian_csr -- build the Laplacian of an undirected, optionally
+ * weighted graph (Sec. 2: L = X^T X with incidence rows +1 at min(i,j), -1 at
+ * max(i,j); weighted form X^T W X; Sec. 4.1 normalised form).
+ *  n, m        node count (< 2^31) and input edge count
+ *  src, dst    DEVICE int32 [m] endpoints in [0, n); self-loops are ignored
+ *              (their incidence row is zero); repeated pairs add their weights
+ *  w           DEVICE float [m] weights, finite and > 0, or NULL for all ones
+ *  kind        sped_lap_kind
+ *  lcc_only    nonzero: keep only the largest connected component (ties: the
+ *              one holding the smallest node id), relabelled in increasing id
+ *  out         HOST struct; on entry its array pointers must point to DEVICE
+ *              buffers of at least rowptr n+1, col/val/rev 2m, diag/scale/bins
+ *              n elements.  On return n, nnz, n_medium, n_heavy, max_degree,
+ *              kind and lambda_bound are filled in.
+ *  old_of_new  DEVICE int32 [n] or NULL: original id of each kept node
+ * Synchronises `stream` before returning (sizes are read back).  Invalid
+ * endpoints or weights found on the device return SPED_E_INVALID.
+ */
+sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                               const float *w, int32_t kind, int32_t lcc_only, sped_csr *out,
+                               int32_t *old_of_new, void *ws, size_t *ws_bytes,
+                               sped_stream_t stream);
+
+/*
+ * A polynomial of the Laplacian (Sec. 4.1-4.2, Table 2, reversed by eq. reveig).
+ *  SPED_POLY_MONOMIAL: M = sum_{i=0..degree} coeffs[i] Lt^i,
+ *                      Lt = (L - shift I) / scale, evaluated by Horner's rule.
+ *  SPED_POLY_LIMIT:    M = (I - L/degree)^degree, the limit approximation of
+ *                      -exp(-L) reversed with lambda* = 0, evaluated as degree
+ *                      factor applications; coeffs/shift/scale are ignored.
+ * coeffs is HOST [degree+1].  1 <= degree <= 1024.
+ */
+typedef enum { SPED_POLY_MONOMIAL = 0, SPED_POLY_LIMIT = 1 } sped_poly_kind;
+typedef struct {
+  int32_t kind;
+  int32_t degree;
+  const double *coeffs;
+  double shift;
+  double scale;
+} sped_poly;
+
+/*
+ * Table 2 transforms reversed by eq. reveig, as monomial coefficients of M.
+ *  SPED_T_PLAIN       identity transform: M = lambda_bound I - L (degree 1)
+ *  SPED_T_LIMIT       limit approximation of -exp(-L), lambda* = 0:
+ *                     M = (I - L/l)^l, c_i = C(l, i) (-1/l)^i
+ *  SPED_T_TAYLOR_EXP  Taylor series of -exp(-L), lambda* = 0: c_i = (-1)^i / i!
+ *  SPED_T_TAYLOR_LOG  Taylor series of log(L + eps I) in y = L - (1 - eps) I,
+ *                     lambda* = f(lambda_bound): c_0 = f(lambda_bound),
+ *                     c_i = (-1)^i / i; shift = 1 - eps, scale = 1
+ * (Sec. 4.1 requires f increasing where the wanted eigenvalues lie; Table 2
+ * takes l odd.)  coeffs HOST [degree+1]; shift, scale HOST.
+ */
+typedef enum { SPED_T_PLAIN = 0, SPED_T_LIMIT = 1, SPED_T_TAYLOR_EXP = 2, SPED_T_TAYLOR_LOG = 3 } sped_transform;
+sped_status sped_transform_coeffs(int32_t transform, int32_t degree, double lambda_bound, double eps,
+                                  double *coeffs, double *shift, double *scale);
+
+/* sped_poly_monomial -- the coefficients of p in powers of L itself
+ * (binomial expansion of the shift and scale, or of the limit product);
+ * out HOST [degree+1]. */
+sped_status sped_poly_monomial(const sped_poly *p, double *out);
+
+/*
+ * sped_apply_poly -- Y = M X for the polynomial p (Sec. 4.2): `degree` fused
+ * sparse-times-block steps, each U' = a (L U) + b U + g X.
+ *  X  DEVICE n x k (ldx), dtype xdt in {F32, BF16}
+ *  Y  DEVICE n x k (ldy), dtype ydt in {F32, BF16}; must not overlap X
+ *  intermediate blocks are F32 and live in the workspace.
+ */
+sped_status sped_apply_poly(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
+                            int64_t ldx, int32_t xdt, void *Y, int64_t ldy, int32_t ydt,
+                            void *ws, size_t *ws_bytes, sped_stream_t stream);
+
+/*
+ * sped_apply_poly_stochastic -- unbiased random-walk estimate of
+ * Y = sum_{i=0..degree} coeffs[i] L^i X (Sec. 4.3: eq. walk_summand, Table 1,
+ * the edge-incidence graph with self-loops, rejection sampling, prefix reuse).
+ * coeffs HOST [degree+1] are monomial coefficients in L itself.
+ *  sampler 0 (importance, row-owned): `walks` walks start at every row; the
+ *    first edge is uniform over the row's edges, each next edge uniform over
+ *    the deg_H = d_a + d_b - 1 edges incident to the current edge (d_a of them
+ *    at its first endpoint, including itself, then the others at the second);
+ *    prefix i adds coeffs[i] * omega_i * (x_{e_i}^T X) with
+ *    omega_i = alpha_c (x_{e_1})_r / q(c); the row's sum is divided by `walks`
+ *    and coeffs[0] X added.  Deterministic (no atomics).
+ *  sampler 1 (rejection, the paper's literal sampler): `walks` trials, first
+ *    edge uniform over all edges, prefix i accepted with probability
+ *    prod_{t<i} deg_H(e_t) / (2 deg* - 1); accepted prefixes add
+ *    |E| (2 deg* - 1)^{i-1} / walks * coeffs[i] alpha_c x_{e_1} (x_{e_i}^T X)
+ *    to both endpoints of e_1 (float atomics: summation order varies).
+ *    Requires ydt = F32.  accept_counts (DEVICE int64 [degree], or NULL) gets
+ *    the number of accepted trials per prefix length (overwritten).
+ * Random numbers: Philox4x32-10 with key (seed mod 2^32, seed >> 32) and
+ * counter (c0, c1, counter, (step << 8) | j); importance: c0 = row,
+ * c1 = walk; rejection: c0 = trial mod 2^32, c1 = (trial >> 32) | 2^31.  Step 0
+ * draws e_1, step t draws e_{t+1}; the rejection sampler's accept uniform for
+ * prefix i uses step degree + i, words 0 and 1: (w0 2^21 + (w1 >> 11)) 2^-53.
+ * Bounded draws use Lemire's multiply-shift with rejection, consuming the 4
+ * words of j = 0, 1, ... in order.  counter < 2^32, degree <= 255,
+ * walks >= 1 (sampler 1: walks < 2^63).
+ */
+sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, int32_t degree,
+                                       int64_t k, const void *X, int64_t ldx, int32_t xdt,
+                                       void *Y, int64_t ldy, int32_t ydt, int32_t sampler,
+                                       int64_t walks, uint64_t seed, uint64_t counter,
+                                       int64_t *accept_counts, void *ws, size_t *ws_bytes,
+                                       sped_stream_t stream);
+
+/*
+ * sped_poly_backward -- coefficient gradient of Y = sum_j theta_j Lt^j X
+ * (learnable dilation coefficients, the meta-learning direction of Sec. 6):
+ * dtheta[j] = <dY, Lt^j X>_F for j = 0..degree, with Lt = (L - shift I)/scale.
+ * The powers Lt^j X are recomputed step by step and never stored; each step
+ * fuses the inner product into the sparse product.  The X gradient
+ * p(L) dY is sped_apply_poly on dY (L is symmetric).
+ *  X, dY   DEVICE F32 n x k (ldx, lddy)
+ *  dtheta  DEVICE double [degree+1] (overwritten)
+ */
+sped_status sped_poly_backward(const sped_csr *L, int32_t degree, double shift, double scale,
+                               int64_t k, const float *X, int64_t ldx, const float *dY,
+                               int64_t lddy, double *dtheta, void *ws, size_t *ws_bytes,
+                               sped_stream_t stream);
+
+/*
+ * sped_gram -- G = A^T B in float64 (the inner products behind the projector
+ * V V^dagger of the subspace-error metric, Sec. 5.2, and the orthonormalisation
+ * of a block solver).  A DEVICE n x ka (lda), B DEVICE n x kb (ldb), both of
+ * dtype dt in {F32, BF16}; G DEVICE double ka x kb row-major (overwritten).
+ * Products are upconverted to float64 and accumulated with float64 matrix-core
+ * instructions in a fixed order (bitwise reproducible).  ka, kb <= 128.
+ */
+sped_status sped_gram(int64_t n, int64_t ka, int64_t kb, const void *A, int64_t lda,
+                      const void *B, int64_t ldb, int32_t dt, double *G, void *ws,
+                      size_t *ws_bytes, sped_stream_t stream);
+
+/*
+ * sped_orthonormalize -- in place V <- V R^{-1} with R the Cholesky factor of
+ * V^T V (Cholesky QR), repeated `passes` times (2 = CholQR2).  If a pivot
+ * breaks down, the Gram matrix is shifted by a multiple of its trace and the
+ * factorisation retried.  V DEVICE n x k (ldv), dtype F32; k <= 96.
+ * R_out DEVICE double k x k or NULL: R of the last pass (upper triangular).
+ */
+sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_t ldv, int32_t dt,
+                                int32_t passes, double *R_out, void *ws, size_t *ws_bytes,
+                                sped_stream_t stream);
+
+/*
+ * sped_rayleigh_ritz -- Ritz pairs of L on span(Q) for orthonormal Q
+ * (the eigenvector estimate of an iterative solver, Sec. 3 and Sec. 5):
+ * Z = L Q, H = Q^T Z (float64), H = S Theta S^T with Theta ascending,
+ * Q <- Q S, and residuals resid[i] = ||L q_i - theta_i q_i||_2.
+ *  Q DEVICE F32 n x k (ldq), updated in place; k <= 96
+ *  theta, resid DEVICE double [k]
+ */
+sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ldq, int32_t dt,
+                               double *theta, double *resid, void *ws, size_t *ws_bytes,
+                               sped_stream_t stream);
+
+/*
+ * sped_bottomk_solve -- bottom-k eigenvectors of L (Sec. 1 and 3): block
+ * subspace iteration (or block Oja with step eta) on the reversed operator
+ * M = p(L) (eq. reveig; p = NULL means the identity transform reversed,
+ * M = lambda_bound I - L), Cholesky-QR2 after every application, and a
+ * Rayleigh-Ritz step on L every check_every iterations.  The block carries
+ * k + guard columns; the stopping test is
+ *     max_{i<k} ||L q_i - theta_i q_i|| / (theta_{k} - theta_{k-1}) <= tol
+ * (a Davis-Kahan bound on the subspace angle with the gap estimated from the
+ * first guard Ritz value; guard must be >= 1).
+ *  V0      DEVICE F32 n x (k+guard) (ldv0): start block
+ *  V_out   DEVICE F32 n x k (ldvo): Ritz vectors, ascending
+ *  evals   HOST double [k]: Ritz values of L, ascending
+ *  resid   HOST double [k] or NULL: final residual norms
+ *  o, st   HOST options / statistics
+ * Synchronous.  Returns SPED_E_NOT_CONVERGED (with outputs and stats filled)
+ * when max_iters is reached first.
+ */
+typedef struct {
+  int32_t solver;          /* 0 = subspace iteration (eta = inf), 1 = block Oja */
+  double eta;              /* Oja step: iterate on M + I/eta */
+  double tol;              /* stopping bound */
+  int32_t max_iters;
+  int32_t check_every;     /* Rayleigh-Ritz cadence, >= 1 */
+  int32_t guard;           /* extra columns, >= 1 */
+  int32_t orth_passes;     /* Cholesky-QR passes per iteration (1 or 2) */
+  int32_t stochastic_iters;/* first iterations use the importance-sampled estimate */
+  int64_t walks_per_row;   /* walks per row for those iterations */
+  uint64_t seed;           /* Philox key; iteration t uses counter t */
+} sped_solve_opts;
+
+typedef struct {
+  int32_t iters;
+  int64_t spmm_count;      /* sparse products applied (chain steps + Rayleigh-Ritz) */
+  double seconds;          /* wall time inside the call */
+  double max_residual;
+  double gap_estimate;
+  double bound;            /* the stopping quantity at exit */
+  int32_t converged;
+  int32_t cholqr_shifts;   /* breakdowns repaired by the shift */
+} sped_solve_stats;
+
+sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p, int64_t k, const void *V0,
+                               int64_t ldv0, void *V_out, int64_t ldvo, int32_t vdt,
+                               double *evals, double *resid, const sped_solve_opts *o,
+                               sped_solve_stats *st, void *ws, size_t *ws_bytes,
+                               sped_stream_t stream);
+
+/*
+ * sped_cluster_embed -- hard clustering of the spectral embedding with k-means
+ * (Sec. 1: the bottom-k eigenvectors embed each node; k-means on them gives
+ * the clusters; Sec. 2.1 uses k = 2 on the Fiedler vector).
+ *  V              DEVICE n x k (ldv), dtype vdt in {F32, BF16}
+ *  row_normalize  nonzero: rows scaled to unit length first
+ *  init           DEVICE double n_clusters x k or NULL.  NULL: k-means++
+ *                 seeding with Philox draws keyed by `seed` (pick c uses
+ *                 counter (c, 0, 0, 0) words 0 and 1 as a 53-bit uniform).
+ *  labels         DEVICE int32 [n]: nearest centre (ties: lowest index)
+ *  centroids      DEVICE double n_clusters x k
+ *  inertia, iters HOST or NULL: final sum of squared distances, Lloyd rounds
+ * Lloyd rounds run until no label changes or max_iters.  Distances and
+ * centroid sums are float64.  Synchronous.  n_clusters <= 256, k <= 128.
+ */
+sped_status sped_cluster_embed(const void *V, int64_t n, int64_t k, int64_t ldv, int32_t vdt,
+                               int32_t n_clusters, int32_t row_normalize, uint64_t seed,
+                               int32_t max_iters, const double *init, int32_t *labels,
+                               double *centroids, double *inertia, int32_t *iters, void *ws,
+                               size_t *ws_bytes, sped_stream_t stream);
+
+/*
+ * sped_stream_copy -- dst <- src, `bytes` bytes (multiple of 16, 16-byte
+ * aligned DEVICE pointers): a plain streaming copy used to calibrate the
+ * chip's achievable HBM bandwidth and its memory counters.
+ */
+sped_status sped_stream_copy(const void *src, void *dst, size_t bytes, sped_stream_t stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *sped_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t sped_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPED_H */

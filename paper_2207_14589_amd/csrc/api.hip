@@ -1,0 +1,162 @@
+// Error state, argument validation helpers and small utility entry points.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace sped {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+sped_status fail(sped_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int pick_vec(int64_t k, std::initializer_list<int64_t> lds, std::initializer_list<const void *> ptrs,
+             std::initializer_list<int> elem_sizes) {
+  for (int vec : {4, 2}) {
+    bool ok = (k % vec) == 0;
+    for (int64_t ld : lds) ok = ok && (ld % vec) == 0;
+    auto es = elem_sizes.begin();
+    for (const void *p : ptrs) {
+      int e = es != elem_sizes.end() ? *es++ : 4;
+      if (p) ok = ok && (reinterpret_cast<uintptr_t>(p) % (uintptr_t(vec) * e)) == 0;
+    }
+    if (ok) return vec;
+  }
+  return 1;
+}
+
+sped_status validate_csr(const sped_csr *L) {
+  if (!L) return fail(SPED_E_INVALID, "csr is NULL");
+  if (L->n < 0 || L->n >= (int64_t(1) << 31)) return fail(SPED_E_INVALID, "csr n out of range");
+  if (L->nnz < 0) return fail(SPED_E_INVALID, "csr nnz negative");
+  if (L->n > 0 && (!L->rowptr || !L->diag || !L->scale))
+    return fail(SPED_E_INVALID, "csr rowptr/diag/scale NULL");
+  if (L->nnz > 0 && (!L->col || !L->val)) return fail(SPED_E_INVALID, "csr col/val NULL");
+  if (L->n_medium < 0 || L->n_heavy < 0 || L->n_medium + L->n_heavy > L->n)
+    return fail(SPED_E_INVALID, "csr bin counts out of range");
+  if (L->n_medium + L->n_heavy > 0 && !L->bins) return fail(SPED_E_INVALID, "csr bins NULL");
+  if (L->kind != SPED_LAP_COMBINATORIAL && L->kind != SPED_LAP_SYM_NORMALIZED)
+    return fail(SPED_E_INVALID, "csr kind");
+  return SPED_OK;
+}
+
+std::vector<double> monomial_in_L(const sped_poly &p) {
+  const int ell = p.degree;
+  std::vector<double> c(ell + 1, 0.0), out(ell + 1, 0.0);
+  if (p.kind == SPED_POLY_LIMIT) {
+    double binom = 1.0;
+    for (int i = 0; i <= ell; ++i) {
+      out[i] = binom * std::pow(-1.0 / ell, i);
+      binom = binom * (ell - i) / (i + 1);
+    }
+    return out;
+  }
+  for (int i = 0; i <= ell; ++i) c[i] = p.coeffs[i];
+  // ((L - a)/s)^i = s^-i sum_j C(i, j) L^j (-a)^(i-j)
+  for (int i = 0; i <= ell; ++i) {
+    double binom = 1.0;
+    for (int j = 0; j <= i; ++j) {
+      out[j] += c[i] * binom * std::pow(-p.shift, i - j) / std::pow(p.scale, i);
+      binom = binom * (i - j) / (j + 1);
+    }
+  }
+  return out;
+}
+
+
+namespace {
+__global__ void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n16) {
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+}  // namespace
+
+}  // namespace sped
+
+using namespace sped;
+
+extern "C" const char *sped_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int32_t sped_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+extern "C" sped_status sped_stream_copy(const void *src, void *dst, size_t bytes, sped_stream_t stream) {
+  clear_error();
+  if (bytes == 0) return SPED_OK;
+  if (!src || !dst) return fail(SPED_E_INVALID, "NULL pointer");
+  if ((bytes & 15) || (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+    return fail(SPED_E_INVALID, "copy needs 16-byte multiples and alignment");
+  size_t n16 = bytes / 16;
+  size_t blocks = (n16 + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;
+  hipLaunchKernelGGL(copy_kernel, dim3(unsigned(blocks)), dim3(256), 0, as_stream(stream),
+                     static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+extern "C" sped_status sped_transform_coeffs(int32_t transform, int32_t degree, double lambda_bound, double eps,
+                                             double *coeffs, double *shift, double *scale) {
+  clear_error();
+  if (!coeffs || !shift || !scale) return fail(SPED_E_INVALID, "NULL output");
+  if (!(std::isfinite(lambda_bound) && lambda_bound > 0.0)) return fail(SPED_E_INVALID, "lambda_bound");
+  *shift = 0.0;
+  *scale = 1.0;
+  switch (transform) {
+    case SPED_T_PLAIN:
+      if (degree != 1) return fail(SPED_E_INVALID, "the plain operator has degree 1");
+      coeffs[0] = lambda_bound;
+      coeffs[1] = -1.0;
+      return SPED_OK;
+    case SPED_T_LIMIT: {
+      if (degree < 1 || degree > 1024) return fail(SPED_E_INVALID, "degree");
+      sped_poly p{SPED_POLY_LIMIT, degree, nullptr, 0.0, 1.0};
+      std::vector<double> c = monomial_in_L(p);
+      for (int i = 0; i <= degree; ++i) coeffs[i] = c[i];
+      return SPED_OK;
+    }
+    case SPED_T_TAYLOR_EXP: {
+      if (degree < 1 || degree > 1024) return fail(SPED_E_INVALID, "degree");
+      double f = 1.0;  // (-1)^i / i!
+      for (int i = 0; i <= degree; ++i) {
+        coeffs[i] = f;
+        f = -f / double(i + 1);
+      }
+      return SPED_OK;
+    }
+    case SPED_T_TAYLOR_LOG: {
+      if (degree < 1 || degree > 1024) return fail(SPED_E_INVALID, "degree");
+      if (!(eps > 0.0 && eps < 1.0)) return fail(SPED_E_INVALID, "eps outside (0, 1)");
+      const double y = lambda_bound - (1.0 - eps);
+      double ftop = 0.0, yp = 1.0;
+      for (int i = 1; i <= degree; ++i) {
+        yp *= y;
+        ftop += ((i & 1) ? 1.0 : -1.0) * yp / double(i);
+      }
+      coeffs[0] = ftop;
+      for (int i = 1; i <= degree; ++i) coeffs[i] = ((i & 1) ? -1.0 : 1.0) / double(i);
+      *shift = 1.0 - eps;
+      return SPED_OK;
+    }
+    default:
+      return fail(SPED_E_INVALID, "transform");
+  }
+}
+
+extern "C" sped_status sped_poly_monomial(const sped_poly *p, double *out) {
+  clear_error();
+  SPED_TRY(validate_poly(p));
+  if (!out) return fail(SPED_E_INVALID, "out NULL");
+  std::vector<double> c = monomial_in_L(*p);
+  for (int i = 0; i <= p->degree; ++i) out[i] = c[i];
+  return SPED_OK;
+}

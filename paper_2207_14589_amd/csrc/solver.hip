@@ -1,0 +1,292 @@
+// Bottom-k block eigensolver on the dilated, reversed operator (Sec. 3,
+// eq. reveig; Sec. 4; Sec. 5 solvers):
+//   W = M Q                 M = p(L), or lambda_bound I - L for the plain solver
+//   Q = W R^{-1}            Cholesky QR (twice by default), float64 Gram
+//   every c iterations:     Rayleigh-Ritz on L: Z = L Q, H = Q^T Z = S Theta S^T,
+//                           Q <- Q S, residuals ||Z s_i - theta_i q_i||
+// Block Oja with step eta iterates on M + I/eta (the same subspace update).
+// The host loop only reads 2(k + guard) doubles and 3 flags per check.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace sped {
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void copy_block_kernel(int64_t n, int k, const TI *__restrict__ in, int64_t ldi,
+                                                            TO *__restrict__ out, int64_t ldo) {
+  const int64_t total = n * k;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    int64_t r = i / k, c = i - r * k;
+    out[r * ldo + c] = from_f32<TO>(to_f32<TI>(in[r * ldi + c]));
+  }
+}
+
+__global__ void zero_int_kernel(int *p, int count) {
+  if (int(threadIdx.x) < count) p[threadIdx.x] = 0;
+}
+
+sped_status copy_block(int64_t n, int k, const void *in, int64_t ldi, int ti, void *out, int64_t ldo, int to,
+                       hipStream_t s) {
+  if (n == 0 || k == 0) return SPED_OK;
+  int64_t blocks = (n * k + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+#define SPED_COPY(TI_, TO_)                                                                          \
+  hipLaunchKernelGGL((copy_block_kernel<TI_, TO_>), dim3(unsigned(blocks)), dim3(kBlock), 0, s, n, k, \
+                     static_cast<const TI_ *>(in), ldi, static_cast<TO_ *>(out), ldo)
+  if (ti == SPED_F32 && to == SPED_F32) SPED_COPY(float, float);
+  else if (ti == SPED_F32 && to == SPED_BF16) SPED_COPY(float, bf16_t);
+  else if (ti == SPED_BF16 && to == SPED_F32) SPED_COPY(bf16_t, float);
+  else if (ti == SPED_BF16 && to == SPED_BF16) SPED_COPY(bf16_t, bf16_t);
+  else return fail(SPED_E_UNSUPPORTED, "copy dtype");
+#undef SPED_COPY
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+struct OrthWs {
+  double *G, *T, *partials;
+  int *flags;
+};
+
+// Q <- W R^{-1} (out of place when W != Q), then `passes - 1` more in place.
+sped_status cholqr(int64_t n, int k, const float *W, float *Q, int64_t ld, int passes, double *R_out,
+                   const OrthWs &w, hipStream_t s) {
+  const float *src = W;
+  for (int pass = 0; pass < passes; ++pass) {
+    SPED_TRY(launch_gram(n, k, k, src, ld, src, ld, SPED_F32, w.G, w.partials, s));
+    SPED_TRY(launch_chol_inv(k, w.G, w.T, pass == passes - 1 ? R_out : nullptr, w.flags, s));
+    SPED_TRY(launch_tsmm(n, k, k, src, ld, SPED_F32, w.T, Q, ld, SPED_F32, s));
+    src = Q;
+  }
+  return SPED_OK;
+}
+
+struct RRWs {
+  float *Z, *ZS, *Qtmp;
+  double *H, *S, *theta, *resid, *partials, *rpartials;
+  int *flags;
+};
+
+// Rayleigh-Ritz of L on span(Q); Q is replaced by the Ritz vectors (via Qtmp).
+sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, float *&Q, int64_t ld, const RRWs &w,
+                          hipStream_t s) {
+  StepArgs a{};
+  a.U = Q; a.ldu = ld; a.tu = SPED_F32;
+  a.V = nullptr; a.ldv = ld; a.tv = SPED_F32;
+  a.O = w.Z; a.ldo = ld; a.to = SPED_F32;
+  a.a = 1.f; a.b = 0.f; a.g = 0.f;
+  SPED_TRY(launch_spmm_step(L, k, a, s));
+  SPED_TRY(launch_gram(n, k, k, Q, ld, w.Z, ld, SPED_F32, w.H, w.partials, s));
+  SPED_TRY(launch_jacobi(k, w.H, w.theta, w.S, w.flags, s));
+  SPED_TRY(launch_tsmm(n, k, k, Q, ld, SPED_F32, w.S, w.Qtmp, ld, SPED_F32, s));
+  SPED_TRY(launch_tsmm(n, k, k, w.Z, ld, SPED_F32, w.S, w.ZS, ld, SPED_F32, s));
+  SPED_TRY(launch_resid(n, k, w.ZS, ld, w.Qtmp, ld, w.theta, w.resid, w.rpartials, s));
+  return SPED_OK;
+}
+
+}  // namespace
+}  // namespace sped
+
+using namespace sped;
+
+extern "C" sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_t ldv, int32_t dt, int32_t passes,
+                                           double *R_out, void *ws, size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  if (n < 0 || k < 1 || k > dense_max_k()) return fail(SPED_E_INVALID, "orthonormalize shape (k in [1, 96])");
+  if (n < k) return fail(SPED_E_INVALID, "orthonormalize needs n >= k");
+  if (ldv < k) return fail(SPED_E_INVALID, "ldv < k");
+  if (dt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "orthonormalize dtype must be F32");
+  if (passes < 1 || passes > 4) return fail(SPED_E_INVALID, "passes outside [1, 4]");
+  if (!V) return fail(SPED_E_INVALID, "V NULL");
+  Carver c(ws);
+  OrthWs w;
+  w.G = c.take<double>(size_t(k) * k);
+  w.T = c.take<double>(size_t(k) * k);
+  w.partials = c.take<double>(gram_ws_doubles(n, k, k));
+  w.flags = c.take<int>(4);
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
+  SPED_CHECK_HIP(hipGetLastError());
+  float *Vf = static_cast<float *>(V);
+  SPED_TRY(cholqr(n, int(k), Vf, Vf, ldv, passes, R_out, w, s));
+  int flags[4];
+  SPED_CHECK_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  if (flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
+  return SPED_OK;
+}
+
+extern "C" sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ldq, int32_t dt,
+                                          double *theta, double *resid, void *ws, size_t *ws_bytes,
+                                          sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (k < 1 || k > dense_max_k()) return fail(SPED_E_INVALID, "k outside [1, 96]");
+  if (ldq < k) return fail(SPED_E_INVALID, "ldq < k");
+  if (dt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "rayleigh_ritz dtype must be F32");
+  if (!Q || !theta || !resid) return fail(SPED_E_INVALID, "NULL pointer");
+  const int64_t n = L->n;
+  Carver c(ws);
+  RRWs w;
+  w.Z = c.take<float>(size_t(n) * ldq);
+  w.ZS = c.take<float>(size_t(n) * ldq);
+  w.Qtmp = c.take<float>(size_t(n) * ldq);
+  w.H = c.take<double>(size_t(k) * k);
+  w.S = c.take<double>(size_t(k) * k);
+  w.theta = theta;
+  w.resid = resid;
+  w.partials = c.take<double>(gram_ws_doubles(n, k, k));
+  w.rpartials = c.take<double>(resid_ws_doubles(k));
+  w.flags = c.take<int>(4);
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
+  SPED_CHECK_HIP(hipGetLastError());
+  float *Qf = static_cast<float *>(Q);
+  SPED_TRY(rayleigh_ritz(L, n, int(k), Qf, ldq, w, s));
+  SPED_TRY(copy_block(n, int(k), w.Qtmp, ldq, SPED_F32, Q, ldq, SPED_F32, s));
+  return SPED_OK;
+}
+
+extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p, int64_t k, const void *V0,
+                                          int64_t ldv0, void *V_out, int64_t ldvo, int32_t vdt, double *evals,
+                                          double *resid_out, const sped_solve_opts *o, sped_solve_stats *st,
+                                          void *ws, size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (!o) return fail(SPED_E_INVALID, "opts NULL");
+  if (p) SPED_TRY(validate_poly(p));
+  if (o->guard < 1) return fail(SPED_E_INVALID, "guard must be >= 1");
+  const int64_t kb = k + o->guard;
+  if (k < 1 || kb > dense_max_k()) return fail(SPED_E_INVALID, "k + guard outside [2, 96]");
+  const int64_t n = L->n;
+  if (n < kb) return fail(SPED_E_INVALID, "n < k + guard");
+  if (ldv0 < kb || ldvo < k) return fail(SPED_E_INVALID, "leading dimension");
+  if (vdt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "solver block dtype must be F32");
+  if (!V0 || !V_out || !evals) return fail(SPED_E_INVALID, "NULL pointer");
+  if (o->max_iters < 1 || o->check_every < 1) return fail(SPED_E_INVALID, "max_iters/check_every");
+  if (o->orth_passes < 1 || o->orth_passes > 4) return fail(SPED_E_INVALID, "orth_passes");
+  if (o->solver != 0 && o->solver != 1) return fail(SPED_E_INVALID, "solver");
+  if (o->solver == 1 && !(o->eta > 0.0 && std::isfinite(o->eta))) return fail(SPED_E_INVALID, "eta");
+  if (!(o->tol >= 0.0)) return fail(SPED_E_INVALID, "tol");
+  if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
+  if (o->stochastic_iters > 0 && (o->walks_per_row < 1 || !L->rev))
+    return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and csr rev");
+
+  // the operator actually iterated on
+  std::vector<double> plain_c = {L->lambda_bound, -1.0};
+  sped_poly M{SPED_POLY_MONOMIAL, 1, plain_c.data(), 0.0, 1.0};
+  if (p) M = *p;
+  std::vector<double> oja_c;
+  if (o->solver == 1) {
+    oja_c = (M.kind == SPED_POLY_LIMIT) ? monomial_in_L(M) : std::vector<double>(M.coeffs, M.coeffs + M.degree + 1);
+    if (M.kind == SPED_POLY_LIMIT) {
+      M.shift = 0.0;
+      M.scale = 1.0;
+    }
+    oja_c[0] += 1.0 / o->eta;
+    M.kind = SPED_POLY_MONOMIAL;
+    M.coeffs = oja_c.data();
+  }
+  std::vector<double> walk_c;
+  if (o->stochastic_iters > 0) {
+    walk_c = monomial_in_L(M);
+    if (M.degree > 255) return fail(SPED_E_UNSUPPORTED, "stochastic iterations need degree <= 255");
+  }
+
+  Carver c(ws);
+  float *Q = c.take<float>(size_t(n) * kb);
+  float *W = c.take<float>(size_t(n) * kb);
+  float *bufA = c.take<float>(size_t(n) * kb);
+  float *bufB = c.take<float>(size_t(n) * kb);
+  OrthWs ow;
+  ow.G = c.take<double>(size_t(kb) * kb);
+  ow.T = c.take<double>(size_t(kb) * kb);
+  ow.partials = c.take<double>(gram_ws_doubles(n, kb, kb));
+  RRWs rw;
+  rw.H = c.take<double>(size_t(kb) * kb);
+  rw.S = c.take<double>(size_t(kb) * kb);
+  rw.theta = c.take<double>(size_t(kb));
+  rw.resid = c.take<double>(size_t(kb));
+  rw.rpartials = c.take<double>(resid_ws_doubles(kb));
+  rw.partials = ow.partials;
+  int *flags = c.take<int>(4);
+  ow.flags = rw.flags = flags;
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+
+  hipStream_t s = as_stream(stream);
+  auto t_start = std::chrono::steady_clock::now();
+  sped_solve_stats stats{};
+  hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, flags, 4);
+  SPED_CHECK_HIP(hipGetLastError());
+  SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, W, kb, SPED_F32, s));
+  SPED_TRY(cholqr(n, int(kb), W, Q, kb, o->orth_passes, nullptr, ow, s));
+
+  std::vector<double> h_theta(kb), h_resid(kb);
+  int h_flags[4] = {0, 0, 0, 0};
+  sped_status result = SPED_E_NOT_CONVERGED;
+  int t = 0;
+  for (t = 1; t <= o->max_iters; ++t) {
+    if (t <= o->stochastic_iters) {
+      SPED_TRY(walk_estimate_impl(L, walk_c.data(), M.degree, kb, Q, kb, SPED_F32, W, kb, SPED_F32, 0,
+                                  o->walks_per_row, o->seed, uint64_t(t), nullptr, s));
+    } else {
+      SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, SPED_F32, W, kb, SPED_F32, bufA, bufB, s, &stats.spmm_count));
+    }
+    SPED_TRY(cholqr(n, int(kb), W, Q, kb, o->orth_passes, nullptr, ow, s));
+    if (t % o->check_every == 0 || t == o->max_iters) {
+      rw.Z = bufA;
+      rw.ZS = bufB;
+      rw.Qtmp = W;
+      SPED_TRY(rayleigh_ritz(L, n, int(kb), Q, kb, rw, s));
+      std::swap(Q, W);  // Ritz vectors now in Q
+      stats.spmm_count += 1;
+      SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+      SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+      SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+      SPED_CHECK_HIP(hipStreamSynchronize(s));
+      if (h_flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
+      double rmax = 0.0;
+      bool finite = true;
+      for (int i = 0; i < k; ++i) {
+        rmax = std::max(rmax, h_resid[i]);
+        finite = finite && std::isfinite(h_resid[i]) && std::isfinite(h_theta[i]);
+      }
+      if (!finite) return fail(SPED_E_NUMERIC, "non-finite Ritz value or residual");
+      double gap = h_theta[k] - h_theta[k - 1];
+      stats.gap_estimate = gap;
+      stats.max_residual = rmax;
+      stats.bound = gap > 0 ? rmax / gap : INFINITY;
+      if (stats.bound <= o->tol) {
+        result = SPED_OK;
+        break;
+      }
+    }
+  }
+  stats.iters = t > o->max_iters ? o->max_iters : t;
+  stats.converged = result == SPED_OK;
+  SPED_TRY(copy_block(n, int(k), Q, kb, SPED_F32, V_out, ldvo, vdt, s));
+  SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  stats.cholqr_shifts = h_flags[0];
+  stats.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  for (int i = 0; i < k; ++i) evals[i] = h_theta[i];
+  if (resid_out)
+    for (int i = 0; i < k; ++i) resid_out[i] = h_resid[i];
+  if (st) *st = stats;
+  if (result != SPED_OK) return fail(SPED_E_NOT_CONVERGED, "iteration cap reached before the tolerance");
+  return SPED_OK;
+}

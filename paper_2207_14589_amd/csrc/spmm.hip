@@ -1,0 +1,350 @@
+// Fused sparse-Laplacian x block step (the inner operation of p(L)V, Sec. 4.2):
+//     O = a (L U) + b U + g V,   L U = diag .* U - S U
+// over the split CSR of sped.h.  One step of Horner's rule (a = 1/scale,
+// b = -shift/scale, g = c_i), one factor of the limit product (a = -1/l, b = 1,
+// g = 0) or a plain product (a = 1, b = g = 0) is one launch set.  Optionally
+// the inner product <O, W> is accumulated in float64 (coefficient gradients).
+//
+// Rows are binned by their number of stored entries d:
+//   light   d <= SPED_LIGHT_MAX : a group of G lanes per row, 256/G rows per block
+//   medium  d <= SPED_MEDIUM_MAX: one 64-lane wavefront per row, 64/G lane groups
+//           split the entries, partial sums meet by cross-lane xor shuffles
+//   heavy   d >  SPED_MEDIUM_MAX: one 256-thread block per row, LDS reduction
+// Each lane owns VEC consecutive columns; G = next_pow2(k / VEC) lanes cover
+// a row of the block (columns beyond 64 VEC are tiled over blockIdx.y).  The
+// G lanes of a group load G consecutive (col, val) pairs with one coalesced
+// access and broadcast them by shuffle, then gather 4 neighbour rows at a time
+// so several row gathers are in flight per lane.
+#include <type_traits>
+
+#include "common.h"
+
+namespace sped {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Coef {
+  float a, b, g;
+};
+
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+struct Step {
+  // Accumulate sum_p S_rp U[col_p, c0 .. c0+VEC) over entries [beg, end),
+  // handled in chunks of G by the lanes of one group (lane `lig`).  Chunks
+  // start at beg + first*G and advance by stride*G.
+  __device__ static void gather(const int32_t *__restrict__ col, const float *__restrict__ val,
+                                const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end,
+                                int G, int lig, int first, int stride, int c0, bool col_ok,
+                                float (&acc)[VEC]) {
+    for (int64_t p = beg + int64_t(first) * G; p < end; p += int64_t(stride) * G) {
+      int cnt = int(min<int64_t>(G, end - p));
+      int32_t myc = 0;
+      float myv = 0.f;
+      if (lig < cnt) {
+        myc = col[p + lig];
+        myv = val[p + lig];
+      }
+      int t = 0;
+      for (; t + 4 <= cnt; t += 4) {
+        int32_t j0 = __shfl(myc, t, G), j1 = __shfl(myc, t + 1, G);
+        int32_t j2 = __shfl(myc, t + 2, G), j3 = __shfl(myc, t + 3, G);
+        float s0 = __shfl(myv, t, G), s1 = __shfl(myv, t + 1, G);
+        float s2 = __shfl(myv, t + 2, G), s3 = __shfl(myv, t + 3, G);
+        if (col_ok) {
+          float u0[VEC], u1[VEC], u2[VEC], u3[VEC];
+          VecIO<TU, VEC>::load(U + int64_t(j0) * ldu + c0, u0);
+          VecIO<TU, VEC>::load(U + int64_t(j1) * ldu + c0, u1);
+          VecIO<TU, VEC>::load(U + int64_t(j2) * ldu + c0, u2);
+          VecIO<TU, VEC>::load(U + int64_t(j3) * ldu + c0, u3);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            acc[v] = fmaf(s0, u0[v], acc[v]);
+            acc[v] = fmaf(s1, u1[v], acc[v]);
+            acc[v] = fmaf(s2, u2[v], acc[v]);
+            acc[v] = fmaf(s3, u3[v], acc[v]);
+          }
+        }
+      }
+      for (; t < cnt; ++t) {
+        int32_t j = __shfl(myc, t, G);
+        float s = __shfl(myv, t, G);
+        if (col_ok) {
+          float u[VEC];
+          VecIO<TU, VEC>::load(U + int64_t(j) * ldu + c0, u);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(s, u[v], acc[v]);
+        }
+      }
+    }
+  }
+
+  // O[row] = a (diag U[row] - acc) + b U[row] + g V[row]; returns <O[row], W[row]>
+  // over this lane's columns when DOT.
+  __device__ static double epilogue(int64_t row, int c0, const float *__restrict__ diag,
+                                    const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V,
+                                    int64_t ldv, TO *__restrict__ O, int64_t ldo, Coef cf,
+                                    const float *__restrict__ W, int64_t ldw, const float (&acc)[VEC]) {
+    float u[VEC], o[VEC];
+    VecIO<TU, VEC>::load(U + row * ldu + c0, u);
+    const float dg = diag[row];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] = cf.a * (dg * u[v] - acc[v]) + cf.b * u[v];
+    if (cf.g != 0.f) {
+      float x[VEC];
+      VecIO<TV, VEC>::load(V + row * ldv + c0, x);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) o[v] = fmaf(cf.g, x[v], o[v]);
+    }
+    VecIO<TO, VEC>::store(O + row * ldo + c0, o);
+    double d = 0.0;
+    if (DOT) {
+      float w[VEC];
+      VecIO<float, VEC>::load(W + row * ldw + c0, w);
+      // the stored (rounded) value is what the next step consumes
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) d += double(to_f32<TO>(from_f32<TO>(o[v]))) * double(w[v]);
+    }
+    return d;
+  }
+};
+
+__device__ inline double block_sum_double(double v, double *lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) t += lds[w];
+  return t;
+}
+
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+__global__ __launch_bounds__(kBlock) void spmm_light(
+    int64_t n, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
+    const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
+    int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
+  using S = Step<TU, TV, TO, VEC, DOT>;
+  const int lig = threadIdx.x & (G - 1);
+  const int grp = threadIdx.x >> lgG;
+  const int64_t row = int64_t(blockIdx.x) * (kBlock >> lgG) + grp;
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  double dsum = 0.0;
+  if (row < n) {
+    const int64_t beg = rowptr[row], end = rowptr[row + 1];
+    if (end - beg <= SPED_LIGHT_MAX) {
+      float acc[VEC];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+      S::gather(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
+      if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+    }
+  }
+  if (DOT) {
+    __shared__ double red[kBlock / 64];
+    double t = block_sum_double(dsum, red);
+    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+__global__ __launch_bounds__(kBlock) void spmm_medium(
+    int64_t n_rows, const int32_t *__restrict__ rows, int k, int G, int lgG,
+    const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+    const float *__restrict__ val, const float *__restrict__ diag, const TU *__restrict__ U,
+    int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O, int64_t ldo, Coef cf,
+    const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
+  using S = Step<TU, TV, TO, VEC, DOT>;
+  const int lane = threadIdx.x & 63;
+  const int lig = lane & (G - 1);
+  const int sub = lane >> lgG;
+  const int nsub = 64 >> lgG;
+  const int64_t ri = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  double dsum = 0.0;
+  if (ri < n_rows) {
+    const int64_t row = rows[ri];
+    const int64_t beg = rowptr[row], end = rowptr[row + 1];
+    float acc[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+    S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+    for (int off = G; off < 64; off <<= 1)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+    if (sub == 0 && col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+  }
+  if (DOT) {
+    __shared__ double red[kBlock / 64];
+    double t = block_sum_double(dsum, red);
+    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+__global__ __launch_bounds__(kBlock) void spmm_heavy(
+    const int32_t *__restrict__ rows, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
+    const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
+    int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
+  using S = Step<TU, TV, TO, VEC, DOT>;
+  __shared__ float red[kBlock * VEC];
+  const int lig = threadIdx.x & (G - 1);
+  const int sub = threadIdx.x >> lgG;
+  const int nsub = kBlock >> lgG;
+  const int64_t row = rows[blockIdx.x];
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  const int64_t beg = rowptr[row], end = rowptr[row + 1];
+  float acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+  S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
+  __syncthreads();
+  double dsum = 0.0;
+  if (sub == 0) {
+    for (int s = 1; s < nsub; ++s)
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += red[(s * G + lig) * VEC + v];
+    if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+  }
+  if (DOT) {
+    __syncthreads();
+    __shared__ double dred[kBlock / 64];
+    double t = block_sum_double(dsum, dred);
+    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double *__restrict__ p,
+                                                                  int64_t count, double *out) {
+  __shared__ double red[kBlock];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += kBlock) s += p[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+struct Geometry {
+  int vec, G, lgG, ytiles;
+  int64_t light_blocks, medium_blocks, heavy_blocks;
+};
+
+Geometry geometry(const sped_csr *L, int64_t k, int vec) {
+  Geometry g;
+  g.vec = vec;
+  int lanes = int((k + vec - 1) / vec);
+  g.ytiles = (lanes + 63) / 64;
+  g.G = lanes >= 64 ? 64 : next_pow2(lanes);
+  g.lgG = ilog2(g.G);
+  g.light_blocks = (L->n + (kBlock >> g.lgG) - 1) / (kBlock >> g.lgG);
+  g.medium_blocks = (L->n_medium + 3) / 4;
+  g.heavy_blocks = L->n_heavy;
+  return g;
+}
+
+int64_t partial_count(const Geometry &g) {
+  return (g.light_blocks + g.medium_blocks + g.heavy_blocks) * g.ytiles;
+}
+
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const Geometry &g,
+                         hipStream_t s) {
+  Coef cf{a.a, a.b, a.g};
+  const TU *U = static_cast<const TU *>(a.U);
+  const TV *V = static_cast<const TV *>(a.V);
+  TO *O = static_cast<TO *>(a.O);
+  double *part = a.dot_partials;
+  if (g.light_blocks > 0) {
+    const dim3 grid = dim3(unsigned(g.light_blocks), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n, int(k),
+                       g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
+                       cf, a.dotw, a.lddw, part);
+    SPED_CHECK_HIP(hipGetLastError());
+    if (DOT) part += g.light_blocks * g.ytiles;
+  }
+  if (g.medium_blocks > 0) {
+    const dim3 grid = dim3(unsigned(g.medium_blocks), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_medium<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n_medium,
+                       L->bins, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu,
+                       V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part);
+    SPED_CHECK_HIP(hipGetLastError());
+    if (DOT) part += g.medium_blocks * g.ytiles;
+  }
+  if (g.heavy_blocks > 0) {
+    const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_heavy<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s,
+                       L->bins + L->n_medium, int(k), g.G, g.lgG, L->rowptr, L->col, L->val,
+                       L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  return SPED_OK;
+}
+
+template <int VEC, bool DOT>
+sped_status dispatch_types(const sped_csr *L, int64_t k, const StepArgs &a, const Geometry &g,
+                           hipStream_t s) {
+  const bool u32 = a.tu == SPED_F32, v32 = a.tv == SPED_F32, o32 = a.to == SPED_F32;
+#define SPED_CASE(TU_, TV_, TO_)                                                      \
+  if (u32 == std::is_same<TU_, float>::value && v32 == std::is_same<TV_, float>::value && \
+      o32 == std::is_same<TO_, float>::value)                                         \
+    return launch_typed<TU_, TV_, TO_, VEC, DOT>(L, k, a, g, s);
+  SPED_CASE(float, float, float)
+  SPED_CASE(float, bf16_t, float)
+  SPED_CASE(float, float, bf16_t)
+  SPED_CASE(float, bf16_t, bf16_t)
+  SPED_CASE(bf16_t, bf16_t, float)
+  SPED_CASE(bf16_t, bf16_t, bf16_t)
+  SPED_CASE(bf16_t, float, float)
+  SPED_CASE(bf16_t, float, bf16_t)
+#undef SPED_CASE
+  return fail(SPED_E_UNSUPPORTED, "spmm dtype combination");
+}
+
+}  // namespace
+
+int64_t spmm_partials(const sped_csr *L, int64_t k) {
+  return partial_count(geometry(L, k, 1));  // upper bound: vec = 1 gives the most blocks
+}
+
+sped_status launch_spmm_step(const sped_csr *L, int64_t k, const StepArgs &a, hipStream_t s,
+                             int64_t *partials_written) {
+  if (a.tu == SPED_F64 || a.tv == SPED_F64 || a.to == SPED_F64)
+    return fail(SPED_E_UNSUPPORTED, "float64 blocks are not supported by the sparse step");
+  const void *V = a.g != 0.f ? a.V : a.U;
+  int64_t ldv = a.g != 0.f ? a.ldv : a.ldu;
+  int vec = pick_vec(k, {a.ldu, ldv, a.ldo, a.dotw ? a.lddw : k}, {a.U, V, a.O, a.dotw},
+                     {int(dtype_size(a.tu)), int(dtype_size(a.g != 0.f ? a.tv : a.tu)),
+                      int(dtype_size(a.to)), 4});
+  StepArgs b = a;
+  if (a.g == 0.f) {
+    b.V = a.U;
+    b.ldv = a.ldu;
+    b.tv = a.tu;
+  }
+  Geometry g = geometry(L, k, vec);
+  const bool dot = a.dotw != nullptr;
+  if (partials_written) *partials_written = dot ? partial_count(g) : 0;
+  if (vec == 4) return dot ? dispatch_types<4, true>(L, k, b, g, s) : dispatch_types<4, false>(L, k, b, g, s);
+  if (vec == 2) return dot ? dispatch_types<2, true>(L, k, b, g, s) : dispatch_types<2, false>(L, k, b, g, s);
+  return dot ? dispatch_types<1, true>(L, k, b, g, s) : dispatch_types<1, false>(L, k, b, g, s);
+}
+
+sped_status launch_reduce_partials(const double *partials, int64_t count, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, partials, count, out);
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+}  // namespace sped

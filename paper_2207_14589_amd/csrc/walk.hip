@@ -1,0 +1,411 @@
+// Random-walk estimate of sum_i c_i L^i X (Sec. 4.3): the chains of
+// eq. walk_summand are walks on the edge-incidence graph H (self-loops
+// included); a walker's state is an edge of G, stored as its CSR position p in
+// row a (the endpoint the walk last stood on) with other endpoint b = col[p].
+//
+// Incidence entries: for edge e = (a, b), h(e, a) = sign sqrt(w_e) s_a with
+// sign +1 when a < b (Sec. 2 convention), and sqrt(w_e) s_a = sqrt(val s_a/s_b)
+// because val = w_e s_a s_b.  Table 1 generalises to x_e^T x_f = h(e,u) h(f,u)
+// for distinct edges meeting at u, and h(e,a)^2 + h(e,b)^2 for e = f.
+//
+// Moving from e = (a, b): draw t uniform in [0, d_a + d_b - 1); t < d_a picks
+// entry t of row a (this includes e itself, the self-loop of H), otherwise
+// entry t - d_a of row b with b's copy of e (position rev[p]) skipped.
+//
+// importance sampler: one 64-lane wavefront per output row, split into lane
+// groups that each run walks of that row; the walk weight
+//   omega_1 = d_r h(e_1, r),   omega_{i+1} = omega_i (x_{e_i}^T x_{e_{i+1}}) deg_H(e_i)
+// is alpha_c (x_{e_1})_r / q(c) for the proposal q, so each prefix adds
+// c_i omega_i (x_{e_i}^T X) to row r; the groups' sums meet by xor shuffles and
+// one store writes the row.  No atomics: the result is deterministic.
+//
+// rejection sampler: lane groups run trials; e_1 is uniform over the stored
+// entries (each edge twice), prefix i is kept with probability
+// prod_{t<i} deg_H(e_t) / (2 deg* - 1) (decided in float64 with the oracle's
+// operation order) and contributes (|E|/N) prod_t (2deg*-1) x_et^T x_et+1 c_i
+// x_{e_1} (x_{e_i}^T X), added to both endpoints of e_1 with float atomics.
+#include <cmath>
+
+#include "common.h"
+
+namespace sped {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxDeg = 255;
+
+// Polynomial coefficients travel by value in the kernel arguments (2 KiB), so
+// concurrent calls with different polynomials never share state.
+struct Coefs {
+  double c[kMaxDeg + 1];
+};
+
+struct Edge {
+  int64_t p;       // CSR position
+  int32_t a, b;    // p lies in row a; b = col[p]
+  int64_t a0, a1;  // rowptr[a], rowptr[a+1]
+  int64_t b0, b1;  // rowptr[b], rowptr[b+1]
+  float sa, sb;    // node scales
+  double ha, hb;   // incidence entries h(e, a), h(e, b)
+};
+
+__device__ inline void edge_entries(Edge &e, float val) {
+  double v = double(val);
+  double ga, gb;
+  if (e.sa == e.sb) {
+    ga = gb = sqrt(v);
+  } else {
+    double ratio = double(e.sa) / double(e.sb);
+    ga = sqrt(v * ratio);
+    gb = sqrt(v / ratio);
+  }
+  const double sg = e.a < e.b ? 1.0 : -1.0;
+  e.ha = sg * ga;
+  e.hb = -sg * gb;
+}
+
+// Entry h(f, u) of an edge f stored at position q in row u with other end v.
+__device__ inline double entry_at(int32_t u, int32_t v, float val, float su, float sv) {
+  double g = (su == sv) ? sqrt(double(val)) : sqrt(double(val) * double(su) / double(sv));
+  return u < v ? g : -g;
+}
+
+struct Graph {
+  const int64_t *rowptr;
+  const int32_t *col;
+  const float *val;
+  const int64_t *rev;
+  const float *scale;
+};
+
+// Move along H; returns x_e^T x_f and sets deg_H(e) in *degH.
+__device__ inline double move(const Graph &g, Edge &e, uint32_t t, uint32_t *degH) {
+  const int64_t da = e.a1 - e.a0, db = e.b1 - e.b0;
+  *degH = uint32_t(da + db - 1);
+  int64_t q;
+  int32_t u;
+  int64_t u0, u1;
+  float su;
+  double h_eu;
+  if (int64_t(t) < da) {
+    q = e.a0 + t;
+    u = e.a; u0 = e.a0; u1 = e.a1; su = e.sa; h_eu = e.ha;
+  } else {
+    q = e.b0 + (int64_t(t) - da);
+    if (q >= g.rev[e.p]) ++q;
+    u = e.b; u0 = e.b0; u1 = e.b1; su = e.sb; h_eu = e.hb;
+  }
+  double dot;
+  if (q == e.p) {
+    dot = e.ha * e.ha + e.hb * e.hb;
+    return dot;  // the walk stays on e
+  }
+  const int32_t v = g.col[q];
+  const float vq = g.val[q];
+  const float sv = g.scale[v];
+  const double h_fu = entry_at(u, v, vq, su, sv);
+  dot = h_eu * h_fu;
+  e.p = q;
+  e.a = u; e.a0 = u0; e.a1 = u1; e.sa = su;
+  e.b = v; e.b0 = g.rowptr[v]; e.b1 = g.rowptr[v + 1]; e.sb = sv;
+  edge_entries(e, vq);
+  return dot;
+}
+
+template <typename TX, typename TY, int VEC>
+__global__ __launch_bounds__(kBlock) void walk_importance_kernel(
+    int64_t n, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
+    TY *__restrict__ Y, int64_t ldy, int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, Coefs cf) {
+  const int lane = threadIdx.x & 63;
+  const int lig = lane & (G - 1);
+  const int sub = lane >> lgG;
+  const int nsub = 64 >> lgG;
+  const int64_t r = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  if (r >= n) return;  // whole wavefront exits together
+  float acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+  const int64_t r0 = g.rowptr[r], r1 = g.rowptr[r + 1];
+  const int64_t dr = r1 - r0;
+  if (dr > 0) {
+    const float sr = g.scale[r];
+    for (int64_t w = sub; w < walks; w += nsub) {
+      Edge e;
+      uint32_t t0 = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 0u, uint32_t(dr));
+      e.p = r0 + t0;
+      e.a = int32_t(r); e.a0 = r0; e.a1 = r1; e.sa = sr;
+      e.b = g.col[e.p];
+      e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
+      e.sb = g.scale[e.b];
+      edge_entries(e, g.val[e.p]);
+      double omega = double(dr) * e.ha;
+      float xa[VEC], xb[VEC];
+      if (col_ok) {
+        VecIO<TX, VEC>::load(X + int64_t(e.a) * ldx + c0, xa);
+        VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
+      }
+      for (int i = 1; i <= ell; ++i) {
+        if (i > 1) {
+          const int32_t olda = e.a;
+          const int32_t oldb = e.b;
+          uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
+          uint32_t t = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(i - 1), bound);
+          uint32_t degH;
+          double dot = move(g, e, t, &degH);
+          omega = omega * dot * double(degH);
+          if (col_ok && (e.a != olda || e.b != oldb)) {
+            // the shared node's row is already loaded; fetch the new far end
+            if (e.a == oldb) {
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) xa[v] = xb[v];
+            }
+            VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
+          }
+        }
+        const float wa = float(cf.c[i] * omega * e.ha);
+        const float wb = float(cf.c[i] * omega * e.hb);
+        if (col_ok) {
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wa, xa[v], fmaf(wb, xb[v], acc[v]));
+        }
+      }
+    }
+  }
+  for (int off = G; off < 64; off <<= 1)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
+  if (sub == 0 && col_ok) {
+    float x[VEC], o[VEC];
+    VecIO<TX, VEC>::load(X + r * ldx + c0, x);
+    const float inv = float(1.0 / double(walks));
+    const float c0f = float(cf.c[0]);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] = fmaf(c0f, x[v], acc[v] * inv);
+    VecIO<TY, VEC>::store(Y + r * ldy + c0, o);
+  }
+}
+
+template <typename TX>
+__global__ __launch_bounds__(kBlock) void scale_init_kernel(int64_t n, int k, const TX *__restrict__ X,
+                                                             int64_t ldx, float *__restrict__ Y, int64_t ldy,
+                                                             double c0d) {
+  const float c0 = float(c0d);
+  const int64_t total = n * k;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    int64_t r = i / k, c = i - r * k;
+    Y[r * ldy + c] = c0 * to_f32<TX>(X[r * ldx + c]);
+  }
+}
+
+__device__ inline int32_t row_of(const int64_t *rowptr, int64_t n, int64_t p) {
+  // largest r with rowptr[r] <= p
+  int64_t lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (rowptr[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return int32_t(lo);
+}
+
+template <typename TX, int VEC>
+__global__ __launch_bounds__(kBlock) void walk_reject_kernel(
+    int64_t n, int64_t nnz, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
+    float *__restrict__ Y, int64_t ldy, int64_t trials, uint32_t k0, uint32_t k1, uint32_t ctr,
+    double scale, double d_inc, unsigned long long *__restrict__ counts, Coefs cf) {
+  __shared__ unsigned int bcount[kMaxDeg];
+  for (int i = threadIdx.x; i < ell; i += kBlock) bcount[i] = 0;
+  __syncthreads();
+  const int lig = threadIdx.x & (G - 1);
+  const int grp = threadIdx.x >> lgG;
+  const int gpb = kBlock >> lgG;
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  for (int64_t T = int64_t(blockIdx.x) * gpb + grp; T < trials; T += int64_t(gridDim.x) * gpb) {
+    const uint32_t tc0 = uint32_t(uint64_t(T) & 0xffffffffu);
+    const uint32_t tc1 = uint32_t(uint64_t(T) >> 32) | 0x80000000u;
+    Edge e;
+    uint32_t p0 = lemire_draw(k0, k1, tc0, tc1, ctr, 0u, uint32_t(nnz));
+    e.p = p0;
+    e.a = row_of(g.rowptr, n, e.p);
+    e.a0 = g.rowptr[e.a]; e.a1 = g.rowptr[e.a + 1];
+    e.b = g.col[e.p];
+    e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
+    e.sa = g.scale[e.a]; e.sb = g.scale[e.b];
+    edge_entries(e, g.val[e.p]);
+    const int32_t a1 = e.a, b1 = e.b;
+    const double h1a = e.ha, h1b = e.hb;
+    double rho = 1.0, accept_p = 1.0;
+    float acc_a[VEC], acc_b[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) acc_a[v] = acc_b[v] = 0.f;
+    bool any = false;
+    for (int i = 1; i <= ell; ++i) {
+      bool ok = true;
+      if (i > 1) {
+        uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
+        uint32_t t = lemire_draw(k0, k1, tc0, tc1, ctr, uint32_t(i - 1), bound);
+        uint32_t degH;
+        double dot = move(g, e, t, &degH);
+        rho = rho * (dot * d_inc);
+        accept_p = (accept_p * double(degH)) / d_inc;
+        double u = uniform53(k0, k1, tc0, tc1, ctr, uint32_t(ell + i));
+        ok = u < accept_p;
+      }
+      if (ok) {
+        if (lig == 0) atomicAdd(&bcount[i - 1], 1u);
+        any = true;
+        if (col_ok) {
+          float xa[VEC], xb[VEC];
+          VecIO<TX, VEC>::load(X + int64_t(e.a) * ldx + c0, xa);
+          VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
+          const double base = cf.c[i] * scale * rho;
+          const float wa = float(base * e.ha), wb = float(base * e.hb);
+          const float fa = float(h1a), fb = float(h1b);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) {
+            float val = fmaf(wa, xa[v], wb * xb[v]);
+            acc_a[v] = fmaf(fa, val, acc_a[v]);
+            acc_b[v] = fmaf(fb, val, acc_b[v]);
+          }
+        }
+      }
+    }
+    if (any && col_ok) {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        atomicAdd(Y + int64_t(a1) * ldy + c0 + v, acc_a[v]);
+        atomicAdd(Y + int64_t(b1) * ldy + c0 + v, acc_b[v]);
+      }
+    }
+  }
+  __syncthreads();
+  if (counts && blockIdx.y == 0)
+    for (int i = threadIdx.x; i < ell; i += kBlock)
+      if (bcount[i]) atomicAdd(counts + i, (unsigned long long)bcount[i]);
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int count) {
+  int i = threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+template <typename TX, typename TY>
+sped_status launch_is(const sped_csr *L, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                      int ell, int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, const Coefs &cf,
+                      hipStream_t s) {
+  int vec = pick_vec(k, {ldx, ldy}, {X, Y}, {int(sizeof(TX)), int(sizeof(TY))});
+  int lanes = int((k + vec - 1) / vec);
+  int ytiles = (lanes + 63) / 64;
+  int G = lanes >= 64 ? 64 : next_pow2(lanes);
+  int lgG = ilog2(G);
+  Graph g{L->rowptr, L->col, L->val, L->rev, L->scale};
+  const dim3 grid = dim3(unsigned((L->n + 3) / 4), unsigned(ytiles));
+#define SPED_IS(V)                                                                                      \
+  hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, int(k), G, lgG, g, \
+                     ell, static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr, cf)
+  if (vec == 4) SPED_IS(4);
+  else if (vec == 2) SPED_IS(2);
+  else SPED_IS(1);
+#undef SPED_IS
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+template <typename TX>
+sped_status launch_rej(const sped_csr *L, int64_t k, const void *X, int64_t ldx, float *Y, int64_t ldy, int ell,
+                       int64_t trials, uint32_t k0, uint32_t k1, uint32_t ctr, int64_t *counts, const Coefs &cf,
+                       hipStream_t s) {
+  int vec = pick_vec(k, {ldx, ldy}, {X, Y}, {int(sizeof(TX)), 4});
+  int lanes = int((k + vec - 1) / vec);
+  int ytiles = (lanes + 63) / 64;
+  int G = lanes >= 64 ? 64 : next_pow2(lanes);
+  int lgG = ilog2(G);
+  Graph g{L->rowptr, L->col, L->val, L->rev, L->scale};
+  const int64_t total = L->n * k;
+  int64_t iblocks = (total + kBlock - 1) / kBlock;
+  if (iblocks > 4096) iblocks = 4096;
+  hipLaunchKernelGGL((scale_init_kernel<TX>), dim3(unsigned(iblocks > 0 ? iblocks : 1)), dim3(kBlock), 0, s,
+                     L->n, int(k), static_cast<const TX *>(X), ldx, Y, ldy, cf.c[0]);
+  SPED_CHECK_HIP(hipGetLastError());
+  unsigned long long *cnt = reinterpret_cast<unsigned long long *>(counts);
+  if (cnt) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(kBlock), 0, s, cnt, ell);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  if (L->nnz == 0) return SPED_OK;  // no edges: the estimate is c_0 X exactly
+  const double n_edges = double(L->nnz / 2);
+  const double scale = n_edges / double(trials);
+  const double d_inc = double(2 * int64_t(L->max_degree) - 1);
+  int64_t gpb = kBlock >> lgG;
+  int64_t blocks = (trials + gpb - 1) / gpb;
+  if (blocks > 65536) blocks = 65536;
+  const dim3 grid = dim3(unsigned(blocks), unsigned(ytiles));
+#define SPED_REJ(V)                                                                                  \
+  hipLaunchKernelGGL((walk_reject_kernel<TX, V>), grid, dim3(kBlock), 0, s, L->n, L->nnz, int(k), G, lgG, g, \
+                     ell, static_cast<const TX *>(X), ldx, Y, ldy, trials, k0, k1, ctr, scale, d_inc, cnt, cf)
+  if (vec == 4) SPED_REJ(4);
+  else if (vec == 2) SPED_REJ(2);
+  else SPED_REJ(1);
+#undef SPED_REJ
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+}  // namespace
+
+sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int64_t k, const void *X,
+                               int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler, int64_t walks,
+                               uint64_t seed, uint64_t counter, int64_t *accept_counts, hipStream_t s) {
+  Coefs cf{};
+  for (int i = 0; i <= degree; ++i) cf.c[i] = coeffs[i];
+  const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32);
+  const uint32_t ctr = uint32_t(counter);
+  if (sampler == 0) {
+    if (xdt == SPED_F32 && ydt == SPED_F32) return launch_is<float, float>(L, k, X, ldx, Y, ldy, degree, walks, k0, k1, ctr, cf, s);
+    if (xdt == SPED_F32 && ydt == SPED_BF16) return launch_is<float, bf16_t>(L, k, X, ldx, Y, ldy, degree, walks, k0, k1, ctr, cf, s);
+    if (xdt == SPED_BF16 && ydt == SPED_F32) return launch_is<bf16_t, float>(L, k, X, ldx, Y, ldy, degree, walks, k0, k1, ctr, cf, s);
+    return launch_is<bf16_t, bf16_t>(L, k, X, ldx, Y, ldy, degree, walks, k0, k1, ctr, cf, s);
+  }
+  if (xdt == SPED_F32)
+    return launch_rej<float>(L, k, X, ldx, static_cast<float *>(Y), ldy, degree, walks, k0, k1, ctr, accept_counts, cf, s);
+  return launch_rej<bf16_t>(L, k, X, ldx, static_cast<float *>(Y), ldy, degree, walks, k0, k1, ctr, accept_counts, cf, s);
+}
+
+}  // namespace sped
+
+using namespace sped;
+
+extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, int32_t degree,
+                                                  int64_t k, const void *X, int64_t ldx, int32_t xdt, void *Y,
+                                                  int64_t ldy, int32_t ydt, int32_t sampler, int64_t walks,
+                                                  uint64_t seed, uint64_t counter, int64_t *accept_counts,
+                                                  void *ws, size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (degree < 1 || degree > kMaxDeg) return fail(SPED_E_INVALID, "degree outside [1, 255]");
+  if (!coeffs) return fail(SPED_E_INVALID, "coeffs NULL");
+  for (int i = 0; i <= degree; ++i)
+    if (!std::isfinite(coeffs[i])) return fail(SPED_E_INVALID, "coefficient not finite");
+  if (k < 1) return fail(SPED_E_INVALID, "k < 1");
+  if (ldx < k || ldy < k) return fail(SPED_E_INVALID, "leading dimension < k");
+  if ((xdt != SPED_F32 && xdt != SPED_BF16) || (ydt != SPED_F32 && ydt != SPED_BF16))
+    return fail(SPED_E_UNSUPPORTED, "dtype");
+  if (L->n > 0 && (!X || !Y)) return fail(SPED_E_INVALID, "X or Y NULL");
+  if (L->nnz > 0 && !L->rev) return fail(SPED_E_INVALID, "csr rev NULL");
+  if (sampler != 0 && sampler != 1) return fail(SPED_E_INVALID, "sampler must be 0 or 1");
+  if (walks < 1) return fail(SPED_E_INVALID, "walks < 1");
+  if (counter >= (uint64_t(1) << 32)) return fail(SPED_E_INVALID, "counter >= 2^32");
+  if (sampler == 0 && walks >= (int64_t(1) << 32)) return fail(SPED_E_INVALID, "walks per row >= 2^32");
+  if (sampler == 1) {
+    if (ydt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "rejection sampler needs a float32 Y");
+    if (L->nnz >= (int64_t(1) << 32)) return fail(SPED_E_UNSUPPORTED, "rejection sampler needs nnz < 2^32");
+  }
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, 0, &query));
+  if (query || L->n == 0) return SPED_OK;
+  return walk_estimate_impl(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
+                            accept_counts, as_stream(stream));
+}

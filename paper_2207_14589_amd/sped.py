@@ -1,0 +1,349 @@
+"""ctypes binding of libsped (include/sped.h) over torch device tensors.
+
+Argument marshalling only: every computation runs in the HIP library.  torch
+provides device memory (inputs, outputs, workspaces) and the current stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsped.so")
+
+OK, E_INVALID, E_WORKSPACE, E_DEVICE, E_NUMERIC, E_NOT_CONVERGED, E_UNSUPPORTED = range(7)
+F32, BF16, F64 = 0, 1, 2
+COMBINATORIAL, SYM_NORMALIZED = 0, 1
+POLY_MONOMIAL, POLY_LIMIT = 0, 1
+T_PLAIN, T_LIMIT, T_TAYLOR_EXP, T_TAYLOR_LOG = 0, 1, 2, 3
+LIGHT_MAX, MEDIUM_MAX = 128, 8192
+
+_c_i32, _c_i64, _c_u64, _c_f64, _c_vp, _c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                                ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t)
+
+
+class CSR(ctypes.Structure):
+    _fields_ = [("n", _c_i64), ("nnz", _c_i64), ("rowptr", _c_vp), ("col", _c_vp), ("val", _c_vp),
+                ("rev", _c_vp), ("diag", _c_vp), ("scale", _c_vp), ("bins", _c_vp),
+                ("n_medium", _c_i64), ("n_heavy", _c_i64), ("max_degree", _c_i32), ("kind", _c_i32),
+                ("lambda_bound", _c_f64)]
+
+
+class Poly(ctypes.Structure):
+    _fields_ = [("kind", _c_i32), ("degree", _c_i32), ("coeffs", ctypes.POINTER(_c_f64)),
+                ("shift", _c_f64), ("scale", _c_f64)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("solver", _c_i32), ("eta", _c_f64), ("tol", _c_f64), ("max_iters", _c_i32),
+                ("check_every", _c_i32), ("guard", _c_i32), ("orth_passes", _c_i32),
+                ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", _c_i32), ("spmm_count", _c_i64), ("seconds", _c_f64), ("max_residual", _c_f64),
+                ("gap_estimate", _c_f64), ("bound", _c_f64), ("converged", _c_i32),
+                ("cholqr_shifts", _c_i32)]
+
+
+_P = ctypes.POINTER
+SIGNATURES = {
+    "sped_laplacian_csr": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_i32, _c_i32, _P(CSR), _c_vp, _c_vp,
+                           _P(_c_sz), _c_vp],
+    "sped_transform_coeffs": [_c_i32, _c_i32, _c_f64, _c_f64, _P(_c_f64), _P(_c_f64), _P(_c_f64)],
+    "sped_poly_monomial": [_P(Poly), _P(_c_f64)],
+    "sped_apply_poly": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp,
+                        _P(_c_sz), _c_vp],
+    "sped_apply_poly_stochastic": [_P(CSR), _P(_c_f64), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
+                                   _c_i32, _c_i32, _c_i64, _c_u64, _c_u64, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_poly_backward": [_P(CSR), _c_i32, _c_f64, _c_f64, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_vp,
+                           _P(_c_sz), _c_vp],
+    "sped_gram": [_c_i64, _c_i64, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_orthonormalize": [_c_i64, _c_i64, _c_vp, _c_i64, _c_i32, _c_i32, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_rayleigh_ritz": [_P(CSR), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_bottomk_solve": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _P(_c_f64),
+                           _P(_c_f64), _P(SolveOpts), _P(SolveStats), _c_vp, _P(_c_sz), _c_vp],
+    "sped_cluster_embed": [_c_vp, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, _c_i32, _c_u64, _c_i32, _c_vp, _c_vp,
+                           _c_vp, _P(_c_f64), _P(_c_i32), _c_vp, _P(_c_sz), _c_vp],
+    "sped_stream_copy": [_c_vp, _c_vp, _c_sz, _c_vp],
+    "sped_last_error": [],
+    "sped_version": [],
+}
+
+_lib = None
+
+
+class SpedError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libsped.so (built by paper_2207_14589_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2207_14589_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "sped_last_error" else _c_i32
+        _lib = L
+    return _lib
+
+
+def _check(status, where, allow=()):
+    if status != OK and status not in allow:
+        raise SpedError(status, where, lib().sped_last_error().decode())
+    return status
+
+
+def _stream(device=None):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ld(t):
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("blocks must be 2-D with unit column stride")
+    return t.stride(0)
+
+
+def _workspace(nbytes, device):
+    if nbytes == 0:
+        return None
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes)]
+
+
+def _call_ws(fn, where, args_before_ws, device, allow=()):
+    """Size query (ws = NULL), allocate, then run; stream is the last argument."""
+    need = ctypes.c_size_t(0)
+    _check(fn(*args_before_ws, None, ctypes.byref(need), _stream(device)), where + " (size query)")
+    ws = _workspace(need.value, device)
+    if ws is None:   # no workspace needed: ws = NULL with ws_bytes = NULL runs the call
+        st = fn(*args_before_ws, None, None, _stream(device))
+    else:
+        st = fn(*args_before_ws, _ptr(ws), ctypes.byref(need), _stream(device))
+    _check(st, where, allow)
+    return st, ws
+
+
+# ------------------------------------------------------------------ Laplacian
+class Laplacian:
+    """Device split CSR of L = diag - S built by sped_laplacian_csr."""
+
+    def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda"):
+        dev = torch.device(device)
+        src = torch.as_tensor(np.asarray(src), dtype=torch.int32).to(dev)
+        dst = torch.as_tensor(np.asarray(dst), dtype=torch.int32).to(dev)
+        wt = None if w is None else torch.as_tensor(np.asarray(w), dtype=torch.float32).to(dev)
+        m = src.numel()
+        n = int(n)
+        if dst.numel() != m or (wt is not None and wt.numel() != m):
+            raise ValueError("src, dst and w must have the same length")
+        self.device = dev
+        self.rowptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        self.col = torch.empty(max(2 * m, 1), dtype=torch.int32, device=dev)
+        self.val = torch.empty(max(2 * m, 1), dtype=torch.float32, device=dev)
+        self.rev = torch.empty(max(2 * m, 1), dtype=torch.int64, device=dev)
+        self.diag = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        self.scale = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        self.bins = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.old_of_new = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        c = CSR()
+        c.rowptr, c.col, c.val, c.rev = (self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
+                                         self.rev.data_ptr())
+        c.diag, c.scale, c.bins = self.diag.data_ptr(), self.scale.data_ptr(), self.bins.data_ptr()
+        kind_i = {"sym": SYM_NORMALIZED, "combinatorial": COMBINATORIAL}[kind] if isinstance(kind, str) else kind
+        self.kind = kind_i
+        fn = lib().sped_laplacian_csr
+        _call_ws(fn, "sped_laplacian_csr",
+                 (n, m, _ptr(src), _ptr(dst), _ptr(wt), kind_i, int(bool(lcc)), ctypes.byref(c),
+                  _ptr(self.old_of_new)), dev)
+        self.c = c
+        self.n, self.nnz = c.n, c.nnz
+        self.max_degree, self.lambda_bound = c.max_degree, c.lambda_bound
+        self.n_medium, self.n_heavy = c.n_medium, c.n_heavy
+        self.old_of_new = self.old_of_new[: self.n]
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+    def host_csr(self):
+        """(rowptr, col, val, diag, scale) as numpy arrays, for checks."""
+        n, nnz = self.n, self.nnz
+        return (self.rowptr[: n + 1].cpu().numpy(), self.col[:nnz].cpu().numpy(), self.val[:nnz].cpu().numpy(),
+                self.diag[:n].cpu().numpy(), self.scale[:n].cpu().numpy())
+
+
+# ------------------------------------------------------------------ polynomials
+@dataclass
+class PolySpec:
+    kind: int
+    degree: int
+    coeffs: np.ndarray = field(default_factory=lambda: np.zeros(1))
+    shift: float = 0.0
+    scale: float = 1.0
+
+    def struct(self):
+        self._buf = np.ascontiguousarray(self.coeffs, dtype=np.float64)
+        p = Poly()
+        p.kind, p.degree = self.kind, self.degree
+        p.coeffs = self._buf.ctypes.data_as(ctypes.POINTER(_c_f64))
+        p.shift, p.scale = float(self.shift), float(self.scale)
+        return p
+
+    def monomial(self):
+        out = np.zeros(self.degree + 1)
+        p = self.struct()
+        _check(lib().sped_poly_monomial(ctypes.byref(p), out.ctypes.data_as(ctypes.POINTER(_c_f64))),
+               "sped_poly_monomial")
+        return out
+
+
+def transform(name, degree, lambda_bound=2.0, eps=1e-3, product_form=True):
+    """Table 2 operator M reversed by eq. reveig: 'plain', 'limit', 'taylor_exp', 'taylor_log'."""
+    t = {"plain": T_PLAIN, "limit": T_LIMIT, "taylor_exp": T_TAYLOR_EXP, "taylor_log": T_TAYLOR_LOG}[name]
+    if name == "plain":
+        degree = 1
+    c = np.zeros(degree + 1)
+    sh, sc = _c_f64(0), _c_f64(1)
+    _check(lib().sped_transform_coeffs(t, degree, lambda_bound, eps, c.ctypes.data_as(ctypes.POINTER(_c_f64)),
+                                       ctypes.byref(sh), ctypes.byref(sc)), "sped_transform_coeffs")
+    if name == "limit" and product_form:
+        return PolySpec(POLY_LIMIT, degree, c, 0.0, 1.0)
+    return PolySpec(POLY_MONOMIAL, degree, c, sh.value, sc.value)
+
+
+def monomial(coeffs, shift=0.0, scale=1.0):
+    c = np.asarray(coeffs, dtype=np.float64)
+    return PolySpec(POLY_MONOMIAL, len(c) - 1, c, shift, scale)
+
+
+# ------------------------------------------------------------------ operations
+def apply_poly(L: Laplacian, p: PolySpec, X: torch.Tensor, out=None, out_dtype=None):
+    k = X.shape[1]
+    if out is None:
+        out = torch.empty(L.n, k, dtype=out_dtype or X.dtype, device=X.device)
+    ps = p.struct()
+    _call_ws(lib().sped_apply_poly, "sped_apply_poly",
+             (L.ref, ctypes.byref(ps), k, _ptr(X), _ld(X), _dt(X), _ptr(out), _ld(out), _dt(out)), X.device)
+    return out
+
+
+def apply_poly_stochastic(L: Laplacian, coeffs, X, walks, seed, counter=0, sampler="importance", out=None,
+                          out_dtype=None, accept_counts=False):
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    k = X.shape[1]
+    smp = {"importance": 0, "reject": 1}[sampler]
+    if out is None:
+        out = torch.empty(L.n, k, dtype=out_dtype or (torch.float32 if smp == 1 else X.dtype), device=X.device)
+    counts = torch.zeros(len(c) - 1, dtype=torch.int64, device=X.device) if accept_counts else None
+    _call_ws(lib().sped_apply_poly_stochastic, "sped_apply_poly_stochastic",
+             (L.ref, c.ctypes.data_as(ctypes.POINTER(_c_f64)), len(c) - 1, k, _ptr(X), _ld(X), _dt(X), _ptr(out),
+              _ld(out), _dt(out), smp, int(walks), int(seed), int(counter), _ptr(counts)), X.device)
+    return (out, counts) if accept_counts else out
+
+
+def poly_backward(L: Laplacian, degree, X, dY, shift=0.0, scale=1.0):
+    dtheta = torch.empty(degree + 1, dtype=torch.float64, device=X.device)
+    _call_ws(lib().sped_poly_backward, "sped_poly_backward",
+             (L.ref, degree, shift, scale, X.shape[1], _ptr(X), _ld(X), _ptr(dY), _ld(dY), _ptr(dtheta)), X.device)
+    return dtheta
+
+
+def gram(A, B=None):
+    B = A if B is None else B
+    G = torch.empty(A.shape[1], B.shape[1], dtype=torch.float64, device=A.device)
+    _call_ws(lib().sped_gram, "sped_gram",
+             (A.shape[0], A.shape[1], B.shape[1], _ptr(A), _ld(A), _ptr(B), _ld(B), _dt(A), _ptr(G)), A.device)
+    return G
+
+
+def orthonormalize(V, passes=2, want_r=False):
+    R = torch.empty(V.shape[1], V.shape[1], dtype=torch.float64, device=V.device) if want_r else None
+    _call_ws(lib().sped_orthonormalize, "sped_orthonormalize",
+             (V.shape[0], V.shape[1], _ptr(V), _ld(V), _dt(V), passes, _ptr(R)), V.device)
+    return (V, R) if want_r else V
+
+
+def rayleigh_ritz(L: Laplacian, Q):
+    k = Q.shape[1]
+    theta = torch.empty(k, dtype=torch.float64, device=Q.device)
+    resid = torch.empty(k, dtype=torch.float64, device=Q.device)
+    _call_ws(lib().sped_rayleigh_ritz, "sped_rayleigh_ritz",
+             (L.ref, k, _ptr(Q), _ld(Q), _dt(Q), _ptr(theta), _ptr(resid)), Q.device)
+    return theta, resid
+
+
+@dataclass
+class SolveResult:
+    evals: np.ndarray
+    V: torch.Tensor
+    residuals: np.ndarray
+    stats: dict
+    converged: bool
+
+
+def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
+            check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
+            seed=3, v0_seed=2):
+    dev = L.device
+    kb = k + guard
+    if V0 is None:
+        g = torch.Generator(device="cpu").manual_seed(v0_seed)
+        V0 = torch.randn(L.n, kb, generator=g, dtype=torch.float64).to(torch.float32).to(dev)
+    V_out = torch.empty(L.n, k, dtype=torch.float32, device=dev)
+    ev = np.zeros(k)
+    rs = np.zeros(k)
+    o = SolveOpts(solver={"subspace": 0, "oja": 1}[solver], eta=eta, tol=tol, max_iters=max_iters,
+                  check_every=check_every, guard=guard, orth_passes=orth_passes,
+                  stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed)
+    st = SolveStats()
+    ps = poly.struct() if poly is not None else None
+    status, _ = _call_ws(lib().sped_bottomk_solve, "sped_bottomk_solve",
+                         (L.ref, ctypes.byref(ps) if ps is not None else None, k, _ptr(V0), _ld(V0), _ptr(V_out),
+                          _ld(V_out), F32, ev.ctypes.data_as(ctypes.POINTER(_c_f64)),
+                          rs.ctypes.data_as(ctypes.POINTER(_c_f64)), ctypes.byref(o), ctypes.byref(st)), dev,
+                         allow=(E_NOT_CONVERGED,))
+    stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    return SolveResult(ev, V_out, rs, stats, status == OK)
+
+
+def cluster_embed(V, n_clusters, row_normalize=True, seed=0, max_iters=300, init=None):
+    n, k = V.shape
+    labels = torch.empty(n, dtype=torch.int32, device=V.device)
+    cent = torch.empty(n_clusters, k, dtype=torch.float64, device=V.device)
+    inertia = _c_f64(0)
+    iters = _c_i32(0)
+    init_t = None if init is None else torch.as_tensor(init, dtype=torch.float64).to(V.device).contiguous()
+    _call_ws(lib().sped_cluster_embed, "sped_cluster_embed",
+             (_ptr(V), n, k, _ld(V), _dt(V), n_clusters, int(bool(row_normalize)), int(seed), max_iters,
+              _ptr(init_t), _ptr(labels), _ptr(cent), ctypes.byref(inertia), ctypes.byref(iters)), V.device)
+    return labels, cent, inertia.value, iters.value
+
+
+def stream_copy(src, dst):
+    _check(lib().sped_stream_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream(src.device)),
+           "sped_stream_copy")

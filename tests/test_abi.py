@@ -1,0 +1,116 @@
+"""The C-ABI library loads, exports every symbol include/sped.h declares, and
+its host-only logic (argument validation, Table 2 coefficients) behaves; no
+GPU needed."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import poly as opoly
+from paper_2207_14589_amd import sped
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sped.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sped_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(sped.LIB_PATH):
+        pytest.fail("libsped.so is not built (run python -m paper_2207_14589_amd.build)")
+    return sped.lib()
+
+
+def test_every_declared_symbol_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(sped.SIGNATURES), "binding and header disagree"
+
+
+def test_version_and_error_string(lib):
+    assert lib.sped_version() == 10000
+    assert lib.sped_last_error() == b""
+
+
+def test_transform_coeffs_match_table2(lib):
+    lam = 2.0
+    for ell in (3, 8, 16):
+        np.testing.assert_allclose(sped.transform("limit", ell, lam, product_form=False).coeffs,
+                                   opoly.limit_exp(ell).coeffs, rtol=1e-14, atol=1e-300)
+        np.testing.assert_allclose(sped.transform("taylor_exp", ell, lam).coeffs, opoly.taylor_exp(ell).coeffs,
+                                   rtol=1e-14)
+        t = sped.transform("taylor_log", ell, lam, eps=1e-3)
+        o = opoly.taylor_log(ell, lam, 1e-3)
+        np.testing.assert_allclose(t.coeffs, o.coeffs, rtol=1e-13)
+        assert t.shift == pytest.approx(o.shift)
+    np.testing.assert_allclose(sped.transform("plain", 1, 3.5).coeffs, [3.5, -1.0])
+
+
+def test_monomial_expansion(lib):
+    t = sped.transform("taylor_log", 7, 2.0)
+    np.testing.assert_allclose(t.monomial(), opoly.monomial_in_L(opoly.taylor_log(7, 2.0)), rtol=1e-11, atol=1e-12)
+    lim = sped.transform("limit", 16, 2.0, product_form=True)
+    np.testing.assert_allclose(lim.monomial(), opoly.limit_exp(16).coeffs, rtol=1e-13, atol=1e-300)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    need = ctypes.c_size_t(0)
+    # NULL csr
+    st = lib.sped_apply_poly(None, None, 4, None, 4, 0, None, 4, 0, None, ctypes.byref(need), None)
+    assert st == sped.E_INVALID
+    assert b"csr" in lib.sped_last_error()
+    # degree 0 polynomial
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 0, 0, sped.SYM_NORMALIZED
+    p = sped.Poly()
+    p.kind, p.degree = sped.POLY_MONOMIAL, 0
+    st = lib.sped_apply_poly(ctypes.byref(c), ctypes.byref(p), 4, None, 4, 0, None, 4, 0, None, ctypes.byref(need),
+                             None)
+    assert st == sped.E_INVALID
+    # bad transform degree for plain
+    out = np.zeros(3)
+    sh, sc = ctypes.c_double(), ctypes.c_double()
+    assert lib.sped_transform_coeffs(sped.T_PLAIN, 2, 2.0, 0.0, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.byref(sh), ctypes.byref(sc)) == sped.E_INVALID
+    # stochastic counter out of range, unsupported rejection dtype
+    coef = np.array([1.0, 0.5])
+    cp = coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.n = 0
+    assert lib.sped_apply_poly_stochastic(ctypes.byref(c), cp, 1, 4, None, 4, 0, None, 4, 0, 0, 8, 1, 1 << 33, None,
+                                          None, ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_apply_poly_stochastic(ctypes.byref(c), cp, 1, 4, None, 4, 0, None, 4, 1, 1, 8, 1, 0, None,
+                                          None, ctypes.byref(need), None) == sped.E_UNSUPPORTED
+    # orthonormalize: k > n
+    assert lib.sped_orthonormalize(3, 5, None, 5, 0, 2, None, None, ctypes.byref(need), None) == sped.E_INVALID
+    # cluster: too many clusters
+    assert lib.sped_cluster_embed(None, 10, 2, 2, 0, 11, 1, 0, 10, None, None, None, None, None, None,
+                                  ctypes.byref(need), None) == sped.E_INVALID
+
+
+def test_workspace_size_query_without_device(lib):
+    """Size queries are pure host arithmetic."""
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 1000, 8000, sped.SYM_NORMALIZED
+    c.rowptr = c.diag = c.scale = c.col = c.val = 16
+    p = sped.transform("limit", 16).struct()
+    need = ctypes.c_size_t(0)
+    st = lib.sped_apply_poly(ctypes.byref(c), ctypes.byref(p), 32, 256, 32, 0, 512, 32, 0, None,
+                             ctypes.byref(need), None)
+    assert st == sped.OK and need.value >= 2 * 1000 * 32 * 4
+    need2 = ctypes.c_size_t(0)
+    assert lib.sped_gram(1000, 32, 32, 256, 32, 256, 32, 0, 512, None, ctypes.byref(need2), None) == sped.OK
+    assert need2.value > 0
+    small = ctypes.c_size_t(16)
+    ws = ctypes.create_string_buffer(1024)
+    aligned = (ctypes.addressof(ws) + 255) // 256 * 256
+    assert lib.sped_gram(1000, 32, 32, 256, 32, 256, 32, 0, 512, aligned, ctypes.byref(small), None) == \
+        sped.E_WORKSPACE

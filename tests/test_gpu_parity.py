@@ -1,0 +1,408 @@
+"""GPU parity: every libsped entry point against the FP64 oracle on the same
+seeded inputs (run on an MI355X; marked gpu).
+
+Tolerances (float32 storage and accumulation, unit roundoff u = 2^-24):
+* Laplacian values: each entry is one float64 product rounded once to float32,
+  so |rel err| <= u; we allow 2u.
+* p(L)X, degree l: every fused step rounds once per output and accumulates
+  d_i float32 products; the polynomial's coefficient mass sum |c_i| ||L||^i
+  (<= 7.4 for the Table 2 rows on [0, 2]) amplifies it, so the relative
+  Frobenius error stays below l * 8 * 4u ~ 3e-5 for l = 16; we check 3e-5
+  relative Frobenius and 2e-4 relative to the max entry elementwise.
+* Gram in float64 of float32 data: products are exact, sums float64: 1e-13.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import grad as ograd
+from oracle import kmeans as okm
+from oracle import laplacian as olap
+from oracle import poly as opoly
+from oracle import solver as osol
+from oracle import walk as owalk
+from paper_2207_14589_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def sped():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2207_14589_amd import sped as s
+    s.lib()
+    return s
+
+
+def mixed_degree_graph(seed=5):
+    """SBM rows plus a hub of degree 9000 (heavy bin) and hubs of degree 300
+    (medium bin), weighted, with repeated edges and self-loops."""
+    n, s, d, _ = synth.sbm_bernoulli([700, 900, 1400], 0.01, 0.0008, seed=seed)
+    n = 12000
+    g = np.random.default_rng(seed)
+    hub_s = np.zeros(9000, dtype=np.int64)
+    hub_d = g.choice(np.arange(1, n), 9000, replace=False)
+    med_s = np.repeat([17, 1200], 300)
+    med_d = g.integers(3000, n, 600)
+    extra_s = g.integers(3000, n, 20000)
+    extra_d = g.integers(3000, n, 20000)
+    src = np.concatenate([s, hub_s, med_s, extra_s, [5, 5, 8]])
+    dst = np.concatenate([d, hub_d, med_d, extra_d, [5, 9, 9]])
+    w = synth.random_weights(src.shape[0], seed + 1).astype(np.float32).astype(np.float64)
+    return n, src, dst, w
+
+
+def dense_from_gpu(L):
+    rowptr, col, val, diag, scale = L.host_csr()
+    import scipy.sparse as sp
+    n = L.n
+    S = sp.csr_matrix((val.astype(np.float64), col, rowptr), shape=(n, n))
+    return sp.diags(diag.astype(np.float64)) - S
+
+
+@pytest.mark.parametrize("kind", ["sym", "combinatorial"])
+@pytest.mark.parametrize("lcc", [False, True])
+def test_laplacian_build(sped, kind, lcc):
+    n, src, dst, w = mixed_degree_graph()
+    # add a separate small component so that lcc matters
+    src = np.concatenate([src, [n - 3, n - 2]])
+    dst = np.concatenate([dst, [n - 2, n - 1]])
+    w = np.concatenate([w, [0.5, 0.25]])
+    _say(f"laplacian kind={kind} lcc={lcc} n={n} m={src.shape[0]}")
+    L = sped.Laplacian(n, src, dst, w, kind=kind, lcc=lcc)
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED if kind == "sym" else olap.COMBINATORIAL, lcc=lcc)
+    assert L.n == ref.n
+    rowptr, col, val, diag, scale = L.host_csr()
+    r_rowptr, r_col, r_w = ref.adjacency()
+    np.testing.assert_array_equal(rowptr, r_rowptr)
+    np.testing.assert_array_equal(col, r_col)
+    np.testing.assert_array_equal(L.old_of_new.cpu().numpy(), ref.old_of_new)
+    Lg = dense_from_gpu(L).tocsr()
+    diff = abs(Lg - ref.L)
+    assert diff.max() <= 2 * U32 * abs(ref.L).max()
+    np.testing.assert_allclose(scale, ref.scale, rtol=2 * U32)
+    assert L.max_degree == int(ref.count_degree.max())
+    assert L.lambda_bound == pytest.approx(ref.lambda_bound, rel=1e-12)
+    rev = L.rev[: L.nnz].cpu().numpy()
+    row_of = np.repeat(np.arange(L.n), np.diff(rowptr))
+    np.testing.assert_array_equal(col[rev], row_of)
+    np.testing.assert_array_equal(rev[rev], np.arange(L.nnz))
+    d = np.diff(rowptr)
+    bins = L.bins[: L.n_medium + L.n_heavy].cpu().numpy()
+    np.testing.assert_array_equal(bins[: L.n_medium], np.nonzero((d > sped.LIGHT_MAX) & (d <= sped.MEDIUM_MAX))[0])
+    np.testing.assert_array_equal(bins[L.n_medium:], np.nonzero(d > sped.MEDIUM_MAX)[0])
+    assert L.n_heavy >= 1 and L.n_medium >= 2
+
+
+def test_laplacian_edge_cases(sped):
+    _say("laplacian empty / self-loops only")
+    L = sped.Laplacian(7, [], [], kind="sym")
+    assert L.n == 7 and L.nnz == 0
+    assert np.all(L.host_csr()[3] == 0) and np.all(L.host_csr()[4] == 0)
+    L2 = sped.Laplacian(4, [1, 2], [1, 2], kind="combinatorial")
+    assert L2.nnz == 0
+    with pytest.raises(sped.SpedError):
+        sped.Laplacian(4, [0, 5], [1, 2])
+    with pytest.raises(sped.SpedError):
+        sped.Laplacian(4, [0, 1], [1, 2], w=[1.0, -1.0])
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+POLYS = [
+    ("limit16-product", lambda s, lam: s.transform("limit", 16, lam), lambda lam: opoly.limit_exp(16)),
+    ("limit16-horner", lambda s, lam: s.transform("limit", 16, lam, product_form=False), lambda lam: opoly.limit_exp(16)),
+    ("taylor_exp9", lambda s, lam: s.transform("taylor_exp", 9, lam), lambda lam: opoly.taylor_exp(9)),
+    ("taylor_log9", lambda s, lam: s.transform("taylor_log", 9, lam), lambda lam: opoly.taylor_log(9, lam)),
+    ("plain", lambda s, lam: s.transform("plain", 1, lam), lambda lam: opoly.plain(lam)),
+]
+
+
+@pytest.mark.parametrize("pname,mk,mkref", POLYS, ids=[p[0] for p in POLYS])
+@pytest.mark.parametrize("k", [32, 7, 64])
+def test_apply_poly_parity(sped, pname, mk, mkref, k):
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"apply_poly {pname} k={k}")
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, k, 3).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Y = sped.apply_poly(L, mk(sped, L.lambda_bound), Xd).cpu().numpy().astype(np.float64)
+    Yr = opoly.apply_terms(ref.L, mkref(ref.lambda_bound), X.astype(np.float64))
+    assert _rel(Y, Yr) < 3e-5
+    assert np.abs(Y - Yr).max() < 2e-4 * np.abs(Yr).max()
+
+
+@pytest.mark.parametrize("xdt,ydt", [("bf16", "f32"), ("f32", "bf16"), ("bf16", "bf16")])
+def test_apply_poly_bf16(sped, xdt, ydt):
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"apply_poly bf16 x={xdt} y={ydt}")
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    k = 64
+    X = torch.from_numpy(synth.gaussian_block(n, k, 4).astype(np.float32))
+    tx = {"bf16": torch.bfloat16, "f32": torch.float32}
+    Xd = X.to(tx[xdt]).cuda()
+    Y = sped.apply_poly(L, sped.transform("limit", 16), Xd, out_dtype=tx[ydt]).float().cpu().numpy()
+    Yr = opoly.apply_terms(ref.L, opoly.limit_exp(16), Xd.float().cpu().numpy().astype(np.float64))
+    tol = 3e-5 + (2.0 ** -8 if ydt == "bf16" else 0.0)
+    assert _rel(Y, Yr) < tol
+
+
+def test_apply_poly_padded_ld_and_tiny(sped):
+    """leading dimension > k, k = 1, and n smaller than one block."""
+    _say("apply_poly padded ld / k=1 / tiny n")
+    n, s, d = synth.path_graph(5)
+    L = sped.Laplacian(n, s, d, kind="combinatorial")
+    ref = olap.laplacian(n, s, d, kind=olap.COMBINATORIAL)
+    big = torch.from_numpy(synth.gaussian_block(n, 12, 1).astype(np.float32)).cuda()
+    X = big[:, 2:7]   # k = 5, ld = 12, offset 2 floats
+    p = sped.transform("taylor_exp", 5, L.lambda_bound)
+    Y = sped.apply_poly(L, p, X).cpu().numpy()
+    Yr = opoly.apply_terms(ref.L, opoly.taylor_exp(5), X.cpu().numpy().astype(np.float64))
+    assert _rel(Y, Yr) < 1e-5
+    X1 = big[:, :1].contiguous()
+    Y1 = sped.apply_poly(L, p, X1).cpu().numpy()
+    assert _rel(Y1, opoly.apply_terms(ref.L, opoly.taylor_exp(5), X1.cpu().numpy().astype(np.float64))) < 1e-5
+
+
+def test_apply_poly_isolated_nodes(sped):
+    _say("apply_poly with isolated nodes")
+    src, dst = [0, 1, 2, 5], [1, 2, 3, 6]
+    L = sped.Laplacian(9, src, dst, kind="sym")
+    ref = olap.laplacian(9, src, dst, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(9, 4, 2).astype(np.float32)
+    Y = sped.apply_poly(L, sped.transform("limit", 8), torch.from_numpy(X).cuda()).cpu().numpy()
+    np.testing.assert_allclose(Y, opoly.apply_terms(ref.L, opoly.limit_exp(8), X.astype(np.float64)), atol=1e-5)
+    np.testing.assert_allclose(Y[[4, 7, 8]], X[[4, 7, 8]], rtol=1e-6)   # zero rows: M = I there
+
+
+@pytest.fixture(scope="module")
+def c2_case(sped):
+    """SBM, 10^6 nodes, 100 blocks, mean degree 20, 5% cross edges (k=32, l=16)."""
+    _say("building the 1e6-node SBM")
+    n, s, d, labels = synth.sbm_from_degrees(1_000_000, 100, 19.0, 1.0, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 32, 2).astype(np.float32)
+    return L, ref, X
+
+
+def test_apply_poly_full_size(sped, c2_case):
+    L, ref, X = c2_case
+    _say("apply_poly limit16 at n=1e6, k=32")
+    Y = sped.apply_poly(L, sped.transform("limit", 16), torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr = opoly.apply_limit_product(ref.L, 16, X.astype(np.float64))
+    assert _rel(Y, Yr) < 3e-5
+    assert np.abs(Y - Yr).max() < 2e-4 * np.abs(Yr).max()
+
+
+def test_stochastic_full_size_sampled_rows(sped, c2_case):
+    L, ref, X = c2_case
+    _say("importance walks at n=1e6, k=32, 8 walks/row, sampled rows")
+    c = opoly.limit_exp(16).coeffs
+    Y = sped.apply_poly_stochastic(L, c, torch.from_numpy(X).cuda(), walks=8, seed=3, counter=1).cpu().numpy()
+    rows = np.random.default_rng(0).choice(L.n, 300, replace=False)
+    rows = np.concatenate([rows, [0, L.n - 1]])
+    Yr = owalk.estimate_importance(ref, c, X.astype(np.float64), 8, seed=3, counter=1, rows=rows)
+    err = np.abs(Y[rows] - Yr)
+    assert err.max() <= 1e-4 * max(1.0, np.abs(Yr).max())
+
+
+@pytest.mark.parametrize("kind", ["sym", "combinatorial"])
+def test_stochastic_importance_same_walks(sped, kind):
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"importance walks parity kind={kind}")
+    L = sped.Laplacian(n, src, dst, w, kind=kind)
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED if kind == "sym" else olap.COMBINATORIAL)
+    X = synth.gaussian_block(n, 16, 5).astype(np.float32)
+    c = np.array([0.9, -0.5, 0.25, -0.1, 0.05]) / (1.0 if kind == "sym" else 100.0)
+    Y = sped.apply_poly_stochastic(L, c, torch.from_numpy(X).cuda(), walks=6, seed=11, counter=4).cpu().numpy()
+    rows = np.concatenate([np.arange(40), [0, 17, 1200], np.arange(n - 40, n)])
+    Yr = owalk.estimate_importance(ref, c, X.astype(np.float64), 6, seed=11, counter=4, rows=rows)
+    scale = np.abs(Yr).max(axis=1, keepdims=True) + 1.0
+    assert (np.abs(Y[rows] - Yr) / scale).max() < 1e-4
+
+
+def test_stochastic_reject_same_walks(sped):
+    _say("rejection walks parity")
+    n, s, d, _ = synth.sbm_bernoulli([60, 80], 0.2, 0.02, seed=2)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 8, 3).astype(np.float32)
+    c = np.array([0.5, -0.5, 0.25, -0.125])
+    N = 200000
+    Y, cnt = sped.apply_poly_stochastic(L, c, torch.from_numpy(X).cuda(), walks=N, seed=9, counter=2,
+                                        sampler="reject", accept_counts=True)
+    Yr, cr = owalk.estimate_reject(ref, c, X.astype(np.float64), N, seed=9, counter=2)
+    np.testing.assert_array_equal(cnt.cpu().numpy(), cr)
+    assert _rel(Y.cpu().numpy(), Yr) < 1e-5
+
+
+def test_stochastic_unbiased(sped):
+    """Mean over many seeds of the GPU importance estimate matches p(L)X."""
+    _say("importance unbiasedness over 64 seeds")
+    n, s, d, _ = synth.sbm_bernoulli([30, 40], 0.3, 0.05, seed=7)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 4, 3).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    c = opoly.limit_exp(8).coeffs
+    est = np.stack([sped.apply_poly_stochastic(L, c, Xd, walks=512, seed=100 + t).cpu().numpy() for t in range(64)])
+    exact = opoly.apply_terms(ref.L, opoly.limit_exp(8), X.astype(np.float64))
+    z = np.abs(est.mean(0) - exact) / (est.std(0, ddof=1) / 8.0 + 1e-12)
+    assert z.max() < 5.0
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_gram_parity(sped, dt):
+    _say(f"gram {dt}")
+    g = np.random.default_rng(1)
+    n = 100_003
+    A = torch.from_numpy(g.standard_normal((n, 20)).astype(np.float32))
+    B = torch.from_numpy(g.standard_normal((n, 36)).astype(np.float32))
+    tdt = torch.float32 if dt == "f32" else torch.bfloat16
+    Ad, Bd = A.to(tdt).cuda(), B.to(tdt).cuda()
+    G = sped.gram(Ad, Bd).cpu().numpy()
+    An = Ad.float().cpu().numpy().astype(np.float64)
+    Bn = Bd.float().cpu().numpy().astype(np.float64)
+    Gr = An.T @ Bn
+    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+    S = sped.gram(Ad).cpu().numpy()
+    np.testing.assert_allclose(S, An.T @ An, rtol=1e-12, atol=1e-12 * n)
+    np.testing.assert_array_equal(S, S.T)
+    G2 = sped.gram(Ad, Bd).cpu().numpy()
+    np.testing.assert_array_equal(G, G2)   # fixed reduction order
+
+
+def test_orthonormalize_and_rr(sped):
+    _say("CholQR2 and Rayleigh-Ritz")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    V = synth.gaussian_block(n, 14, 2).astype(np.float32)
+    Vd = torch.from_numpy(V).cuda()
+    Q = sped.orthonormalize(Vd.clone(), passes=2).cpu().numpy().astype(np.float64)
+    assert np.abs(Q.T @ Q - np.eye(14)).max() < 2e-6
+    assert osol.max_principal_angle(V.astype(np.float64), Q) < 1e-5
+    Qd = torch.from_numpy(Q.astype(np.float32)).cuda()
+    theta, resid = sped.rayleigh_ritz(L, Qd)
+    th_r, Q_r, res_r = osol.rayleigh_ritz(ref.L, Qd.cpu().numpy().astype(np.float64))
+    np.testing.assert_allclose(theta.cpu().numpy(), th_r, rtol=1e-5, atol=1e-6)
+    np.testing.assert_allclose(resid.cpu().numpy(), res_r, rtol=1e-3, atol=1e-5)
+
+
+@pytest.mark.parametrize("poly", ["limit", "plain"])
+def test_bottomk_solve_c1(sped, poly):
+    """SBM n=2000, 10 blocks, k=10: the bottom-10 span within 1e-6 of dense eigh."""
+    _say(f"bottomk solve C1 poly={poly}")
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    k, guard = 10, 4
+    V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 2).astype(np.float32)).cuda()
+    p = sped.transform("limit", 8) if poly == "limit" else None
+    r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=1e-6, max_iters=3000)
+    assert r.converged, r.stats
+    ang = osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64))
+    assert ang <= 1e-6, (ang, r.stats)
+    np.testing.assert_allclose(r.evals[1:], lam[1:], rtol=1e-6)
+    assert abs(r.evals[0]) < 1e-6
+    _say(f"  iters={r.stats['iters']} spmm={r.stats['spmm_count']} angle={ang:.2e}")
+
+
+def test_bottomk_oja_and_stochastic_start(sped):
+    _say("bottomk with Oja step and stochastic first iterations")
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    r = sped.bottomk(L, 10, sped.transform("limit", 8), V0=V0, guard=4, tol=1e-6, max_iters=3000, solver="oja",
+                     eta=1.0)
+    assert r.converged and osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64)) <= 1e-6
+    r2 = sped.bottomk(L, 10, sped.transform("limit", 8), V0=V0, guard=4, tol=1e-6, max_iters=3000,
+                      stochastic_iters=5, walks_per_row=16, seed=5)
+    assert r2.converged and osol.max_principal_angle(U, r2.V.cpu().numpy().astype(np.float64)) <= 1e-6
+
+
+def test_poly_backward_parity(sped):
+    _say("poly backward")
+    n, src, dst, w = mixed_degree_graph()
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    g = np.random.default_rng(3)
+    theta = g.standard_normal(13) * 0.3
+    X = g.standard_normal((n, 10)).astype(np.float32)
+    G = g.standard_normal((n, 10)).astype(np.float32)
+    dth = sped.poly_backward(L, 12, torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda()).cpu().numpy()
+    dth_r, dX_r = ograd.backward(ref.L, theta, X.astype(np.float64), G.astype(np.float64))
+    np.testing.assert_allclose(dth, dth_r, rtol=5e-5, atol=5e-5 * np.abs(dth_r).max())
+
+
+def test_polyapply_autograd(sped):
+    _say("PolyApply forward/backward vs float64 reference")
+    from paper_2207_14589_amd.autograd import poly_apply
+    n, s, d, _ = synth.sbm_bernoulli([150, 150, 200], 0.05, 0.002, seed=4)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    g = np.random.default_rng(2)
+    theta0 = g.standard_normal(13) * 0.2
+    X0 = g.standard_normal((n, 6)).astype(np.float32)
+    G0 = g.standard_normal((n, 6)).astype(np.float32)
+    theta = torch.tensor(theta0, dtype=torch.float64, requires_grad=True)
+    X = torch.from_numpy(X0).cuda().requires_grad_(True)
+    Y = poly_apply(theta, X, L)
+    loss = (Y * torch.from_numpy(G0).cuda()).sum()
+    loss.backward()
+    dth_r, dX_r = ograd.backward(ref.L, theta0, X0.astype(np.float64), G0.astype(np.float64))
+    np.testing.assert_allclose(Y.detach().cpu().numpy(), ograd.forward(ref.L, theta0, X0.astype(np.float64)),
+                               rtol=1e-4, atol=1e-4)
+    np.testing.assert_allclose(theta.grad.numpy(), dth_r, rtol=1e-4, atol=1e-4 * np.abs(dth_r).max())
+    np.testing.assert_allclose(X.grad.cpu().numpy(), dX_r, rtol=1e-4, atol=1e-4 * np.abs(dX_r).max())
+    # finite differences in theta (the loss is linear in theta: exact up to rounding)
+    for j in (0, 5, 12):
+        e = np.zeros(13)
+        e[j] = 0.1
+        lp = float((poly_apply(torch.tensor(theta0 + e), X.detach(), L) * torch.from_numpy(G0).cuda()).sum())
+        lm = float((poly_apply(torch.tensor(theta0 - e), X.detach(), L) * torch.from_numpy(G0).cuda()).sum())
+        assert (lp - lm) / 0.2 == pytest.approx(dth_r[j], rel=1e-3, abs=1e-3 * np.abs(dth_r).max())
+
+
+def test_cluster_embed_parity(sped):
+    _say("k-means from given centres, and with k-means++ seeding")
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    _, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    X = okm.normalize_rows(U)
+    C0 = okm.kmeans_pp(X, 10, seed=3)
+    lab_r, C_r, in_r, it_r = okm.lloyd(X, C0)
+    Vd = torch.from_numpy(U.astype(np.float32)).cuda()
+    lab, C, inertia, iters = sped.cluster_embed(Vd, 10, row_normalize=True, init=C0)
+    Xf = okm.normalize_rows(U.astype(np.float32).astype(np.float64))
+    lab_f, C_f, in_f, it_f = okm.lloyd(Xf, C0)
+    np.testing.assert_array_equal(lab.cpu().numpy(), lab_f)
+    np.testing.assert_allclose(C.cpu().numpy(), C_f, atol=1e-10)
+    assert inertia == pytest.approx(in_f, rel=1e-9, abs=1e-12)
+    lab2, _, _, _ = sped.cluster_embed(Vd, 10, row_normalize=True, seed=7)
+    assert okm.adjusted_rand_index(lab2.cpu().numpy(), labels) > 0.99
+
+
+def test_stream_copy(sped):
+    _say("stream copy")
+    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    sped.stream_copy(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
