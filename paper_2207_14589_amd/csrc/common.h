@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sped.h"
+#include "sped.h"
 
 namespace sped {
 
@@ -164,6 +164,57 @@ struct VecIO<bf16_t, 1> {
   __device__ static void load(const bf16_t *p, float (&o)[1]) { o[0] = bf16_to_f32(*p); }
   __device__ static void store(bf16_t *p, const float (&o)[1]) { *p = f32_to_bf16(o[0]); }
 };
+
+// Streaming (non-temporal) variants: data read or written once per kernel,
+// kept out of the way of the cache lines that gathers re-use.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+template <typename T, int VEC>
+struct VecNT {
+  __device__ static void store(T *p, const float (&o)[VEC]) { VecIO<T, VEC>::store(p, o); }
+};
+template <>
+struct VecNT<float, 4> {
+  __device__ static void store(float *p, const float (&o)[4]) {
+    f32x4_t v = {o[0], o[1], o[2], o[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4_t *>(p));
+  }
+};
+template <>
+struct VecNT<float, 2> {
+  __device__ static void store(float *p, const float (&o)[2]) {
+    f32x2_t v = {o[0], o[1]};
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x2_t *>(p));
+  }
+};
+template <>
+struct VecNT<bf16_t, 4> {
+  __device__ static void store(bf16_t *p, const float (&o)[4]) {
+    u32x2_t v = {uint32_t(f32_to_bf16(o[0])) | (uint32_t(f32_to_bf16(o[1])) << 16),
+                 uint32_t(f32_to_bf16(o[2])) | (uint32_t(f32_to_bf16(o[3])) << 16)};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2_t *>(p));
+  }
+};
+
+template <typename T>
+__device__ inline T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+// Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
+// maps hardware block b to logical block (b % 8) * per + b / 8 so that each
+// XCD walks one contiguous stretch of logical blocks (rows), keeping the rows
+// its neighbourhoods re-read in its own L2.  The grid is padded to 8 * per;
+// logical ids >= nb have nothing to do.
+constexpr int kXcds = 8;
+__device__ inline int64_t xcd_logical_block(int64_t nb) {
+  const int64_t per = gridDim.x / kXcds;
+  const int64_t b = blockIdx.x;
+  return (b % kXcds) * per + b / kXcds;
+}
+inline int64_t xcd_padded_grid(int64_t nb) { return (nb + kXcds - 1) / kXcds * kXcds; }
 
 // Largest element vector width (4, 2 or 1) that divides k and every leading
 // dimension and keeps every base pointer aligned.

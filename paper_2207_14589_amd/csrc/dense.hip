@@ -98,49 +98,62 @@ __device__ inline int rr_player(int pos, int round, int m) {
 __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__restrict__ H,
                                                         double *__restrict__ theta, double *__restrict__ S,
                                                         int *__restrict__ flags) {
+  // LDS rows are padded to ld = k + 1 doubles so that walking down a column
+  // (the column half of a rotation) touches different banks.
   extern __shared__ double sm[];
+  const int ld = k + 1;
   double *A = sm;
-  double *V = sm + k * k;
+  double *V = sm + k * ld;
   __shared__ double cs[kMaxDense / 2 + 1][2];
   __shared__ int pp[kMaxDense / 2 + 1][2];
+  __shared__ double red[kBlock / 64];
   __shared__ double off2, tot2;
   __shared__ int perm[kMaxDense];
   const int m = k + (k & 1);  // players, with a bye when k is odd
+  const int npairs = m / 2;
   for (int i = threadIdx.x; i < k * k; i += kBlock) {
     int r = i / k, c = i - r * k;
-    A[i] = 0.5 * (H[r * k + c] + H[c * k + r]);
-    V[i] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int i = 0; i < k * k; ++i) t += A[i] * A[i];
-    tot2 = t;
+    A[r * ld + c] = 0.5 * (H[r * k + c] + H[c * k + r]);
+    V[r * ld + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
   int sweep = 0;
   for (; sweep < 60 && k > 1; ++sweep) {
-    if (threadIdx.x == 0) {
-      double o = 0.0;
-      for (int r = 0; r < k; ++r)
-        for (int c = r + 1; c < k; ++c) o += 2.0 * A[r * k + c] * A[r * k + c];
-      off2 = o;
+    // squared norms of the off-diagonal part and of the whole matrix
+    double o = 0.0, t = 0.0;
+    for (int i = threadIdx.x; i < k * k; i += kBlock) {
+      int r = i / k, c = i - r * k;
+      double x = A[r * ld + c];
+      t += x * x;
+      if (r != c) o += x * x;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+      o += __shfl_xor(o, off, 64);
+      t += __shfl_xor(t, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = o;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      off2 = red[0] + red[1] + red[2] + red[3];
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) tot2 = red[0] + red[1] + red[2] + red[3];
     __syncthreads();
     if (!(off2 > 1e-30 * tot2) || !(tot2 > 0.0)) break;
     for (int round = 0; round < m - 1; ++round) {
-      const int npairs = m / 2;
       for (int q = threadIdx.x; q < npairs; q += kBlock) {
         int a = rr_player(q, round, m), b = rr_player(m - 1 - q, round, m);
         int p = a < b ? a : b, r = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (r < k) {
-          double apq = A[p * k + r];
+          double apq = A[p * ld + r];
           if (apq != 0.0) {
-            double tau = (A[r * k + r] - A[p * k + p]) / (2.0 * apq);
-            double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            double tau = (A[r * ld + r] - A[p * ld + p]) / (2.0 * apq);
+            double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
           }
         }
         pp[q][0] = p;
@@ -149,29 +162,29 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__r
         cs[q][1] = s;
       }
       __syncthreads();
-      // columns: A <- A J, V <- V J
+      // columns: A <- A J, V <- V J  (consecutive threads walk down a column)
       for (int i = threadIdx.x; i < k * npairs; i += kBlock) {
-        int row = i / npairs, q = i - row * npairs;
+        int q = i / k, row = i - q * k;
         int p = pp[q][0], r = pp[q][1];
         if (r < 0) continue;
         double c = cs[q][0], s = cs[q][1];
-        double ap = A[row * k + p], ar = A[row * k + r];
-        A[row * k + p] = c * ap - s * ar;
-        A[row * k + r] = s * ap + c * ar;
-        double vp = V[row * k + p], vr = V[row * k + r];
-        V[row * k + p] = c * vp - s * vr;
-        V[row * k + r] = s * vp + c * vr;
+        double ap = A[row * ld + p], ar = A[row * ld + r];
+        A[row * ld + p] = c * ap - s * ar;
+        A[row * ld + r] = s * ap + c * ar;
+        double vp = V[row * ld + p], vr = V[row * ld + r];
+        V[row * ld + p] = c * vp - s * vr;
+        V[row * ld + r] = s * vp + c * vr;
       }
       __syncthreads();
-      // rows: A <- J^T A
+      // rows: A <- J^T A  (consecutive threads walk along a row)
       for (int i = threadIdx.x; i < k * npairs; i += kBlock) {
-        int col = i / npairs, q = i - col * npairs;
+        int q = i / k, col = i - q * k;
         int p = pp[q][0], r = pp[q][1];
         if (r < 0) continue;
         double c = cs[q][0], s = cs[q][1];
-        double ap = A[p * k + col], ar = A[r * k + col];
-        A[p * k + col] = c * ap - s * ar;
-        A[r * k + col] = s * ap + c * ar;
+        double ap = A[p * ld + col], ar = A[r * ld + col];
+        A[p * ld + col] = c * ap - s * ar;
+        A[r * ld + col] = s * ap + c * ar;
       }
       __syncthreads();
     }
@@ -181,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__r
     for (int i = 0; i < k; ++i) {
       int best = i;
       for (int j = i + 1; j < k; ++j)
-        if (A[perm[j] * k + perm[j]] < A[perm[best] * k + perm[best]]) best = j;
+        if (A[perm[j] * ld + perm[j]] < A[perm[best] * ld + perm[best]]) best = j;
       int t = perm[i];
       perm[i] = perm[best];
       perm[best] = t;
@@ -189,10 +202,10 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__r
     if (sweep >= 60) atomicAdd(flags + 2, 1);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += kBlock) theta[i] = A[perm[i] * k + perm[i]];
+  for (int i = threadIdx.x; i < k; i += kBlock) theta[i] = A[perm[i] * ld + perm[i]];
   for (int i = threadIdx.x; i < k * k; i += kBlock) {
     int r = i / k, c = i - r * k;
-    S[i] = V[r * k + perm[c]];
+    S[i] = V[r * ld + perm[c]];
   }
 }
 
@@ -211,7 +224,7 @@ sped_status launch_chol_inv(int k, const double *G, double *T, double *R_out, in
 
 sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s) {
   if (k < 1 || k > kMaxDense) return fail(SPED_E_UNSUPPORTED, "dense width outside [1, 96]");
-  size_t shm = size_t(2) * k * k * sizeof(double);
+  size_t shm = size_t(2) * k * (k + 1) * sizeof(double);
   SPED_TRY(set_max_lds(jacobi_kernel, shm));
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBlock), shm, s, k, H, theta, S, flags);
   SPED_CHECK_HIP(hipGetLastError());

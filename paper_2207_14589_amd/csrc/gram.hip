@@ -12,7 +12,6 @@ namespace sped {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kChunk = 64;        // rows staged in LDS per round
 constexpr int kMaxK = 128;        // ka, kb <= kMaxK
 constexpr int kGramBlocks = 512;
 
@@ -25,28 +24,30 @@ __device__ inline double load_as_double<float>(const float *p) { return double(*
 template <>
 __device__ inline double load_as_double<bf16_t>(const bf16_t *p) { return double(bf16_to_f32(*p)); }
 
-// Tiles of the ka x kb output are assigned round-robin to the 4 waves; a wave
-// holds at most MAXT tiles.  With SYM (A == B) only tiles p <= q are formed.
-template <typename T, int MAXT, bool SYM>
+// Each wavefront streams its rows straight from global memory (16 rows per
+// round: lane (li, lk) reads element [row + 4u + lk][16 tile + li], u = 0..3)
+// into float64 MFMA operands; no LDS and no barriers.  With few output tiles
+// (ROWSPLIT) every wavefront forms all tiles over its own quarter of the
+// block's rows and writes its own partial; otherwise the tiles are dealt
+// round-robin to the 4 wavefronts, which all read the block's rows (their
+// shared lines come from L1) and write disjoint tiles of one partial.  With
+// SYM (A == B) only tiles p <= q are formed and mirrored on output.
+template <typename T, int MAXT, bool SYM, bool ROWSPLIT>
 __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, const T *__restrict__ A,
                                                       int64_t lda, const T *__restrict__ B, int64_t ldb,
-                                                      double *__restrict__ partials) {
-  extern __shared__ double lds[];
+                                                      int64_t rows_per_block, double *__restrict__ partials) {
+  constexpr int KU = MAXT <= 4 ? 4 : 1;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  const int pa = TA * 16 + 1, pb = TB * 16 + 1;  // padded LDS row strides
-  double *sA = lds;
-  double *sB = SYM ? lds : lds + kChunk * pa;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
 
-  // tile list of this wave
   int tp[MAXT], tq[MAXT];
   int nt = 0;
   {
     int idx = 0;
     for (int p = 0; p < TA; ++p)
       for (int q = SYM ? p : 0; q < TB; ++q) {
-        if (idx % 4 == wave && nt < MAXT) {
+        if ((ROWSPLIT || idx % 4 == wave) && nt < MAXT) {
           tp[nt] = p;
           tq[nt] = q;
           ++nt;
@@ -58,34 +59,31 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
 
-  const int64_t nchunks = (n + kChunk - 1) / kChunk;
-  for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int64_t r0 = ch * kChunk;
-    __syncthreads();
-    for (int i = threadIdx.x; i < kChunk * TA * 16; i += kBlock) {
-      int r = i / (TA * 16), c = i - r * (TA * 16);
-      int64_t gr = r0 + r;
-      sA[r * pa + c] = (gr < n && c < ka) ? load_as_double(A + gr * lda + c) : 0.0;
-    }
-    if (!SYM)
-      for (int i = threadIdx.x; i < kChunk * TB * 16; i += kBlock) {
-        int r = i / (TB * 16), c = i - r * (TB * 16);
-        int64_t gr = r0 + r;
-        sB[r * pb + c] = (gr < n && c < kb) ? load_as_double(B + gr * ldb + c) : 0.0;
-      }
-    __syncthreads();
-    const int sbs = SYM ? pa : pb;
-#pragma unroll 4
-    for (int kk = 0; kk < kChunk; kk += 4) {
+  const int64_t r_begin = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t r_end = min(n, r_begin + rows_per_block);
+  const int64_t first = r_begin + (ROWSPLIT ? 4 * KU * wave : 0);
+  const int64_t stride = ROWSPLIT ? 16 * KU : 4 * KU;
+  for (int64_t r = first; r < r_end; r += stride) {
+    double a[KU][MAXT], b[KU][MAXT];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t row = r + 4 * u + lk;
+      const bool rok = row < r_end;
 #pragma unroll
       for (int t = 0; t < MAXT; ++t) {
-        if (t < nt) {
-          double a = sA[(kk + lk) * pa + tp[t] * 16 + li];
-          double b = sB[(kk + lk) * sbs + tq[t] * 16 + li];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        a[u][t] = b[u][t] = 0.0;
+        if (t < nt && rok) {
+          const int ca = tp[t] * 16 + li, cb = tq[t] * 16 + li;
+          if (ca < ka) a[u][t] = load_as_double(A + row * lda + ca);
+          if (cb < kb) b[u][t] = load_as_double(B + row * ldb + cb);
         }
       }
     }
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t)
+        if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[u][t], acc[t], 0, 0, 0);
   }
   // Which (row, column) of the 16x16 tile each of this lane's 4 accumulator
   // slots holds is read off the matrix core itself: with A[i][0] = i,
@@ -97,7 +95,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
                                                                zero4, 0, 0, 0);
   const double4_t colid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? 1.0 : 0.0, lk == 0 ? double(li) : 0.0,
                                                                zero4, 0, 0, 0);
-  double *out = partials + int64_t(blockIdx.x) * ka * kb;
+  const int64_t slot = ROWSPLIT ? int64_t(blockIdx.x) * 4 + wave : int64_t(blockIdx.x);
+  double *out = partials + slot * ka * kb;
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) {
     if (t < nt) {
@@ -112,13 +111,108 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
   }
 }
 
+// Narrow Gram (both widths <= 32): 16 wavefronts per block, each streams its
+// own interleaved 16-row chunks of the block's rows and forms all TA x TB tiles
+// (operand fragments loaded once per row group and reused across tiles).  The
+// wavefronts then add their tiles into one LDS copy in wavefront order (fixed
+// order: deterministic) and the block writes one partial.
+constexpr int kNarrowBlock = 1024;
+template <typename T, int TA, int TB, bool SYM>
+__global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, int ka, int kb,
+                                                                   const T *__restrict__ A, int64_t lda,
+                                                                   const T *__restrict__ B, int64_t ldb,
+                                                                   int64_t rows_per_block,
+                                                                   double *__restrict__ partials) {
+  constexpr int KU = 4;
+  constexpr int NW = kNarrowBlock / 64;
+  __shared__ double red[TA * 16 * TB * 16];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  double4_t acc[TA][TB];
+#pragma unroll
+  for (int p = 0; p < TA; ++p)
+#pragma unroll
+    for (int q = 0; q < TB; ++q) acc[p][q] = double4_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t r_end = min(n, r_begin + rows_per_block);
+  for (int64_t r = r_begin + 4 * KU * wave; r < r_end; r += 4 * KU * NW) {
+    double fa[KU][TA], fb[KU][TB];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t row = r + 4 * u + lk;
+      const bool rok = row < r_end;
+#pragma unroll
+      for (int p = 0; p < TA; ++p) {
+        const int c = p * 16 + li;
+        fa[u][p] = (rok && c < ka) ? load_as_double(A + row * lda + c) : 0.0;
+      }
+      if (!SYM) {
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+          const int c = q * 16 + li;
+          fb[u][q] = (rok && c < kb) ? load_as_double(B + row * ldb + c) : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int p = 0; p < TA; ++p)
+#pragma unroll
+        for (int q = 0; q < TB; ++q)
+          if (!SYM || p <= q)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u][p], SYM ? fa[u][q] : fb[u][q], acc[p][q], 0, 0, 0);
+  }
+  const double4_t zero4 = double4_t{0.0, 0.0, 0.0, 0.0};
+  const double4_t rowid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? double(li) : 0.0, lk == 0 ? 1.0 : 0.0,
+                                                               zero4, 0, 0, 0);
+  const double4_t colid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? 1.0 : 0.0, lk == 0 ? double(li) : 0.0,
+                                                               zero4, 0, 0, 0);
+  constexpr int W = TB * 16;
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int p = 0; p < TA; ++p)
+#pragma unroll
+        for (int q = 0; q < TB; ++q)
+          if (!SYM || p <= q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = p * 16 + int(rowid[r]), j = q * 16 + int(colid[r]);
+              red[i * W + j] = (w == 0 ? 0.0 : red[i * W + j]) + acc[p][q][r];
+            }
+    }
+    __syncthreads();
+  }
+  double *out = partials + int64_t(blockIdx.x) * ka * kb;
+  for (int idx = threadIdx.x; idx < ka * kb; idx += kNarrowBlock) {
+    const int i = idx / kb, j = idx - i * kb;
+    const int pi = i / 16, qj = j / 16;
+    out[idx] = (SYM && pi > qj) ? red[j * W + i] : red[i * W + j];
+  }
+}
+
+// One wavefront per output entry: lane l adds partials l, l + 64, ... and the
+// lanes meet in a fixed xor tree (deterministic).
 __global__ __launch_bounds__(kBlock) void sum_partials_kernel(const double *__restrict__ partials, int nparts,
-                                                               int64_t count, double *__restrict__ out) {
-  int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= count) return;
+                                                               int64_t count, double *__restrict__ out,
+                                                               int take_sqrt) {
+  const int64_t i = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= count) return;  // uniform per wavefront
   double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * count + i];
-  out[i] = s;
+  for (int p = lane; p < nparts; p += 64) s += partials[int64_t(p) * count + i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[i] = take_sqrt ? sqrt(s) : s;
+}
+
+sped_status launch_sum_partials(const double *partials, int nparts, int64_t count, double *out, bool take_sqrt,
+                                hipStream_t s) {
+  const int64_t blocks = (count + kBlock / 64 - 1) / (kBlock / 64);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, partials, nparts, count, out,
+                     int(take_sqrt));
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
 }
 
 // O[r, :] = X[r, :] T, T kin x kout float64 -> float in LDS.
@@ -177,45 +271,75 @@ __global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, int k, const f
   }
 }
 
-__global__ void sqrt_sum_kernel(const double *__restrict__ partials, int nparts, int k, double *__restrict__ out) {
-  int c = threadIdx.x;
-  if (c >= k) return;
-  double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += partials[int64_t(p) * k + c];
-  out[c] = sqrt(s);
-}
 
 constexpr int kResidBlocks = 512;
 
-template <typename T, int MAXT, bool SYM>
-sped_status launch_gram_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
-                          double *partials, int nblocks, hipStream_t s) {
+struct GramPlan {
+  int nblocks, nparts, maxt;
+  bool rowsplit, narrow;
+  int64_t rows_per_block;
+};
+
+GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  size_t shm = size_t(kChunk) * (TA * 16 + 1) * sizeof(double);
-  if (!SYM) shm += size_t(kChunk) * (TB * 16 + 1) * sizeof(double);
-  SPED_TRY(set_max_lds(gram_kernel<T, MAXT, SYM>, shm));
-  hipLaunchKernelGGL((gram_kernel<T, MAXT, SYM>), dim3(nblocks), dim3(kBlock), shm, s, n, ka, kb,
-                     static_cast<const T *>(A), lda, static_cast<const T *>(B), ldb, partials);
+  const int tiles = sym ? TA * (TA + 1) / 2 : TA * TB;
+  GramPlan p;
+  p.rowsplit = tiles <= 4;
+  const int per_wave = p.rowsplit ? tiles : (tiles + 3) / 4;
+  p.maxt = per_wave <= 1 ? 1 : per_wave <= 2 ? 2 : per_wave <= 4 ? 4 : per_wave <= 8 ? 8 : 16;
+  int64_t blocks = (n + 255) / 256;
+  p.nblocks = int(blocks < kGramBlocks ? (blocks > 0 ? blocks : 1) : kGramBlocks);
+  int64_t rpb = (n + p.nblocks - 1) / p.nblocks;
+  p.rows_per_block = (rpb + 63) / 64 * 64;
+  p.nparts = p.rowsplit ? 4 * p.nblocks : p.nblocks;
+  p.narrow = TA <= 2 && TB <= 2;
+  if (p.narrow) {
+    int64_t nb = (n + 1023) / 1024;
+    p.nblocks = int(nb < kGramBlocks ? (nb > 0 ? nb : 1) : kGramBlocks);
+    int64_t r = (n + p.nblocks - 1) / p.nblocks;
+    p.rows_per_block = (r + 255) / 256 * 256;
+    p.nparts = p.nblocks;
+  }
+  return p;
+}
+
+template <typename T, int MAXT, bool SYM, bool RS>
+sped_status launch_gram_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
+                          double *partials, const GramPlan &p, hipStream_t s) {
+  hipLaunchKernelGGL((gram_kernel<T, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb,
+                     static_cast<const T *>(A), lda, static_cast<const T *>(B), ldb, p.rows_per_block, partials);
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+template <typename T, int TA, int TB, bool SYM>
+sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
+                                 double *partials, const GramPlan &p, hipStream_t s) {
+  hipLaunchKernelGGL((gram_narrow_kernel<T, TA, TB, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb,
+                     static_cast<const T *>(A), lda, static_cast<const T *>(B), ldb, p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
 
 template <typename T, bool SYM>
 sped_status launch_gram_maxt(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B,
-                             int64_t ldb, double *partials, int nblocks, hipStream_t s) {
-  const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  int tiles = SYM ? TA * (TA + 1) / 2 : TA * TB;
-  int per_wave = (tiles + 3) / 4;
-  if (per_wave <= 1) return launch_gram_t<T, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, nblocks, s);
-  if (per_wave <= 2) return launch_gram_t<T, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, nblocks, s);
-  if (per_wave <= 4) return launch_gram_t<T, 4, SYM>(n, ka, kb, A, lda, B, ldb, partials, nblocks, s);
-  if (per_wave <= 8) return launch_gram_t<T, 8, SYM>(n, ka, kb, A, lda, B, ldb, partials, nblocks, s);
-  return launch_gram_t<T, 16, SYM>(n, ka, kb, A, lda, B, ldb, partials, nblocks, s);
-}
-
-int gram_blocks(int64_t n) {
-  int64_t chunks = (n + kChunk - 1) / kChunk;
-  return int(chunks < kGramBlocks ? (chunks > 0 ? chunks : 1) : kGramBlocks);
+                             int64_t ldb, double *partials, const GramPlan &p, hipStream_t s) {
+  if (p.narrow) {
+    const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
+    if (TA == 1 && TB == 1) return launch_gram_narrow_t<T, 1, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (TA == 1 && TB == 2) return launch_gram_narrow_t<T, 1, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (TA == 2 && TB == 1) return launch_gram_narrow_t<T, 2, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    return launch_gram_narrow_t<T, 2, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  }
+  if (p.rowsplit) {
+    if (p.maxt <= 1) return launch_gram_t<T, 1, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (p.maxt <= 2) return launch_gram_t<T, 2, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    return launch_gram_t<T, 4, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  }
+  if (p.maxt <= 2) return launch_gram_t<T, 2, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  if (p.maxt <= 4) return launch_gram_t<T, 4, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  if (p.maxt <= 8) return launch_gram_t<T, 8, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  return launch_gram_t<T, 16, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
 }
 
 template <typename TX, typename TO>
@@ -245,28 +369,28 @@ sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t l
 
 }  // namespace
 
-size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb) { return size_t(gram_blocks(n)) * ka * kb; }
+size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb) {
+  // the larger of the symmetric and general plans
+  GramPlan a = gram_plan(n, int(ka), int(kb), false), b = gram_plan(n, int(ka), int(kb), ka == kb);
+  return size_t(a.nparts > b.nparts ? a.nparts : b.nparts) * ka * kb;
+}
 
 sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
                         int dt, double *G, double *partials, hipStream_t s) {
   if (ka < 1 || kb < 1 || ka > kMaxK || kb > kMaxK) return fail(SPED_E_UNSUPPORTED, "gram width outside [1, 128]");
-  const int nb = gram_blocks(n);
   const bool sym = (A == B) && (lda == ldb) && (ka == kb);
+  const GramPlan plan = gram_plan(n, ka, kb, sym);
   sped_status st;
   if (dt == SPED_F32)
-    st = sym ? launch_gram_maxt<float, true>(n, ka, kb, A, lda, B, ldb, partials, nb, s)
-             : launch_gram_maxt<float, false>(n, ka, kb, A, lda, B, ldb, partials, nb, s);
+    st = sym ? launch_gram_maxt<float, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
+             : launch_gram_maxt<float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else if (dt == SPED_BF16)
-    st = sym ? launch_gram_maxt<bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, nb, s)
-             : launch_gram_maxt<bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, nb, s);
+    st = sym ? launch_gram_maxt<bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
+             : launch_gram_maxt<bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else
     return fail(SPED_E_UNSUPPORTED, "gram dtype");
   if (st != SPED_OK) return st;
-  int64_t count = int64_t(ka) * kb;
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(unsigned((count + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     partials, nb, count, G);
-  SPED_CHECK_HIP(hipGetLastError());
-  return SPED_OK;
+  return launch_sum_partials(partials, plan.nparts, int64_t(ka) * kb, G, false, s);
 }
 
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
@@ -286,9 +410,7 @@ sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const fl
   if (k > kBlock) return fail(SPED_E_UNSUPPORTED, "resid width > 256");
   hipLaunchKernelGGL(resid_kernel, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz, Q, ldq, theta, partials);
   SPED_CHECK_HIP(hipGetLastError());
-  hipLaunchKernelGGL(sqrt_sum_kernel, dim3(1), dim3(kBlock), 0, s, partials, kResidBlocks, k, resid);
-  SPED_CHECK_HIP(hipGetLastError());
-  return SPED_OK;
+  return launch_sum_partials(partials, kResidBlocks, k, resid, true, s);
 }
 
 }  // namespace sped

@@ -13,8 +13,9 @@
 // Each lane owns VEC consecutive columns; G = next_pow2(k / VEC) lanes cover
 // a row of the block (columns beyond 64 VEC are tiled over blockIdx.y).  The
 // G lanes of a group load G consecutive (col, val) pairs with one coalesced
-// access and broadcast them by shuffle, then gather 4 neighbour rows at a time
-// so several row gathers are in flight per lane.
+// access (the next chunk's pairs are fetched while the current chunk's rows are
+// in flight), broadcast them by shuffle, and issue 8 neighbour-row gathers
+// before consuming any, so each lane keeps 8 row gathers in flight.
 #include <type_traits>
 
 #include "common.h"
@@ -37,45 +38,50 @@ struct Step {
                                 const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end,
                                 int G, int lig, int first, int stride, int c0, bool col_ok,
                                 float (&acc)[VEC]) {
-    for (int64_t p = beg + int64_t(first) * G; p < end; p += int64_t(stride) * G) {
-      int cnt = int(min<int64_t>(G, end - p));
-      int32_t myc = 0;
-      float myv = 0.f;
-      if (lig < cnt) {
-        myc = col[p + lig];
-        myv = val[p + lig];
+    int64_t p = beg + int64_t(first) * G;
+    if (p >= end) return;
+    // the (col, val) chunk for the next round is loaded while this round's
+    // neighbour rows are in flight
+    int32_t myc = 0;
+    float myv = 0.f;
+    if (p + lig < end) {
+      myc = ld_stream(col + p + lig);
+      myv = ld_stream(val + p + lig);
+    }
+    for (; p < end; p += int64_t(stride) * G) {
+      const int cnt = int(min<int64_t>(G, end - p));
+      const int64_t pn = p + int64_t(stride) * G;
+      int32_t nc = 0;
+      float nv = 0.f;
+      if (pn + lig < end) {
+        nc = ld_stream(col + pn + lig);
+        nv = ld_stream(val + pn + lig);
       }
-      int t = 0;
-      for (; t + 4 <= cnt; t += 4) {
-        int32_t j0 = __shfl(myc, t, G), j1 = __shfl(myc, t + 1, G);
-        int32_t j2 = __shfl(myc, t + 2, G), j3 = __shfl(myc, t + 3, G);
-        float s0 = __shfl(myv, t, G), s1 = __shfl(myv, t + 1, G);
-        float s2 = __shfl(myv, t + 2, G), s3 = __shfl(myv, t + 3, G);
-        if (col_ok) {
-          float u0[VEC], u1[VEC], u2[VEC], u3[VEC];
-          VecIO<TU, VEC>::load(U + int64_t(j0) * ldu + c0, u0);
-          VecIO<TU, VEC>::load(U + int64_t(j1) * ldu + c0, u1);
-          VecIO<TU, VEC>::load(U + int64_t(j2) * ldu + c0, u2);
-          VecIO<TU, VEC>::load(U + int64_t(j3) * ldu + c0, u3);
+      for (int t = 0; t < cnt; t += 8) {
+        int32_t j[8];
+        float sv[8];
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) {
-            acc[v] = fmaf(s0, u0[v], acc[v]);
-            acc[v] = fmaf(s1, u1[v], acc[v]);
-            acc[v] = fmaf(s2, u2[v], acc[v]);
-            acc[v] = fmaf(s3, u3[v], acc[v]);
+        for (int u = 0; u < 8; ++u) {
+          j[u] = __shfl(myc, (t + u) & (G - 1), G);
+          sv[u] = (t + u < cnt) ? __shfl(myv, (t + u) & (G - 1), G) : 0.f;
+        }
+        if (col_ok) {
+          float x[8][VEC];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t + u < cnt) VecIO<TU, VEC>::load(U + int64_t(j[u]) * ldu + c0, x[u]);
+            else
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) x[u][v] = 0.f;
           }
-        }
-      }
-      for (; t < cnt; ++t) {
-        int32_t j = __shfl(myc, t, G);
-        float s = __shfl(myv, t, G);
-        if (col_ok) {
-          float u[VEC];
-          VecIO<TU, VEC>::load(U + int64_t(j) * ldu + c0, u);
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(s, u[v], acc[v]);
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(sv[u], x[u][v], acc[v]);
         }
       }
+      myc = nc;
+      myv = nv;
     }
   }
 
@@ -96,7 +102,7 @@ struct Step {
 #pragma unroll
       for (int v = 0; v < VEC; ++v) o[v] = fmaf(cf.g, x[v], o[v]);
     }
-    VecIO<TO, VEC>::store(O + row * ldo + c0, o);
+    VecNT<TO, VEC>::store(O + row * ldo + c0, o);
     double d = 0.0;
     if (DOT) {
       float w[VEC];
@@ -122,14 +128,16 @@ __device__ inline double block_sum_double(double v, double *lds) {
 
 template <typename TU, typename TV, typename TO, int VEC, bool DOT>
 __global__ __launch_bounds__(kBlock) void spmm_light(
-    int64_t n, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    int64_t n, int64_t nb, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
     const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
     int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
   using S = Step<TU, TV, TO, VEC, DOT>;
+  const int64_t lb = xcd_logical_block(nb);
+  if (lb >= nb) return;  // padding block (uniform over the block)
   const int lig = threadIdx.x & (G - 1);
   const int grp = threadIdx.x >> lgG;
-  const int64_t row = int64_t(blockIdx.x) * (kBlock >> lgG) + grp;
+  const int64_t row = lb * (kBlock >> lgG) + grp;
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   const bool col_ok = c0 < k;
   double dsum = 0.0;
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
   if (DOT) {
     __shared__ double red[kBlock / 64];
     double t = block_sum_double(dsum, red);
-    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
+    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * nb + lb] = t;
   }
 }
 
@@ -267,8 +275,8 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
   TO *O = static_cast<TO *>(a.O);
   double *part = a.dot_partials;
   if (g.light_blocks > 0) {
-    const dim3 grid = dim3(unsigned(g.light_blocks), unsigned(g.ytiles));
-    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n, int(k),
+    const dim3 grid = dim3(unsigned(xcd_padded_grid(g.light_blocks)), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n, g.light_blocks, int(k),
                        g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
                        cf, a.dotw, a.lddw, part);
     SPED_CHECK_HIP(hipGetLastError());

@@ -12,12 +12,13 @@
 // entry t of row a (this includes e itself, the self-loop of H), otherwise
 // entry t - d_a of row b with b's copy of e (position rev[p]) skipped.
 //
-// importance sampler: one 64-lane wavefront per output row, split into lane
-// groups that each run walks of that row; the walk weight
+// importance sampler: one lane group per output row; each lane of the group
+// drives its own walk of that row and the group gathers X rows together; the
+// walk weight
 //   omega_1 = d_r h(e_1, r),   omega_{i+1} = omega_i (x_{e_i}^T x_{e_{i+1}}) deg_H(e_i)
 // is alpha_c (x_{e_1})_r / q(c) for the proposal q, so each prefix adds
-// c_i omega_i (x_{e_i}^T X) to row r; the groups' sums meet by xor shuffles and
-// one store writes the row.  No atomics: the result is deterministic.
+// c_i omega_i (x_{e_i}^T X) to row r; one store writes the row.  No atomics:
+// the result is deterministic.
 //
 // rejection sampler: lane groups run trials; e_1 is uniform over the stored
 // entries (each edge twice), prefix i is kept with probability
@@ -112,71 +113,79 @@ __device__ inline double move(const Graph &g, Edge &e, uint32_t t, uint32_t *deg
   return dot;
 }
 
+// One group of G lanes owns output row r.  Lane j of the group drives the
+// control path (random draws, index loads, weights) of walks j, j + G, ...
+// so G walks advance in parallel; after each step the group visits those
+// walks one by one, every lane gathering its VEC columns of the two rows of
+// the walk's current edge, and accumulates into the row's sum.  All walks of a
+// row meet in the same registers: one store per row, no atomics.
 template <typename TX, typename TY, int VEC>
 __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
     int64_t n, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
     TY *__restrict__ Y, int64_t ldy, int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, Coefs cf) {
-  const int lane = threadIdx.x & 63;
-  const int lig = lane & (G - 1);
-  const int sub = lane >> lgG;
-  const int nsub = 64 >> lgG;
-  const int64_t r = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lig = threadIdx.x & (G - 1);
+  const int64_t r = int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG);
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   const bool col_ok = c0 < k;
-  if (r >= n) return;  // whole wavefront exits together
+  const bool row_ok = r < n;
   float acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-  const int64_t r0 = g.rowptr[r], r1 = g.rowptr[r + 1];
+  int64_t r0 = 0, r1 = 0;
+  float sr = 0.f;
+  if (row_ok) {
+    r0 = g.rowptr[r];
+    r1 = g.rowptr[r + 1];
+    sr = g.scale[r];
+  }
   const int64_t dr = r1 - r0;
+  // every lane of a group sees the same dr, so the loops below are uniform per group
   if (dr > 0) {
-    const float sr = g.scale[r];
-    for (int64_t w = sub; w < walks; w += nsub) {
+    for (int64_t wbase = 0; wbase < walks; wbase += G) {
+      const int64_t w = wbase + lig;
+      const bool live = w < walks;
+      const int nlive = int(min<int64_t>(G, walks - wbase));
       Edge e;
-      uint32_t t0 = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 0u, uint32_t(dr));
-      e.p = r0 + t0;
-      e.a = int32_t(r); e.a0 = r0; e.a1 = r1; e.sa = sr;
-      e.b = g.col[e.p];
-      e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
-      e.sb = g.scale[e.b];
-      edge_entries(e, g.val[e.p]);
-      double omega = double(dr) * e.ha;
-      float xa[VEC], xb[VEC];
-      if (col_ok) {
-        VecIO<TX, VEC>::load(X + int64_t(e.a) * ldx + c0, xa);
-        VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
+      double omega = 0.0;
+      if (live) {
+        uint32_t t0 = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 0u, uint32_t(dr));
+        e.p = r0 + t0;
+        e.a = int32_t(r); e.a0 = r0; e.a1 = r1; e.sa = sr;
+        e.b = g.col[e.p];
+        e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
+        e.sb = g.scale[e.b];
+        edge_entries(e, g.val[e.p]);
+        omega = double(dr) * e.ha;
+      } else {
+        e.a = e.b = int32_t(r);
+        e.ha = e.hb = 0.0;
       }
       for (int i = 1; i <= ell; ++i) {
-        if (i > 1) {
-          const int32_t olda = e.a;
-          const int32_t oldb = e.b;
+        if (i > 1 && live) {
           uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
           uint32_t t = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(i - 1), bound);
           uint32_t degH;
           double dot = move(g, e, t, &degH);
           omega = omega * dot * double(degH);
-          if (col_ok && (e.a != olda || e.b != oldb)) {
-            // the shared node's row is already loaded; fetch the new far end
-            if (e.a == oldb) {
-#pragma unroll
-              for (int v = 0; v < VEC; ++v) xa[v] = xb[v];
-            }
-            VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
-          }
         }
-        const float wa = float(cf.c[i] * omega * e.ha);
-        const float wb = float(cf.c[i] * omega * e.hb);
-        if (col_ok) {
+        const double ci = cf.c[i] * omega;
+        const float wa = live ? float(ci * e.ha) : 0.f;
+        const float wb = live ? float(ci * e.hb) : 0.f;
+        for (int j = 0; j < nlive; ++j) {
+          const int32_t aj = __shfl(e.a, j, G), bj = __shfl(e.b, j, G);
+          const float waj = __shfl(wa, j, G), wbj = __shfl(wb, j, G);
+          if (col_ok) {
+            float xa[VEC], xb[VEC];
+            VecIO<TX, VEC>::load(X + int64_t(aj) * ldx + c0, xa);
+            VecIO<TX, VEC>::load(X + int64_t(bj) * ldx + c0, xb);
 #pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wa, xa[v], fmaf(wb, xb[v], acc[v]));
+            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(waj, xa[v], fmaf(wbj, xb[v], acc[v]));
+          }
         }
       }
     }
   }
-  for (int off = G; off < 64; off <<= 1)
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
-  if (sub == 0 && col_ok) {
+  if (row_ok && col_ok) {
     float x[VEC], o[VEC];
     VecIO<TX, VEC>::load(X + r * ldx + c0, x);
     const float inv = float(1.0 / double(walks));
@@ -302,7 +311,8 @@ sped_status launch_is(const sped_csr *L, int64_t k, const void *X, int64_t ldx, 
   int G = lanes >= 64 ? 64 : next_pow2(lanes);
   int lgG = ilog2(G);
   Graph g{L->rowptr, L->col, L->val, L->rev, L->scale};
-  const dim3 grid = dim3(unsigned((L->n + 3) / 4), unsigned(ytiles));
+  const int64_t rows_per_block = kBlock >> lgG;
+  const dim3 grid = dim3(unsigned((L->n + rows_per_block - 1) / rows_per_block), unsigned(ytiles));
 #define SPED_IS(V)                                                                                      \
   hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, int(k), G, lgG, g, \
                      ell, static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr, cf)
