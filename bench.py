@@ -63,6 +63,69 @@ def measured_traffic(per_launch_alg):
     return t.get("hbm_bytes_per_launch")
 
 
+COPY_BYTES = 512 * 1024 * 1024
+
+
+def traffic_probe(args):
+    """Workload for the counter runs: 3 plain copies of COPY_BYTES (the
+    calibration kernel), then 2 exact applications (32 fused-step launches)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14589_amd import sped, synth
+
+    n, s, d, _ = synth.sbm_from_degrees(1_000_000, 100, 19.0, 1.0, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    Q = torch.from_numpy(synth.gaussian_block(n, 32, 2).astype(np.float32)).cuda()
+    W = torch.empty_like(Q)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        sped.stream_copy(a, b)
+    p = sped.transform("limit", 16)
+    for _ in range(2):
+        sped.apply_poly(L, p, Q, out=W)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "done", "n": L.n, "nnz": L.nnz}), flush=True)
+
+
+def write_traffic(fetch_db, write_db):
+    """Turn two rocprofv3 --pmc databases (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch) into HBM bytes per fused-step launch, each counter scaled by what
+    it reads for the plain copy kernel of known size."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        c = sqlite3.connect(db)
+        rows = c.execute("select name, avg(counter_value), count(*) from pmc_events where counter_name = ? "
+                         "group by name", (counter,)).fetchall()
+        out = {}
+        for name, v, cnt in rows:
+            if "copy_kernel" in name:
+                out["copy"] = v
+            elif "spmm_light" in name:
+                out["spmm"] = v
+        return out
+
+    f = per_kernel(fetch_db, "FETCH_SIZE")
+    w = per_kernel(write_db, "WRITE_SIZE")
+    f_scale = COPY_BYTES / f["copy"]
+    w_scale = COPY_BYTES / w["copy"]
+    fetch = f["spmm"] * f_scale
+    write = w["spmm"] * w_scale
+    out = {"kernel": "spmm_light (fused sparse step), SBM n=1e6, k=32, float32",
+           "kernel_sha": kernel_source_hash(),
+           "copy_bytes": COPY_BYTES,
+           "copy_fetch_kib": f["copy"], "copy_write_kib": w["copy"],
+           "fetch_scale": f_scale, "write_scale": w_scale,
+           "spmm_fetch_kib": f["spmm"], "spmm_write_kib": w["spmm"],
+           "hbm_fetch_bytes_per_launch": fetch, "hbm_write_bytes_per_launch": write,
+           "hbm_bytes_per_launch": fetch + write}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline_leg(n, s, d, X, ell, alg_bytes):
     import numpy as np
 
@@ -107,7 +170,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="summarise the two counter databases into the committed traffic file")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic)
+        return
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(collectives and sharding are out of scope); use --gpus 1", file=sys.stderr)
