@@ -126,6 +126,54 @@ def write_traffic(fetch_db, write_db):
     print(json.dumps(out))
 
 
+def locality_sweep():
+    """Per-launch time of the fused step on SBMs of 1e6 nodes and mean degree
+    20 whose block size sets how local each row's neighbourhood is, plus a
+    plain copy of the same compulsory byte count."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14589_amd import sped, synth
+
+    n = 1_000_000
+    X = torch.from_numpy(synth.gaussian_block(n, 32, 2).astype(np.float32)).cuda()
+    Y = torch.empty_like(X)
+    p = sped.transform("limit", 16)
+    for bs in (125, 1000, 10000, 100000, 1000000):
+        if bs < n:
+            _, s, d, _ = synth.sbm_from_degrees(n, n // bs, 19.0, 1.0, seed=1)
+        else:
+            _, s, d, _ = synth.sbm_sparse([n], 20.0 / (n - 1), 0.0, seed=1)
+        L = sped.Laplacian(n, s, d, kind="sym")
+        for _ in range(2):
+            sped.apply_poly(L, p, X, out=Y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            sped.apply_poly(L, p, X, out=Y)
+        e1.record()
+        torch.cuda.synchronize()
+        print(json.dumps({"block": bs, "nnz": L.nnz, "step_us": round(e0.elapsed_time(e1) * 100 / 16, 2)}),
+              flush=True)
+        del L
+    nbytes = spmm_step_bytes(n, 20_000_000, 32) // 16 * 16
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        sped.stream_copy(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(20):
+        sped.stream_copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1000 / 20
+    print(json.dumps({"copy_bytes_each_way": nbytes, "copy_us": round(us, 2),
+                      "copy_GBps_read_plus_write": round(2 * nbytes / us / 1e3, 1)}), flush=True)
+
+
 def cpu_baseline_leg(n, s, d, X, ell, alg_bytes):
     import numpy as np
 
@@ -174,7 +222,12 @@ def main():
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="summarise the two counter databases into the committed traffic file")
+    ap.add_argument("--locality-sweep", action="store_true",
+                    help="time the fused step against neighbourhood locality, and a plain copy")
     args = ap.parse_args()
+    if args.locality_sweep:
+        locality_sweep()
+        return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
         return
