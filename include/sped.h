@@ -252,11 +252,16 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  * M = lambda_bound I - L), Cholesky-QR2 after every application, and a
  * Rayleigh-Ritz step on L every check_every iterations.  The block carries
  * k + guard columns; the stopping test is
- *     max_{i<k} ||L q_i - theta_i q_i|| / (theta_{k} - theta_{k-1}) <= tol
- * (a Davis-Kahan bound on the subspace angle with the gap estimated from the
- * first guard Ritz value; guard must be >= 1).
+ *     ||R||_F / (theta_k - ||r_k|| - theta_{k-1}) <= tol,   R = [L q_i - theta_i q_i]_{i<k}
+ * (a Davis-Kahan bound on the sine of the largest angle to the true bottom-k
+ * subspace; the gap is estimated from the first guard Ritz value theta_k
+ * lowered by its residual r_k; guard >= 1).
  *  V0      DEVICE F32 n x (k+guard) (ldv0): start block
  *  V_out   DEVICE F32 n x k (ldvo): Ritz vectors, ascending
+ *  vdt     storage of the iterate: F32, or BF16 (float32 sums, float64 Gram,
+ *          Cholesky and Rayleigh-Ritz) until the bound reaches coarse_tol or
+ *          stops improving (8 checks without a 2% drop: bf16's rounding floor),
+ *          followed by a float32 refinement sweep down to tol
  *  evals   HOST double [k]: Ritz values of L, ascending
  *  resid   HOST double [k] or NULL: final residual norms
  *  o, st   HOST options / statistics
@@ -274,6 +279,7 @@ typedef struct {
   int32_t stochastic_iters;/* first iterations use the importance-sampled estimate */
   int64_t walks_per_row;   /* walks per row for those iterations */
   uint64_t seed;           /* Philox key; iteration t uses counter t */
+  double coarse_tol;       /* BF16 phase stops at this bound (<= 0: 1e-2) */
 } sped_solve_opts;
 
 typedef struct {
@@ -285,6 +291,7 @@ typedef struct {
   double bound;            /* the stopping quantity at exit */
   int32_t converged;
   int32_t cholqr_shifts;   /* breakdowns repaired by the shift */
+  int32_t coarse_iters;    /* iterations done with BF16 storage */
 } sped_solve_stats;
 
 sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p, int64_t k, const void *V0,

@@ -86,9 +86,9 @@ def subspace_iteration(L, apply_M, k: int, V0, max_iters: int, tol: float = 0.0,
                        guard: int = 0):
     """Block subspace iteration (eta = inf) or block Oja (finite eta) on M.
 
-    Iterates with k + guard columns; stops when every one of the first k Ritz
-    residuals divided by the gap estimate theta_{k+1} - theta_k (guard > 0) or
-    by 1 (guard = 0) is <= tol.  With Vstar given, records the largest
+    Iterates with k + guard columns; stops when the Frobenius norm of the first
+    k Ritz residuals divided by the gap estimate theta_{k+1} - ||r_{k+1}|| -
+    theta_k (guard > 0) or by 1 (guard = 0) is <= tol (Davis-Kahan).  With Vstar given, records the largest
     principal angle and the subspace error after each check."""
     Q = orthonormal(V0)
     hist = []
@@ -100,8 +100,8 @@ def subspace_iteration(L, apply_M, k: int, V0, max_iters: int, tol: float = 0.0,
         Q = orthonormal(W)
         if t % check_every == 0 or t == max_iters:
             theta, Q, res = rayleigh_ritz(L, Q)
-            gap = (theta[k] - theta[k - 1]) if guard > 0 else 1.0
-            bound = float(np.max(res[:k]) / max(gap, 1e-300))
+            gap = (theta[k] - res[k] - theta[k - 1]) if guard > 0 else 1.0
+            bound = float(np.linalg.norm(res[:k]) / max(gap, 1e-300))
             rec = {"iter": t, "bound": bound, "max_residual": float(np.max(res[:k]))}
             if Vstar is not None:
                 rec["angle"] = max_principal_angle(Vstar, Q[:, :k])

@@ -322,12 +322,12 @@ sped_status launch_dot(int64_t n, int64_t k, const float *A, int64_t lda, const 
 
 // gram.hip
 size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb);
-sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
-                        int dt, double *G, double *partials, hipStream_t s);
+sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, int ta, const void *B, int64_t ldb,
+                        int tb, double *G, double *partials, hipStream_t s);
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
                         void *O, int64_t ldo, int to, hipStream_t s);
 size_t resid_ws_doubles(int64_t k);
-sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const float *Q, int64_t ldq,
+sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const void *Q, int64_t ldq, int tq,
                          const double *theta, double *resid, double *partials, hipStream_t s);
 
 // dense.hip (flags: [0] Cholesky shifts, [1] Cholesky failures, [2] Jacobi caps)

@@ -32,9 +32,9 @@ __device__ inline double load_as_double<bf16_t>(const bf16_t *p) { return double
 // round-robin to the 4 wavefronts, which all read the block's rows (their
 // shared lines come from L1) and write disjoint tiles of one partial.  With
 // SYM (A == B) only tiles p <= q are formed and mirrored on output.
-template <typename T, int MAXT, bool SYM, bool ROWSPLIT>
-__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, const T *__restrict__ A,
-                                                      int64_t lda, const T *__restrict__ B, int64_t ldb,
+template <typename T1, typename T2, int MAXT, bool SYM, bool ROWSPLIT>
+__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, const T1 *__restrict__ A,
+                                                      int64_t lda, const T2 *__restrict__ B, int64_t ldb,
                                                       int64_t rows_per_block, double *__restrict__ partials) {
   constexpr int KU = MAXT <= 4 ? 4 : 1;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
@@ -117,10 +117,10 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
 // wavefronts then add their tiles into one LDS copy in wavefront order (fixed
 // order: deterministic) and the block writes one partial.
 constexpr int kNarrowBlock = 1024;
-template <typename T, int TA, int TB, bool SYM>
+template <typename T1, typename T2, int TA, int TB, bool SYM>
 __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, int ka, int kb,
-                                                                   const T *__restrict__ A, int64_t lda,
-                                                                   const T *__restrict__ B, int64_t ldb,
+                                                                   const T1 *__restrict__ A, int64_t lda,
+                                                                   const T2 *__restrict__ B, int64_t ldb,
                                                                    int64_t rows_per_block,
                                                                    double *__restrict__ partials) {
   constexpr int KU = 4;
@@ -245,8 +245,9 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int ko
 }
 
 // partial[b][c] = sum over this block's rows of (Z[r,c] - theta[c] Q[r,c])^2
+template <typename TQ>
 __global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, int k, const float *__restrict__ Z, int64_t ldz,
-                                                        const float *__restrict__ Q, int64_t ldq,
+                                                        const TQ *__restrict__ Q, int64_t ldq,
                                                         const double *__restrict__ theta,
                                                         double *__restrict__ partials) {
   // thread layout: column c = threadIdx.x % kc, row lane = threadIdx.x / kc
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, int k, const f
   if (rl < nrl) {
     const double th = theta[c];
     for (int64_t r = int64_t(blockIdx.x) * nrl + rl; r < n; r += int64_t(gridDim.x) * nrl) {
-      double d = double(Z[r * ldz + c]) - th * double(Q[r * ldq + c]);
+      double d = double(Z[r * ldz + c]) - th * double(to_f32<TQ>(Q[r * ldq + c]));
       s += d * d;
     }
   }
@@ -303,43 +304,43 @@ GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
   return p;
 }
 
-template <typename T, int MAXT, bool SYM, bool RS>
+template <typename T1, typename T2, int MAXT, bool SYM, bool RS>
 sped_status launch_gram_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
                           double *partials, const GramPlan &p, hipStream_t s) {
-  hipLaunchKernelGGL((gram_kernel<T, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb,
-                     static_cast<const T *>(A), lda, static_cast<const T *>(B), ldb, p.rows_per_block, partials);
+  hipLaunchKernelGGL((gram_kernel<T1, T2, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb,
+                     static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb, p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
 
-template <typename T, int TA, int TB, bool SYM>
+template <typename T1, typename T2, int TA, int TB, bool SYM>
 sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
                                  double *partials, const GramPlan &p, hipStream_t s) {
-  hipLaunchKernelGGL((gram_narrow_kernel<T, TA, TB, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb,
-                     static_cast<const T *>(A), lda, static_cast<const T *>(B), ldb, p.rows_per_block, partials);
+  hipLaunchKernelGGL((gram_narrow_kernel<T1, T2, TA, TB, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb,
+                     static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb, p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
 
-template <typename T, bool SYM>
+template <typename T1, typename T2, bool SYM>
 sped_status launch_gram_maxt(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B,
                              int64_t ldb, double *partials, const GramPlan &p, hipStream_t s) {
   if (p.narrow) {
     const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-    if (TA == 1 && TB == 1) return launch_gram_narrow_t<T, 1, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (TA == 1 && TB == 2) return launch_gram_narrow_t<T, 1, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (TA == 2 && TB == 1) return launch_gram_narrow_t<T, 2, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    return launch_gram_narrow_t<T, 2, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (TA == 1 && TB == 1) return launch_gram_narrow_t<T1, T2, 1, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (TA == 1 && TB == 2) return launch_gram_narrow_t<T1, T2, 1, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (TA == 2 && TB == 1) return launch_gram_narrow_t<T1, T2, 2, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    return launch_gram_narrow_t<T1, T2, 2, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
   }
   if (p.rowsplit) {
-    if (p.maxt <= 1) return launch_gram_t<T, 1, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (p.maxt <= 2) return launch_gram_t<T, 2, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    return launch_gram_t<T, 4, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (p.maxt <= 1) return launch_gram_t<T1, T2, 1, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    if (p.maxt <= 2) return launch_gram_t<T1, T2, 2, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+    return launch_gram_t<T1, T2, 4, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
   }
-  if (p.maxt <= 2) return launch_gram_t<T, 2, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  if (p.maxt <= 4) return launch_gram_t<T, 4, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  if (p.maxt <= 8) return launch_gram_t<T, 8, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  return launch_gram_t<T, 16, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  if (p.maxt <= 2) return launch_gram_t<T1, T2, 2, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  if (p.maxt <= 4) return launch_gram_t<T1, T2, 4, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  if (p.maxt <= 8) return launch_gram_t<T1, T2, 8, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  return launch_gram_t<T1, T2, 16, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
 }
 
 template <typename TX, typename TO>
@@ -375,20 +376,26 @@ size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb) {
   return size_t(a.nparts > b.nparts ? a.nparts : b.nparts) * ka * kb;
 }
 
-sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
-                        int dt, double *G, double *partials, hipStream_t s) {
+sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, int ta, const void *B, int64_t ldb,
+                        int tb, double *G, double *partials, hipStream_t s) {
   if (ka < 1 || kb < 1 || ka > kMaxK || kb > kMaxK) return fail(SPED_E_UNSUPPORTED, "gram width outside [1, 128]");
-  const bool sym = (A == B) && (lda == ldb) && (ka == kb);
+  const bool sym = (A == B) && (lda == ldb) && (ka == kb) && (ta == tb);
   const GramPlan plan = gram_plan(n, ka, kb, sym);
   sped_status st;
-  if (dt == SPED_F32)
-    st = sym ? launch_gram_maxt<float, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
-             : launch_gram_maxt<float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
-  else if (dt == SPED_BF16)
-    st = sym ? launch_gram_maxt<bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
-             : launch_gram_maxt<bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
-  else
+  const bool a32 = ta == SPED_F32, b32 = tb == SPED_F32;
+  if ((ta != SPED_F32 && ta != SPED_BF16) || (tb != SPED_F32 && tb != SPED_BF16))
     return fail(SPED_E_UNSUPPORTED, "gram dtype");
+  if (sym)
+    st = a32 ? launch_gram_maxt<float, float, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
+             : launch_gram_maxt<bf16_t, bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+  else if (a32 && b32)
+    st = launch_gram_maxt<float, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+  else if (!a32 && !b32)
+    st = launch_gram_maxt<bf16_t, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+  else if (!a32 && b32)
+    st = launch_gram_maxt<bf16_t, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+  else
+    st = launch_gram_maxt<float, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   if (st != SPED_OK) return st;
   return launch_sum_partials(partials, plan.nparts, int64_t(ka) * kb, G, false, s);
 }
@@ -405,10 +412,15 @@ sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx
 
 size_t resid_ws_doubles(int64_t k) { return size_t(kResidBlocks) * k; }
 
-sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const float *Q, int64_t ldq,
+sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const void *Q, int64_t ldq, int tq,
                          const double *theta, double *resid, double *partials, hipStream_t s) {
   if (k > kBlock) return fail(SPED_E_UNSUPPORTED, "resid width > 256");
-  hipLaunchKernelGGL(resid_kernel, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz, Q, ldq, theta, partials);
+  if (tq == SPED_F32)
+    hipLaunchKernelGGL(resid_kernel<float>, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz,
+                       static_cast<const float *>(Q), ldq, theta, partials);
+  else
+    hipLaunchKernelGGL(resid_kernel<bf16_t>, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz,
+                       static_cast<const bf16_t *>(Q), ldq, theta, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return launch_sum_partials(partials, kResidBlocks, k, resid, true, s);
 }
@@ -431,5 +443,5 @@ extern "C" sped_status sped_gram(int64_t n, int64_t ka, int64_t kb, const void *
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
-  return launch_gram(n, int(ka), int(kb), A, lda, B, ldb, dt, G, partials, as_stream(stream));
+  return launch_gram(n, int(ka), int(kb), A, lda, dt, B, ldb, dt, G, partials, as_stream(stream));
 }

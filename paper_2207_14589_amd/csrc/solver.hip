@@ -55,38 +55,41 @@ struct OrthWs {
 };
 
 // Q <- W R^{-1} (out of place when W != Q), then `passes - 1` more in place.
-sped_status cholqr(int64_t n, int k, const float *W, float *Q, int64_t ld, int passes, double *R_out,
+// W and Q share the storage type dt (float32 or bf16); the Gram and R are float64.
+sped_status cholqr(int64_t n, int k, const void *W, void *Q, int64_t ld, int dt, int passes, double *R_out,
                    const OrthWs &w, hipStream_t s) {
-  const float *src = W;
+  const void *src = W;
   for (int pass = 0; pass < passes; ++pass) {
-    SPED_TRY(launch_gram(n, k, k, src, ld, src, ld, SPED_F32, w.G, w.partials, s));
+    SPED_TRY(launch_gram(n, k, k, src, ld, dt, src, ld, dt, w.G, w.partials, s));
     SPED_TRY(launch_chol_inv(k, w.G, w.T, pass == passes - 1 ? R_out : nullptr, w.flags, s));
-    SPED_TRY(launch_tsmm(n, k, k, src, ld, SPED_F32, w.T, Q, ld, SPED_F32, s));
+    SPED_TRY(launch_tsmm(n, k, k, src, ld, dt, w.T, Q, ld, dt, s));
     src = Q;
   }
   return SPED_OK;
 }
 
 struct RRWs {
-  float *Z, *ZS, *Qtmp;
+  float *Z, *ZS;
+  void *Qtmp;
   double *H, *S, *theta, *resid, *partials, *rpartials;
   int *flags;
 };
 
-// Rayleigh-Ritz of L on span(Q); Q is replaced by the Ritz vectors (via Qtmp).
-sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, float *&Q, int64_t ld, const RRWs &w,
+// Rayleigh-Ritz of L on span(Q) (Q of storage type dt, Z = L Q in float32);
+// the Ritz vectors are written to Qtmp.
+sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, const void *Q, int64_t ld, int dt, const RRWs &w,
                           hipStream_t s) {
   StepArgs a{};
-  a.U = Q; a.ldu = ld; a.tu = SPED_F32;
-  a.V = nullptr; a.ldv = ld; a.tv = SPED_F32;
+  a.U = Q; a.ldu = ld; a.tu = dt;
+  a.V = nullptr; a.ldv = ld; a.tv = dt;
   a.O = w.Z; a.ldo = ld; a.to = SPED_F32;
   a.a = 1.f; a.b = 0.f; a.g = 0.f;
   SPED_TRY(launch_spmm_step(L, k, a, s));
-  SPED_TRY(launch_gram(n, k, k, Q, ld, w.Z, ld, SPED_F32, w.H, w.partials, s));
+  SPED_TRY(launch_gram(n, k, k, Q, ld, dt, w.Z, ld, SPED_F32, w.H, w.partials, s));
   SPED_TRY(launch_jacobi(k, w.H, w.theta, w.S, w.flags, s));
-  SPED_TRY(launch_tsmm(n, k, k, Q, ld, SPED_F32, w.S, w.Qtmp, ld, SPED_F32, s));
+  SPED_TRY(launch_tsmm(n, k, k, Q, ld, dt, w.S, w.Qtmp, ld, dt, s));
   SPED_TRY(launch_tsmm(n, k, k, w.Z, ld, SPED_F32, w.S, w.ZS, ld, SPED_F32, s));
-  SPED_TRY(launch_resid(n, k, w.ZS, ld, w.Qtmp, ld, w.theta, w.resid, w.rpartials, s));
+  SPED_TRY(launch_resid(n, k, w.ZS, ld, w.Qtmp, ld, dt, w.theta, w.resid, w.rpartials, s));
   return SPED_OK;
 }
 
@@ -116,8 +119,7 @@ extern "C" sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
-  float *Vf = static_cast<float *>(V);
-  SPED_TRY(cholqr(n, int(k), Vf, Vf, ldv, passes, R_out, w, s));
+  SPED_TRY(cholqr(n, int(k), V, V, ldv, SPED_F32, passes, R_out, w, s));
   int flags[4];
   SPED_CHECK_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
   SPED_CHECK_HIP(hipStreamSynchronize(s));
@@ -153,8 +155,7 @@ extern "C" sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q,
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
-  float *Qf = static_cast<float *>(Q);
-  SPED_TRY(rayleigh_ritz(L, n, int(k), Qf, ldq, w, s));
+  SPED_TRY(rayleigh_ritz(L, n, int(k), Q, ldq, SPED_F32, w, s));
   SPED_TRY(copy_block(n, int(k), w.Qtmp, ldq, SPED_F32, Q, ldq, SPED_F32, s));
   return SPED_OK;
 }
@@ -173,7 +174,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   const int64_t n = L->n;
   if (n < kb) return fail(SPED_E_INVALID, "n < k + guard");
   if (ldv0 < kb || ldvo < k) return fail(SPED_E_INVALID, "leading dimension");
-  if (vdt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "solver block dtype must be F32");
+  if (vdt != SPED_F32 && vdt != SPED_BF16) return fail(SPED_E_UNSUPPORTED, "solver block dtype must be F32 or BF16");
   if (!V0 || !V_out || !evals) return fail(SPED_E_INVALID, "NULL pointer");
   if (o->max_iters < 1 || o->check_every < 1) return fail(SPED_E_INVALID, "max_iters/check_every");
   if (o->orth_passes < 1 || o->orth_passes > 4) return fail(SPED_E_INVALID, "orth_passes");
@@ -205,11 +206,15 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     if (M.degree > 255) return fail(SPED_E_UNSUPPORTED, "stochastic iterations need degree <= 255");
   }
 
+  const bool two_phase = vdt == SPED_BF16;
+  const double coarse_tol = o->coarse_tol > 0.0 ? o->coarse_tol : 1e-2;
   Carver c(ws);
-  float *Q = c.take<float>(size_t(n) * kb);
-  float *W = c.take<float>(size_t(n) * kb);
+  float *Q32 = c.take<float>(size_t(n) * kb);
+  float *W32 = c.take<float>(size_t(n) * kb);
   float *bufA = c.take<float>(size_t(n) * kb);
   float *bufB = c.take<float>(size_t(n) * kb);
+  bf16_t *Q16 = two_phase ? c.take<bf16_t>(size_t(n) * kb) : nullptr;
+  bf16_t *W16 = two_phase ? c.take<bf16_t>(size_t(n) * kb) : nullptr;
   OrthWs ow;
   ow.G = c.take<double>(size_t(kb) * kb);
   ow.T = c.take<double>(size_t(kb) * kb);
@@ -232,53 +237,92 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   sped_solve_stats stats{};
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
-  SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, W, kb, SPED_F32, s));
-  SPED_TRY(cholqr(n, int(kb), W, Q, kb, o->orth_passes, nullptr, ow, s));
 
   std::vector<double> h_theta(kb), h_resid(kb);
   int h_flags[4] = {0, 0, 0, 0};
-  sped_status result = SPED_E_NOT_CONVERGED;
   int t = 0;
-  for (t = 1; t <= o->max_iters; ++t) {
-    if (t <= o->stochastic_iters) {
-      SPED_TRY(walk_estimate_impl(L, walk_c.data(), M.degree, kb, Q, kb, SPED_F32, W, kb, SPED_F32, 0,
-                                  o->walks_per_row, o->seed, uint64_t(t), nullptr, s));
-    } else {
-      SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, SPED_F32, W, kb, SPED_F32, bufA, bufB, s, &stats.spmm_count));
-    }
-    SPED_TRY(cholqr(n, int(kb), W, Q, kb, o->orth_passes, nullptr, ow, s));
-    if (t % o->check_every == 0 || t == o->max_iters) {
-      rw.Z = bufA;
-      rw.ZS = bufB;
-      rw.Qtmp = W;
-      SPED_TRY(rayleigh_ritz(L, n, int(kb), Q, kb, rw, s));
-      std::swap(Q, W);  // Ritz vectors now in Q
-      stats.spmm_count += 1;
-      SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-      SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-      SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
-      SPED_CHECK_HIP(hipStreamSynchronize(s));
-      if (h_flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
-      double rmax = 0.0;
-      bool finite = true;
-      for (int i = 0; i < k; ++i) {
-        rmax = std::max(rmax, h_resid[i]);
-        finite = finite && std::isfinite(h_resid[i]) && std::isfinite(h_theta[i]);
+  // One phase of iterations with the iterate stored as dt in (Q, W); returns
+  // with the Ritz vectors in Q after the last check.
+  // With stall_checks > 0 the phase also ends when the bound has not dropped
+  // below 0.98 x its best value for that many consecutive checks (the
+  // storage's rounding floor has been reached).
+  auto phase = [&](int dt, void *&Q, void *&W, double tol, int iter_cap, int stall_checks,
+                   bool *done) -> sped_status {
+    *done = false;
+    const int first = t + 1;
+    double best = INFINITY;
+    int since_best = 0;
+    for (t = first; t <= iter_cap; ++t) {
+      if (t <= o->stochastic_iters) {
+        SPED_TRY(walk_estimate_impl(L, walk_c.data(), M.degree, kb, Q, kb, dt, W, kb, dt, 0, o->walks_per_row,
+                                    o->seed, uint64_t(t), nullptr, s));
+      } else {
+        SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, s, &stats.spmm_count));
       }
-      if (!finite) return fail(SPED_E_NUMERIC, "non-finite Ritz value or residual");
-      double gap = h_theta[k] - h_theta[k - 1];
-      stats.gap_estimate = gap;
-      stats.max_residual = rmax;
-      stats.bound = gap > 0 ? rmax / gap : INFINITY;
-      if (stats.bound <= o->tol) {
-        result = SPED_OK;
-        break;
+      SPED_TRY(cholqr(n, int(kb), W, Q, kb, dt, o->orth_passes, nullptr, ow, s));
+      if ((t - first + 1) % o->check_every == 0 || t == iter_cap) {
+        rw.Z = bufA;
+        rw.ZS = bufB;
+        rw.Qtmp = W;
+        SPED_TRY(rayleigh_ritz(L, n, int(kb), Q, kb, dt, rw, s));
+        std::swap(Q, W);  // Ritz vectors now in Q
+        stats.spmm_count += 1;
+        SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+        SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+        SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+        SPED_CHECK_HIP(hipStreamSynchronize(s));
+        if (h_flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
+        double rmax = 0.0, rf2 = 0.0;
+        bool finite = true;
+        for (int i = 0; i < k; ++i) {
+          rmax = std::max(rmax, h_resid[i]);
+          rf2 += h_resid[i] * h_resid[i];
+          finite = finite && std::isfinite(h_resid[i]) && std::isfinite(h_theta[i]);
+        }
+        if (!finite) return fail(SPED_E_NUMERIC, "non-finite Ritz value or residual");
+        // the first guard Ritz value overestimates lambda_{k+1}; its residual
+        // bounds by how much, so the gap estimate subtracts it
+        double gap = h_theta[k] - h_resid[k] - h_theta[k - 1];
+        stats.gap_estimate = gap;
+        stats.max_residual = rmax;
+        // Davis-Kahan: sin of the largest angle <= ||R||_2 / gap <= ||R||_F / gap
+        stats.bound = gap > 0 ? std::sqrt(rf2) / gap : INFINITY;
+        if (stats.bound <= tol) {
+          *done = true;
+          return SPED_OK;
+        }
+        if (stats.bound < 0.98 * best) {
+          best = stats.bound;
+          since_best = 0;
+        } else if (stall_checks > 0 && ++since_best >= stall_checks) {
+          return SPED_OK;
+        }
       }
     }
+    t = iter_cap;
+    return SPED_OK;
+  };
+
+  void *Q = Q32, *W = W32;
+  bool done = false;
+  if (two_phase) {
+    void *Qh = Q16, *Wh = W16;
+    SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, Wh, kb, SPED_BF16, s));
+    SPED_TRY(cholqr(n, int(kb), Wh, Qh, kb, SPED_BF16, o->orth_passes, nullptr, ow, s));
+    SPED_TRY(phase(SPED_BF16, Qh, Wh, coarse_tol, o->max_iters, 8, &done));
+    stats.coarse_iters = t;
+    // refinement sweep: the bf16 iterate seeds float32 iterations
+    SPED_TRY(copy_block(n, int(kb), Qh, kb, SPED_BF16, W, kb, SPED_F32, s));
+  } else {
+    SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, W, kb, SPED_F32, s));
   }
-  stats.iters = t > o->max_iters ? o->max_iters : t;
+  SPED_TRY(cholqr(n, int(kb), W, Q, kb, SPED_F32, o->orth_passes, nullptr, ow, s));
+  done = false;
+  if (t < o->max_iters) SPED_TRY(phase(SPED_F32, Q, W, o->tol, o->max_iters, 0, &done));
+  sped_status result = done ? SPED_OK : SPED_E_NOT_CONVERGED;
+  stats.iters = t;
   stats.converged = result == SPED_OK;
-  SPED_TRY(copy_block(n, int(k), Q, kb, SPED_F32, V_out, ldvo, vdt, s));
+  SPED_TRY(copy_block(n, int(k), Q, kb, SPED_F32, V_out, ldvo, SPED_F32, s));
   SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
   SPED_CHECK_HIP(hipStreamSynchronize(s));
   stats.cholqr_shifts = h_flags[0];

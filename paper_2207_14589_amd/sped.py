@@ -42,13 +42,14 @@ class Poly(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", _c_i32), ("eta", _c_f64), ("tol", _c_f64), ("max_iters", _c_i32),
                 ("check_every", _c_i32), ("guard", _c_i32), ("orth_passes", _c_i32),
-                ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64)]
+                ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64),
+                ("coarse_tol", _c_f64)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", _c_i32), ("spmm_count", _c_i64), ("seconds", _c_f64), ("max_residual", _c_f64),
                 ("gap_estimate", _c_f64), ("bound", _c_f64), ("converged", _c_i32),
-                ("cholqr_shifts", _c_i32)]
+                ("cholqr_shifts", _c_i32), ("coarse_iters", _c_i32)]
 
 
 _P = ctypes.POINTER
@@ -308,7 +309,7 @@ class SolveResult:
 
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
-            seed=3, v0_seed=2):
+            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2):
     dev = L.device
     kb = k + guard
     if V0 is None:
@@ -319,12 +320,13 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
     rs = np.zeros(k)
     o = SolveOpts(solver={"subspace": 0, "oja": 1}[solver], eta=eta, tol=tol, max_iters=max_iters,
                   check_every=check_every, guard=guard, orth_passes=orth_passes,
-                  stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed)
+                  stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
+                  coarse_tol=coarse_tol)
     st = SolveStats()
     ps = poly.struct() if poly is not None else None
     status, _ = _call_ws(lib().sped_bottomk_solve, "sped_bottomk_solve",
                          (L.ref, ctypes.byref(ps) if ps is not None else None, k, _ptr(V0), _ld(V0), _ptr(V_out),
-                          _ld(V_out), F32, ev.ctypes.data_as(ctypes.POINTER(_c_f64)),
+                          _ld(V_out), {"f32": F32, "bf16": BF16}[storage], ev.ctypes.data_as(ctypes.POINTER(_c_f64)),
                           rs.ctypes.data_as(ctypes.POINTER(_c_f64)), ctypes.byref(o), ctypes.byref(st)), dev,
                          allow=(E_NOT_CONVERGED,))
     stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}

@@ -406,3 +406,40 @@ def test_stream_copy(sped):
     sped.stream_copy(a, b)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def test_bottomk_bf16_then_f32_refinement(sped):
+    """bf16 iterate storage down to its rounding floor (bound ~1e-2 here: bf16's
+    u = 2^-9 over a gap of 0.33), then a float32 refinement sweep to 1e-6: the
+    bottom-10 span still matches dense eigh within 1e-6, and the bf16 iterate
+    itself is within 1e-2 of it."""
+    _say("bottomk bf16 storage + float32 refinement")
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    r = sped.bottomk(L, 10, sped.transform("limit", 8), V0=V0, guard=4, tol=1e-6, max_iters=3000,
+                     storage="bf16")
+    assert r.converged, r.stats
+    assert 0 < r.stats["coarse_iters"] < r.stats["iters"]
+    ang = osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64))
+    assert ang <= 1e-6, (ang, r.stats)
+    np.testing.assert_allclose(r.evals[1:], lam[1:], rtol=1e-6)
+    _say(f"  bf16 iters={r.stats['coarse_iters']} total={r.stats['iters']} angle={ang:.2e}")
+
+
+def test_gram_bf16_f32_rayleigh_path(sped):
+    """The mixed bf16 x float32 Gram used by the bf16 solver: H = Q^T (L Q)."""
+    _say("mixed-dtype Rayleigh-Ritz inside a bf16 solve, 3 iterations vs oracle trajectory")
+    n, s, d, _ = synth.sbm_bernoulli([150] * 6, 0.08, 0.002, seed=9)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    V0n = synth.gaussian_block(n, 10, 4).astype(np.float32)
+    V0 = torch.from_numpy(V0n).cuda()
+    p = opoly.limit_exp(8)
+    r32 = sped.bottomk(L, 6, sped.transform("limit", 8), V0=V0, guard=4, tol=0.0, max_iters=3)
+    o = osol.subspace_iteration(ref.L, lambda Q: opoly.apply_terms(ref.L, p, Q), 6, V0n.astype(np.float64),
+                                max_iters=3, guard=4)
+    assert osol.max_principal_angle(o.Q, r32.V.cpu().numpy().astype(np.float64)) < 1e-4
+    np.testing.assert_allclose(r32.evals, o.evals, rtol=1e-5, atol=1e-6)
