@@ -129,3 +129,40 @@ def laplacian(n, src, dst, w=None, kind: str = SYM_NORMALIZED, lcc: bool = False
     return Laplacian(n=n, kind=kind, L=L, eu=eu, ev=ev, ew=ew, degree=degree,
                      count_degree=cdeg, scale=scale, old_of_new=old_of_new,
                      lambda_bound=float(lambda_bound))
+
+
+def rows_times_block(n, src, dst, w, kind: str, rows, V_rows_fn):
+    """Rows `rows` of L V straight from the edge list, without forming L.
+
+    (L V)_r = sum over edges e = (r, j) of w_e s_r (s_r V_r - s_j V_j), which is
+    row r of X~^T W X~ V (Sec. 2, weighted form; s = D^{-1/2} when normalised).
+    Repeated edges contribute once each; self-loops contribute nothing.
+    `V_rows_fn(ids)` returns the float64 rows of V for the node ids asked for
+    (so V never has to be materialised in full).  Returns (len(rows), k).
+    """
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    rows = np.asarray(rows, dtype=np.int64)
+    w = np.ones(src.shape[0]) if w is None else np.asarray(w, dtype=np.float64)
+    keep = src != dst
+    src, dst, w = src[keep], dst[keep], w[keep]
+    degree = np.bincount(src, weights=w, minlength=n) + np.bincount(dst, weights=w, minlength=n)
+    if kind == SYM_NORMALIZED:
+        scale = np.zeros(n)
+        nz = degree > 0
+        scale[nz] = 1.0 / np.sqrt(degree[nz])
+    else:
+        scale = np.ones(n)
+    pos = {int(r): i for i, r in enumerate(rows)}
+    sel_a = np.isin(src, rows)
+    sel_b = np.isin(dst, rows)
+    r_of = np.concatenate([src[sel_a], dst[sel_b]])          # the sampled endpoint
+    o_of = np.concatenate([dst[sel_a], src[sel_b]])          # the other endpoint
+    w_of = np.concatenate([w[sel_a], w[sel_b]])
+    Vr = V_rows_fn(rows)
+    Vo = V_rows_fn(o_of)
+    out = np.zeros((rows.shape[0], Vr.shape[1]))
+    idx = np.array([pos[int(r)] for r in r_of], dtype=np.int64)
+    contrib = (w_of * scale[r_of])[:, None] * (scale[r_of][:, None] * Vr[idx] - scale[o_of][:, None] * Vo)
+    np.add.at(out, idx, contrib)
+    return out

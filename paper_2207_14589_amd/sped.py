@@ -155,9 +155,15 @@ class Laplacian:
 
     def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda"):
         dev = torch.device(device)
-        src = torch.as_tensor(np.asarray(src), dtype=torch.int32).to(dev)
-        dst = torch.as_tensor(np.asarray(dst), dtype=torch.int32).to(dev)
-        wt = None if w is None else torch.as_tensor(np.asarray(w), dtype=torch.float32).to(dev)
+
+        def dev_tensor(x, dt):
+            if isinstance(x, torch.Tensor):
+                return x.to(device=dev, dtype=dt).contiguous()
+            return torch.as_tensor(np.asarray(x), dtype=dt).to(dev)
+
+        src = dev_tensor(src, torch.int32)
+        dst = dev_tensor(dst, torch.int32)
+        wt = None if w is None else dev_tensor(w, torch.float32)
         m = src.numel()
         n = int(n)
         if dst.numel() != m or (wt is not None and wt.numel() != m):

@@ -20,6 +20,8 @@ undirected edges, possibly with duplicates or self-loops only where stated):
   well-clustered workload of the paper's clique experiments (Sec. 5.4).
 * ``three_room_grid`` -- the 3-room grid-world state graph of Sec. 5.3.
 * ``gaussian_block`` -- an n x k block with i.i.d. N(0,1) entries.
+* ``rmat_device``, ``gaussian_block_device`` -- the same on the GPU with torch's
+  seeded generator, for graphs and blocks too large to draw on the host.
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ __all__ = [
     "rng", "path_graph", "cycle_graph", "complete_graph", "disjoint_cliques",
     "sbm_bernoulli", "sbm_sparse", "sbm_from_degrees", "chung_lu", "rmat",
     "cliques_short_circuit", "three_room_grid", "gaussian_block",
-    "random_weights",
+    "random_weights", "rmat_device", "gaussian_block_device",
 ]
 
 
@@ -284,3 +286,54 @@ def random_weights(m: int, seed: int, lo: float = 0.05, hi: float = 1.0):
 def gaussian_block(n: int, k: int, seed: int) -> np.ndarray:
     """An n x k float64 block with i.i.d. N(0, 1) entries (row-major)."""
     return rng(seed).standard_normal((n, k))
+
+
+def rmat_device(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
+                device="cuda", chunk: int = 1 << 27):
+    """R-MAT on the GPU with torch's seeded counter-based generator, for graphs
+    too large to draw on the host (scale 26 = 1.07e9 edges): each edge descends
+    `scale` levels choosing quadrant (0,0),(0,1),(1,0),(1,1) with probabilities
+    a, b, c, 1-a-b-c; vertex ids are relabelled by a seeded random permutation;
+    self-loops and repeated pairs are removed (the graph is unweighted).
+    Returns (n, src, dst) as int32 device tensors with src < dst."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = 1 << scale
+    m = edge_factor * n
+    perm = torch.randperm(n, generator=g, device=device, dtype=torch.int64)
+    ab, abc = a + b, a + b + c
+    keys = []
+    for lo in range(0, m, chunk):
+        cnt = min(chunk, m - lo)
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for lev in range(scale):
+            r = torch.rand(cnt, generator=g, device=device)
+            u |= (r >= ab).to(torch.int64) << lev
+            v |= (((r >= a) & (r < ab)) | (r >= abc)).to(torch.int64) << lev
+            del r
+        u = perm[u]
+        v = perm[v]
+        lo_, hi_ = torch.minimum(u, v), torch.maximum(u, v)
+        del u, v
+        k = (lo_ << 32) | hi_
+        keys.append(k[lo_ != hi_])
+        del lo_, hi_, k
+    key = torch.unique(torch.cat(keys))
+    del keys
+    src = (key >> 32).to(torch.int32)
+    dst = (key & 0xFFFFFFFF).to(torch.int32)
+    return n, src, dst
+
+
+def gaussian_block_device(n: int, k: int, seed: int, dtype=None, device="cuda"):
+    """An n x k block of i.i.d. N(0, 1) entries drawn on the device (float32
+    draws, optionally cast), for blocks too large to draw on the host."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    x = torch.randn(n, k, generator=g, device=device, dtype=torch.float32)
+    return x if dtype is None else x.to(dtype)

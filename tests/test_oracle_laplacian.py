@@ -145,3 +145,19 @@ def test_table1_edge_pair_products():
     assert owalk.edge_pair_product(lap2, 0, 1) == 1.0        # converging 0 -> 2 <- 1
     assert owalk.edge_pair_product(lap, e01, e01) == 2.0     # repeated
     assert owalk.edge_pair_product(lap, e01, e67) == 0.0     # disconnected
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_rows_times_block_matches_full_operator(kind):
+    """Sampled rows of L V from the edge list equal the full incidence-built
+    operator applied to V (repeats, self-loops and weights included)."""
+    g = np.random.default_rng(8)
+    n = 300
+    src = g.integers(0, n, 2000)
+    dst = g.integers(0, n, 2000)
+    w = g.uniform(0.1, 1.0, 2000)
+    V = g.standard_normal((n, 5))
+    lap = olap.laplacian(n, src, dst, w, kind=kind)
+    rows = np.array([0, 7, 7 + 1, 150, n - 1])
+    got = olap.rows_times_block(n, src, dst, w, kind, rows, lambda ids: V[ids])
+    np.testing.assert_allclose(got, (lap.L @ V)[rows], rtol=1e-12, atol=1e-12)
