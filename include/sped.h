@@ -65,10 +65,25 @@ typedef enum {
  *  scale  [n]   float   s_i = 1 (combinatorial) or d_i^{-1/2} (normalised; 0 if d_i = 0)
  *  bins   [n]   int32   rows with more than SPED_LIGHT_MAX entries, medium rows
  *                       (<= SPED_MEDIUM_MAX entries) first, then heavy rows
+ *  wentry [nnz], wnode [n]  packed walk records (see above), optional
  * d_i is the weighted degree; nnz = 2 x the number of distinct undirected edges.
  */
 #define SPED_LIGHT_MAX 128
 #define SPED_MEDIUM_MAX 8192
+/* Packed records read by the walk estimators: one 16-byte load per move.
+ *  sped_walk_entry[p] = (col[p], val[p], rev[p] - rowptr[col[p]], 0)
+ *  sped_walk_node[u]  = (rowptr[u], rowptr[u+1] - rowptr[u], sqrt(scale[u])) */
+typedef struct {
+  int32_t col;
+  float val;
+  int32_t rev_local;
+  int32_t pad;
+} sped_walk_entry;
+typedef struct {
+  int64_t start;
+  int32_t degree;
+  float root_scale;
+} sped_walk_node;
 typedef struct {
   int64_t n;
   int64_t nnz;
@@ -79,6 +94,8 @@ typedef struct {
   float *diag;
   float *scale;
   int32_t *bins;
+  sped_walk_entry *wentry; /* [nnz], or NULL (then the walk estimators are unavailable) */
+  sped_walk_node *wnode;   /* [n], or NULL */
   int64_t n_medium;
   int64_t n_heavy;
   int32_t max_degree;   /* largest number of neighbours of any node (deg* of Sec. 4.3) */
@@ -98,8 +115,8 @@ typedef struct {
  *  lcc_only    nonzero: keep only the largest connected component (ties: the
  *              one holding the smallest node id), relabelled in increasing id
  *  out         HOST struct; on entry its array pointers must point to DEVICE
- *              buffers of at least rowptr n+1, col/val/rev 2m, diag/scale/bins
- *              n elements.  On return n, nnz, n_medium, n_heavy, max_degree,
+ *              buffers of at least rowptr n+1, col/val/rev/wentry 2m,
+ *              diag/scale/bins/wnode n elements (wentry, wnode may be NULL).  On return n, nnz, n_medium, n_heavy, max_degree,
  *              kind and lambda_bound are filled in.
  *  old_of_new  DEVICE int32 [n] or NULL: original id of each kept node
  * Synchronises `stream` before returning (sizes are read back).  Invalid

@@ -218,6 +218,31 @@ __global__ void reverse_positions(int64_t nnz, const uint64_t *__restrict__ keys
   }
 }
 
+__global__ void walk_entry_records(int64_t nnz, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                   const float *__restrict__ val, const int64_t *__restrict__ rev,
+                                   sped_walk_entry *__restrict__ we) {
+  GRID_STRIDE(p, nnz) {
+    const int32_t c = col[p];
+    sped_walk_entry e;
+    e.col = c;
+    e.val = val[p];
+    e.rev_local = int32_t(rev[p] - rowptr[c]);
+    e.pad = 0;
+    we[p] = e;
+  }
+}
+
+__global__ void walk_node_records(int64_t n, const int64_t *__restrict__ rowptr, const float *__restrict__ scale,
+                                  sped_walk_node *__restrict__ wn) {
+  GRID_STRIDE(r, n) {
+    sped_walk_node v;
+    v.start = rowptr[r];
+    v.degree = int32_t(rowptr[r + 1] - rowptr[r]);
+    v.root_scale = sqrtf(scale[r]);
+    wn[r] = v;
+  }
+}
+
 __global__ void bin_flags(int64_t n, const int64_t *__restrict__ rowptr, char *__restrict__ fmed,
                           char *__restrict__ fheavy) {
   GRID_STRIDE(r, n) {
@@ -414,6 +439,16 @@ extern "C" sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *s
                          out->val);
       hipLaunchKernelGGL(reverse_positions, dim3(grid_for(nnz)), dim3(kBlock), 0, s, nnz, keys, out->rowptr,
                          out->rev);
+      SPED_CHECK_HIP(hipGetLastError());
+    }
+    if (out->wentry && nnz > 0) {
+      hipLaunchKernelGGL(walk_entry_records, dim3(grid_for(nnz)), dim3(kBlock), 0, s, nnz, out->rowptr, out->col,
+                         out->val, out->rev, out->wentry);
+      SPED_CHECK_HIP(hipGetLastError());
+    }
+    if (out->wnode) {
+      hipLaunchKernelGGL(walk_node_records, dim3(grid_for(n_out)), dim3(kBlock), 0, s, n_out, out->rowptr,
+                         out->scale, out->wnode);
       SPED_CHECK_HIP(hipGetLastError());
     }
     size_t tb = b.temp_bytes;

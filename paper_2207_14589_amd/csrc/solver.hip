@@ -182,8 +182,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->solver == 1 && !(o->eta > 0.0 && std::isfinite(o->eta))) return fail(SPED_E_INVALID, "eta");
   if (!(o->tol >= 0.0)) return fail(SPED_E_INVALID, "tol");
   if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
-  if (o->stochastic_iters > 0 && (o->walks_per_row < 1 || !L->rev))
-    return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and csr rev");
+  if (o->stochastic_iters > 0 && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
+    return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and the walk records");
 
   // the operator actually iterated on
   std::vector<double> plain_c = {L->lambda_bound, -1.0};

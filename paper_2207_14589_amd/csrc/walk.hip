@@ -5,7 +5,8 @@
 //
 // Incidence entries: for edge e = (a, b), h(e, a) = sign sqrt(w_e) s_a with
 // sign +1 when a < b (Sec. 2 convention), and sqrt(w_e) s_a = sqrt(val s_a/s_b)
-// because val = w_e s_a s_b.  Table 1 generalises to x_e^T x_f = h(e,u) h(f,u)
+// because val = w_e s_a s_b.  Entries and inner products are float32; the
+// walk weights (products of up to 16 factors) are float64.  Table 1 generalises to x_e^T x_f = h(e,u) h(f,u)
 // for distinct edges meeting at u, and h(e,a)^2 + h(e,b)^2 for e = f.
 //
 // Moving from e = (a, b): draw t uniform in [0, d_a + d_b - 1); t < d_a picks
@@ -41,75 +42,74 @@ struct Coefs {
   double c[kMaxDeg + 1];
 };
 
+// A walker's current edge e = (a, b): CSR position p in row a, the row
+// ranges of both endpoints, the square roots of their scales (r_u = sqrt(s_u))
+// and the incidence entries h(e, a), h(e, b).  Kept in registers.
 struct Edge {
-  int64_t p;       // CSR position
-  int32_t a, b;    // p lies in row a; b = col[p]
-  int64_t a0, a1;  // rowptr[a], rowptr[a+1]
-  int64_t b0, b1;  // rowptr[b], rowptr[b+1]
-  float sa, sb;    // node scales
-  double ha, hb;   // incidence entries h(e, a), h(e, b)
+  int64_t p;
+  int64_t a0, a1, b0, b1;
+  int32_t a, b;
+  float ra, rb;
+  float ha, hb;
 };
 
+struct Graph {
+  const int64_t *rowptr;
+  const sped_walk_entry *we;
+  const sped_walk_node *wn;
+};
+
+// h(e, a) = sign sqrt(w_e) s_a with sqrt(w_e) s_a = sqrt(val) r_a / r_b
+// (val = w_e s_a s_b), sign + when a < b.
 __device__ inline void edge_entries(Edge &e, float val) {
-  double v = double(val);
-  double ga, gb;
-  if (e.sa == e.sb) {
-    ga = gb = sqrt(v);
-  } else {
-    double ratio = double(e.sa) / double(e.sb);
-    ga = sqrt(v * ratio);
-    gb = sqrt(v / ratio);
-  }
-  const double sg = e.a < e.b ? 1.0 : -1.0;
+  const float sv = sqrtf(val);
+  const float ga = sv * (e.ra / e.rb);
+  const float gb = sv * (e.rb / e.ra);
+  const float sg = e.a < e.b ? 1.f : -1.f;
   e.ha = sg * ga;
   e.hb = -sg * gb;
 }
 
-// Entry h(f, u) of an edge f stored at position q in row u with other end v.
-__device__ inline double entry_at(int32_t u, int32_t v, float val, float su, float sv) {
-  double g = (su == sv) ? sqrt(double(val)) : sqrt(double(val) * double(su) / double(sv));
-  return u < v ? g : -g;
+// The walk state after picking entry p of row r (node record nr).  *rev_p
+// receives the position of the edge's copy in the other endpoint's row.
+__device__ inline Edge first_edge(const Graph &g, int32_t r, const sped_walk_node &nr, int64_t p, int64_t *rev_p) {
+  const sped_walk_entry en = g.we[p];
+  const sped_walk_node nb = g.wn[en.col];
+  Edge e;
+  e.p = p;
+  e.a = r; e.a0 = nr.start; e.a1 = nr.start + nr.degree; e.ra = nr.root_scale;
+  e.b = en.col; e.b0 = nb.start; e.b1 = nb.start + nb.degree; e.rb = nb.root_scale;
+  edge_entries(e, en.val);
+  *rev_p = nb.start + en.rev_local;
+  return e;
 }
 
-struct Graph {
-  const int64_t *rowptr;
-  const int32_t *col;
-  const float *val;
-  const int64_t *rev;
-  const float *scale;
-};
-
-// Move along H; returns x_e^T x_f and sets deg_H(e) in *degH.
-__device__ inline double move(const Graph &g, Edge &e, uint32_t t, uint32_t *degH) {
-  const int64_t da = e.a1 - e.a0, db = e.b1 - e.b0;
-  *degH = uint32_t(da + db - 1);
-  int64_t q;
-  int32_t u;
-  int64_t u0, u1;
-  float su;
-  double h_eu;
-  if (int64_t(t) < da) {
-    q = e.a0 + t;
-    u = e.a; u0 = e.a0; u1 = e.a1; su = e.sa; h_eu = e.ha;
-  } else {
-    q = e.b0 + (int64_t(t) - da);
-    if (q >= g.rev[e.p]) ++q;
-    u = e.b; u0 = e.b0; u1 = e.b1; su = e.sb; h_eu = e.hb;
-  }
-  double dot;
-  if (q == e.p) {
-    dot = e.ha * e.ha + e.hb * e.hb;
-    return dot;  // the walk stays on e
-  }
-  const int32_t v = g.col[q];
-  const float vq = g.val[q];
-  const float sv = g.scale[v];
-  const double h_fu = entry_at(u, v, vq, su, sv);
-  dot = h_eu * h_fu;
-  e.p = q;
-  e.a = u; e.a0 = u0; e.a1 = u1; e.sa = su;
-  e.b = v; e.b0 = g.rowptr[v]; e.b1 = g.rowptr[v + 1]; e.sb = sv;
-  edge_entries(e, vq);
+// Move along H to neighbour number t of e (t < deg_H(e) = d_a + d_b - 1):
+// t < d_a picks entry t of row a (t = p - a0 is e itself, H's self-loop),
+// otherwise entry t - d_a of row b skipping b's copy of e at *rev_p.  Two
+// dependent 16-byte loads (entry record, then node record); *rev_p is updated
+// for the new edge.  Returns x_e^T x_f.
+__device__ inline float move(const Graph &g, Edge &e, uint32_t t, int64_t *rev_p) {
+  const int64_t da = e.a1 - e.a0;
+  const bool fa = int64_t(t) < da;
+  int64_t qb = e.b0 + (int64_t(t) - da);
+  qb += qb >= *rev_p ? 1 : 0;
+  const int64_t q = fa ? e.a0 + int64_t(t) : qb;
+  const int32_t u = fa ? e.a : e.b;
+  const int64_t u0 = fa ? e.a0 : e.b0, u1 = fa ? e.a1 : e.b1;
+  const float ru = fa ? e.ra : e.rb;
+  const float h_eu = fa ? e.ha : e.hb;
+  const sped_walk_entry en = g.we[q];
+  const sped_walk_node nv = g.wn[en.col];
+  const float dot_same = e.ha * e.ha + e.hb * e.hb;
+  Edge f;
+  f.p = q;
+  f.a = u; f.a0 = u0; f.a1 = u1; f.ra = ru;
+  f.b = en.col; f.b0 = nv.start; f.b1 = nv.start + nv.degree; f.rb = nv.root_scale;
+  edge_entries(f, en.val);
+  *rev_p = nv.start + en.rev_local;
+  const float dot = (q == e.p) ? dot_same : h_eu * f.ha;  // f.ha: entry of f at u
+  e = f;
   return dot;
 }
 
@@ -131,14 +131,10 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
   float acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-  int64_t r0 = 0, r1 = 0;
-  float sr = 0.f;
-  if (row_ok) {
-    r0 = g.rowptr[r];
-    r1 = g.rowptr[r + 1];
-    sr = g.scale[r];
-  }
-  const int64_t dr = r1 - r0;
+  sped_walk_node nr{0, 0, 0.f};
+  if (row_ok) nr = g.wn[r];
+  const int64_t r0 = nr.start;
+  const int64_t dr = nr.degree;
   // every lane of a group sees the same dr, so the loops below are uniform per group
   if (dr > 0) {
     for (int64_t wbase = 0; wbase < walks; wbase += G) {
@@ -147,30 +143,25 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
       const int nlive = int(min<int64_t>(G, walks - wbase));
       Edge e;
       double omega = 0.0;
+      int64_t rev_p = 0;
       if (live) {
         uint32_t t0 = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 0u, uint32_t(dr));
-        e.p = r0 + t0;
-        e.a = int32_t(r); e.a0 = r0; e.a1 = r1; e.sa = sr;
-        e.b = g.col[e.p];
-        e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
-        e.sb = g.scale[e.b];
-        edge_entries(e, g.val[e.p]);
-        omega = double(dr) * e.ha;
+        e = first_edge(g, int32_t(r), nr, r0 + t0, &rev_p);
+        omega = double(dr) * double(e.ha);
       } else {
         e.a = e.b = int32_t(r);
-        e.ha = e.hb = 0.0;
+        e.ha = e.hb = 0.f;
       }
       for (int i = 1; i <= ell; ++i) {
         if (i > 1 && live) {
           uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
           uint32_t t = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(i - 1), bound);
-          uint32_t degH;
-          double dot = move(g, e, t, &degH);
-          omega = omega * dot * double(degH);
+          float dot = move(g, e, t, &rev_p);
+          omega = omega * double(dot) * double(bound);
         }
         const double ci = cf.c[i] * omega;
-        const float wa = live ? float(ci * e.ha) : 0.f;
-        const float wb = live ? float(ci * e.hb) : 0.f;
+        const float wa = live ? float(ci * double(e.ha)) : 0.f;
+        const float wb = live ? float(ci * double(e.hb)) : 0.f;
         for (int j = 0; j < nlive; ++j) {
           const int32_t aj = __shfl(e.a, j, G), bj = __shfl(e.b, j, G);
           const float waj = __shfl(wa, j, G), wbj = __shfl(wb, j, G);
@@ -235,17 +226,12 @@ __global__ __launch_bounds__(kBlock) void walk_reject_kernel(
   for (int64_t T = int64_t(blockIdx.x) * gpb + grp; T < trials; T += int64_t(gridDim.x) * gpb) {
     const uint32_t tc0 = uint32_t(uint64_t(T) & 0xffffffffu);
     const uint32_t tc1 = uint32_t(uint64_t(T) >> 32) | 0x80000000u;
-    Edge e;
     uint32_t p0 = lemire_draw(k0, k1, tc0, tc1, ctr, 0u, uint32_t(nnz));
-    e.p = p0;
-    e.a = row_of(g.rowptr, n, e.p);
-    e.a0 = g.rowptr[e.a]; e.a1 = g.rowptr[e.a + 1];
-    e.b = g.col[e.p];
-    e.b0 = g.rowptr[e.b]; e.b1 = g.rowptr[e.b + 1];
-    e.sa = g.scale[e.a]; e.sb = g.scale[e.b];
-    edge_entries(e, g.val[e.p]);
+    const int32_t ra_ = row_of(g.rowptr, n, int64_t(p0));
+    int64_t rev_p = 0;
+    Edge e = first_edge(g, ra_, g.wn[ra_], int64_t(p0), &rev_p);
     const int32_t a1 = e.a, b1 = e.b;
-    const double h1a = e.ha, h1b = e.hb;
+    const float h1a = e.ha, h1b = e.hb;
     double rho = 1.0, accept_p = 1.0;
     float acc_a[VEC], acc_b[VEC];
 #pragma unroll
@@ -256,10 +242,9 @@ __global__ __launch_bounds__(kBlock) void walk_reject_kernel(
       if (i > 1) {
         uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
         uint32_t t = lemire_draw(k0, k1, tc0, tc1, ctr, uint32_t(i - 1), bound);
-        uint32_t degH;
-        double dot = move(g, e, t, &degH);
-        rho = rho * (dot * d_inc);
-        accept_p = (accept_p * double(degH)) / d_inc;
+        float dot = move(g, e, t, &rev_p);
+        rho = rho * (double(dot) * d_inc);
+        accept_p = (accept_p * double(bound)) / d_inc;
         double u = uniform53(k0, k1, tc0, tc1, ctr, uint32_t(ell + i));
         ok = u < accept_p;
       }
@@ -271,8 +256,8 @@ __global__ __launch_bounds__(kBlock) void walk_reject_kernel(
           VecIO<TX, VEC>::load(X + int64_t(e.a) * ldx + c0, xa);
           VecIO<TX, VEC>::load(X + int64_t(e.b) * ldx + c0, xb);
           const double base = cf.c[i] * scale * rho;
-          const float wa = float(base * e.ha), wb = float(base * e.hb);
-          const float fa = float(h1a), fb = float(h1b);
+          const float wa = float(base * double(e.ha)), wb = float(base * double(e.hb));
+          const float fa = h1a, fb = h1b;
 #pragma unroll
           for (int v = 0; v < VEC; ++v) {
             float val = fmaf(wa, xa[v], wb * xb[v]);
@@ -310,7 +295,7 @@ sped_status launch_is(const sped_csr *L, int64_t k, const void *X, int64_t ldx, 
   int ytiles = (lanes + 63) / 64;
   int G = lanes >= 64 ? 64 : next_pow2(lanes);
   int lgG = ilog2(G);
-  Graph g{L->rowptr, L->col, L->val, L->rev, L->scale};
+  Graph g{L->rowptr, L->wentry, L->wnode};
   const int64_t rows_per_block = kBlock >> lgG;
   const dim3 grid = dim3(unsigned((L->n + rows_per_block - 1) / rows_per_block), unsigned(ytiles));
 #define SPED_IS(V)                                                                                      \
@@ -333,7 +318,7 @@ sped_status launch_rej(const sped_csr *L, int64_t k, const void *X, int64_t ldx,
   int ytiles = (lanes + 63) / 64;
   int G = lanes >= 64 ? 64 : next_pow2(lanes);
   int lgG = ilog2(G);
-  Graph g{L->rowptr, L->col, L->val, L->rev, L->scale};
+  Graph g{L->rowptr, L->wentry, L->wnode};
   const int64_t total = L->n * k;
   int64_t iblocks = (total + kBlock - 1) / kBlock;
   if (iblocks > 4096) iblocks = 4096;
@@ -404,7 +389,7 @@ extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const doubl
   if ((xdt != SPED_F32 && xdt != SPED_BF16) || (ydt != SPED_F32 && ydt != SPED_BF16))
     return fail(SPED_E_UNSUPPORTED, "dtype");
   if (L->n > 0 && (!X || !Y)) return fail(SPED_E_INVALID, "X or Y NULL");
-  if (L->nnz > 0 && !L->rev) return fail(SPED_E_INVALID, "csr rev NULL");
+  if (L->nnz > 0 && (!L->wentry || !L->wnode)) return fail(SPED_E_INVALID, "csr walk records NULL");
   if (sampler != 0 && sampler != 1) return fail(SPED_E_INVALID, "sampler must be 0 or 1");
   if (walks < 1) return fail(SPED_E_INVALID, "walks < 1");
   if (counter >= (uint64_t(1) << 32)) return fail(SPED_E_INVALID, "counter >= 2^32");

@@ -30,7 +30,7 @@ _c_i32, _c_i64, _c_u64, _c_f64, _c_vp, _c_sz = (ctypes.c_int32, ctypes.c_int64, 
 class CSR(ctypes.Structure):
     _fields_ = [("n", _c_i64), ("nnz", _c_i64), ("rowptr", _c_vp), ("col", _c_vp), ("val", _c_vp),
                 ("rev", _c_vp), ("diag", _c_vp), ("scale", _c_vp), ("bins", _c_vp),
-                ("n_medium", _c_i64), ("n_heavy", _c_i64), ("max_degree", _c_i32), ("kind", _c_i32),
+                ("wentry", _c_vp), ("wnode", _c_vp), ("n_medium", _c_i64), ("n_heavy", _c_i64), ("max_degree", _c_i32), ("kind", _c_i32),
                 ("lambda_bound", _c_f64)]
 
 
@@ -177,10 +177,13 @@ class Laplacian:
         self.scale = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
         self.bins = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self.old_of_new = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        self.wentry = torch.empty(max(2 * m, 1) * 4, dtype=torch.int32, device=dev)   # 16-byte records
+        self.wnode = torch.empty(max(n, 1) * 2, dtype=torch.int64, device=dev)        # 16-byte records
         c = CSR()
         c.rowptr, c.col, c.val, c.rev = (self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
                                          self.rev.data_ptr())
         c.diag, c.scale, c.bins = self.diag.data_ptr(), self.scale.data_ptr(), self.bins.data_ptr()
+        c.wentry, c.wnode = self.wentry.data_ptr(), self.wnode.data_ptr()
         kind_i = {"sym": SYM_NORMALIZED, "combinatorial": COMBINATORIAL}[kind] if isinstance(kind, str) else kind
         self.kind = kind_i
         fn = lib().sped_laplacian_csr

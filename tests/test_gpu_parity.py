@@ -95,6 +95,16 @@ def test_laplacian_build(sped, kind, lcc):
     row_of = np.repeat(np.arange(L.n), np.diff(rowptr))
     np.testing.assert_array_equal(col[rev], row_of)
     np.testing.assert_array_equal(rev[rev], np.arange(L.nnz))
+    # packed walk records agree with the CSR arrays and the oracle's adjacency
+    we = L.wentry[: 4 * L.nnz].view(L.nnz, 4).cpu().numpy()
+    np.testing.assert_array_equal(we[:, 0], r_col)
+    np.testing.assert_array_equal(we[:, 1].view(np.float32), val)
+    np.testing.assert_array_equal(we[:, 2], rev - rowptr[r_col])
+    wn = L.wnode[: 2 * L.n].view(L.n, 2).cpu().numpy()
+    np.testing.assert_array_equal(wn[:, 0], rowptr[:-1])
+    np.testing.assert_array_equal((wn[:, 1] & 0xFFFFFFFF).astype(np.int64), np.diff(r_rowptr))
+    root = (wn[:, 1] >> 32).astype(np.uint32).view(np.float32)
+    np.testing.assert_allclose(root, np.sqrt(ref.scale), rtol=3 * U32)
     d = np.diff(rowptr)
     bins = L.bins[: L.n_medium + L.n_heavy].cpu().numpy()
     np.testing.assert_array_equal(bins[: L.n_medium], np.nonzero((d > sped.LIGHT_MAX) & (d <= sped.MEDIUM_MAX))[0])
