@@ -152,26 +152,56 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
         e.a = e.b = int32_t(r);
         e.ha = e.hb = 0.f;
       }
-      for (int i = 1; i <= ell; ++i) {
-        if (i > 1 && live) {
-          uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
-          uint32_t t = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(i - 1), bound);
-          float dot = move(g, e, t, &rev_p);
-          omega = omega * double(dot) * double(bound);
-        }
-        const double ci = cf.c[i] * omega;
-        const float wa = live ? float(ci * double(e.ha)) : 0.f;
-        const float wb = live ? float(ci * double(e.hb)) : 0.f;
-        for (int j = 0; j < nlive; ++j) {
-          const int32_t aj = __shfl(e.a, j, G), bj = __shfl(e.b, j, G);
-          const float waj = __shfl(wa, j, G), wbj = __shfl(wb, j, G);
-          if (col_ok) {
-            float xa[VEC], xb[VEC];
-            VecIO<TX, VEC>::load(X + int64_t(aj) * ldx + c0, xa);
-            VecIO<TX, VEC>::load(X + int64_t(bj) * ldx + c0, xb);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(waj, xa[v], fmaf(wbj, xb[v], acc[v]));
+      // Coefficients of X[e.a] and X[e.b] not yet gathered.  Consecutive edges
+      // of a walk share a node, so a node's row is gathered once, when the
+      // walk leaves it (and both at the end): one row gather per step.
+      double pa = live ? cf.c[1] * omega * double(e.ha) : 0.0;
+      double pb = live ? cf.c[1] * omega * double(e.hb) : 0.0;
+      for (int i = 2; i <= ell + 1; ++i) {
+        int32_t leave = e.a;
+        double wleave = 0.0;
+        if (i <= ell) {
+          if (live) {
+            uint32_t bound = uint32_t((e.a1 - e.a0) + (e.b1 - e.b0) - 1);
+            uint32_t t = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(i - 1), bound);
+            const int32_t oa = e.a, ob = e.b;
+            float dot = move(g, e, t, &rev_p);
+            omega = omega * double(dot) * double(bound);
+            const double ci = cf.c[i] * omega;
+            if (e.a == oa && e.b == ob) {  // stayed on the same edge
+              pa += ci * double(e.ha);
+              pb += ci * double(e.hb);
+            } else {                        // kept node e.a, left the other one
+              const bool kept_a = e.a == oa;
+              leave = kept_a ? ob : oa;
+              wleave = kept_a ? pb : pa;
+              pa = (kept_a ? pa : pb) + ci * double(e.ha);
+              pb = ci * double(e.hb);
+            }
           }
+        } else {  // after the last prefix: flush both endpoints (second one below)
+          leave = e.a;
+          wleave = pa;
+        }
+        for (int j = 0; j < nlive; ++j) {
+          const float wj = __shfl(float(wleave), j, G);
+          const int32_t nj = __shfl(leave, j, G);
+          if (col_ok && wj != 0.f) {
+            float xv[VEC];
+            VecIO<TX, VEC>::load(X + int64_t(nj) * ldx + c0, xv);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wj, xv[v], acc[v]);
+          }
+        }
+      }
+      for (int j = 0; j < nlive; ++j) {
+        const float wj = __shfl(float(pb), j, G);
+        const int32_t nj = __shfl(e.b, j, G);
+        if (col_ok && wj != 0.f) {
+          float xv[VEC];
+          VecIO<TX, VEC>::load(X + int64_t(nj) * ldx + c0, xv);
+#pragma unroll
+          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wj, xv[v], acc[v]);
         }
       }
     }
