@@ -269,7 +269,8 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  * M = lambda_bound I - L), Cholesky-QR2 after every application, and a
  * Rayleigh-Ritz step on L every check_every iterations.  The block carries
  * k + guard columns; the stopping test is
- *     ||R||_F / (theta_k - ||r_k|| - theta_{k-1}) <= tol,   R = [L q_i - theta_i q_i]_{i<k}
+ *     rho / (theta_k - ||r_k|| - theta_{k-1}) <= tol,   R = [L q_i - theta_i q_i]_{i<k}
+ * with rho = sqrt(min(||R^T R||_inf, ||R||_F^2)) >= ||R||_2 (R^T R in float64)
  * (a Davis-Kahan bound on the sine of the largest angle to the true bottom-k
  * subspace; the gap is estimated from the first guard Ritz value theta_k
  * lowered by its residual r_k; guard >= 1).
@@ -305,7 +306,7 @@ typedef struct {
   double seconds;          /* wall time inside the call */
   double max_residual;
   double gap_estimate;
-  double bound;            /* the stopping quantity at exit */
+  double bound;            /* the stopping quantity at exit (rho / gap) */
   int32_t converged;
   int32_t cholqr_shifts;   /* breakdowns repaired by the shift */
   int32_t coarse_iters;    /* iterations done with BF16 storage */

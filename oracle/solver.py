@@ -59,8 +59,11 @@ def eigenvector_streak(Vstar, Q, eps: float = np.pi / 8) -> int:
     return streak
 
 
-def rayleigh_ritz(L, Q):
-    """Ritz pairs of L on span(Q): H = Q^T L Q = S Theta S^T (ascending)."""
+def rayleigh_ritz(L, Q, return_block: bool = False):
+    """Ritz pairs of L on span(Q): H = Q^T L Q = S Theta S^T (ascending).
+
+    Returns (theta, Q S, residual norms), plus the residual block
+    R = L Q S - Q S Theta when return_block is set."""
     Z = L @ Q
     H = Q.T @ Z
     H = 0.5 * (H + H.T)
@@ -68,7 +71,17 @@ def rayleigh_ritz(L, Q):
     Q = Q @ S
     Z = Z @ S
     R = Z - Q * theta
+    if return_block:
+        return theta, Q, np.linalg.norm(R, axis=0), R
     return theta, Q, np.linalg.norm(R, axis=0)
+
+
+def residual_norm_bound(R) -> float:
+    """rho = sqrt(min(||R^T R||_inf, ||R||_F^2)), an upper bound on ||R||_2:
+    the largest eigenvalue of the Gram matrix G = R^T R is at most any induced
+    norm of G (the infinity norm here) and at most its trace."""
+    G = R.T @ R
+    return float(np.sqrt(min(np.abs(G).sum(axis=1).max(), np.trace(G))))
 
 
 @dataclass
@@ -86,10 +99,12 @@ def subspace_iteration(L, apply_M, k: int, V0, max_iters: int, tol: float = 0.0,
                        guard: int = 0):
     """Block subspace iteration (eta = inf) or block Oja (finite eta) on M.
 
-    Iterates with k + guard columns; stops when the Frobenius norm of the first
-    k Ritz residuals divided by the gap estimate theta_{k+1} - ||r_{k+1}|| -
-    theta_k (guard > 0) or by 1 (guard = 0) is <= tol (Davis-Kahan).  With Vstar given, records the largest
-    principal angle and the subspace error after each check."""
+    Iterates with k + guard columns; stops when residual_norm_bound of the
+    first k Ritz residual columns (an upper bound on their spectral norm)
+    divided by the gap estimate theta_{k+1} - ||r_{k+1}|| - theta_k
+    (guard > 0) or by 1 (guard = 0) is <= tol (Davis-Kahan).  With Vstar
+    given, records the largest principal angle and the subspace error after
+    each check."""
     Q = orthonormal(V0)
     hist = []
     theta = res = None
@@ -99,9 +114,9 @@ def subspace_iteration(L, apply_M, k: int, V0, max_iters: int, tol: float = 0.0,
             W = Q + eta * W
         Q = orthonormal(W)
         if t % check_every == 0 or t == max_iters:
-            theta, Q, res = rayleigh_ritz(L, Q)
+            theta, Q, res, R = rayleigh_ritz(L, Q, return_block=True)
             gap = (theta[k] - res[k] - theta[k - 1]) if guard > 0 else 1.0
-            bound = float(np.linalg.norm(res[:k]) / max(gap, 1e-300))
+            bound = residual_norm_bound(R[:, :k]) / max(gap, 1e-300)
             rec = {"iter": t, "bound": bound, "max_residual": float(np.max(res[:k]))}
             if Vstar is not None:
                 rec["angle"] = max_principal_angle(Vstar, Q[:, :k])

@@ -326,9 +326,12 @@ sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, i
                         int tb, double *G, double *partials, hipStream_t s);
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
                         void *O, int64_t ldo, int to, hipStream_t s);
-size_t resid_ws_doubles(int64_t k);
-sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const void *Q, int64_t ldq, int tq,
-                         const double *theta, double *resid, double *partials, hipStream_t s);
+// G = R^T R for R = Z - Q diag(theta) (k columns, shared leading dimension
+// ld), resid[i] = ||R e_i||, *norm2 >= ||R||_2 of the first kn columns.
+// partials as for the symmetric Gram of width k.
+sped_status launch_resid(int64_t n, int k, int kn, const float *Z, const void *Q, int64_t ld, int tq,
+                         const double *theta, double *G, double *resid, double *norm2, double *partials,
+                         hipStream_t s);
 
 // dense.hip (flags: [0] Cholesky shifts, [1] Cholesky failures, [2] Jacobi caps)
 int dense_max_k();

@@ -3,7 +3,8 @@
 //          (v_mfma_f64_16x16x4f64), one 16x16 output tile per MFMA chain;
 //   tsmm   O = X T for a small k_in x k_out matrix T (float64 in memory, float
 //          in LDS), one lane group per row like the sparse step;
-//   resid  per-column ||Z_i - theta_i Q_i||_2 in float64.
+//   resid  R^T R for R = Z - Q diag(theta) formed on the fly (same Gram
+//          kernels), column norms and an upper bound on ||R||_2.
 // Split over rows, every block writes its own partial; a second pass adds the
 // partials in a fixed order, so results are bitwise reproducible.
 #include "common.h"
@@ -24,6 +25,31 @@ __device__ inline double load_as_double<float>(const float *p) { return double(*
 template <>
 __device__ inline double load_as_double<bf16_t>(const bf16_t *p) { return double(bf16_to_f32(*p)); }
 
+// Operand loaders of the Gram kernels: element (row, c) of the left and right
+// factors, converted to float64.
+template <typename T1, typename T2>
+struct PlainLoad {
+  const T1 *A;
+  int64_t lda;
+  const T2 *B;
+  int64_t ldb;
+  __device__ double a(int64_t r, int c) const { return load_as_double(A + r * lda + c); }
+  __device__ double b(int64_t r, int c) const { return load_as_double(B + r * ldb + c); }
+};
+
+// Residual block R = Z - Q diag(theta) formed on the fly (both factors are R).
+template <typename TQ>
+struct ResidLoad {
+  const float *Z;
+  const TQ *Q;
+  int64_t ld;
+  const double *theta;
+  __device__ double a(int64_t r, int c) const {
+    return double(Z[r * ld + c]) - theta[c] * load_as_double(Q + r * ld + c);
+  }
+  __device__ double b(int64_t r, int c) const { return a(r, c); }
+};
+
 // Each wavefront streams its rows straight from global memory (16 rows per
 // round: lane (li, lk) reads element [row + 4u + lk][16 tile + li], u = 0..3)
 // into float64 MFMA operands; no LDS and no barriers.  With few output tiles
@@ -32,9 +58,8 @@ __device__ inline double load_as_double<bf16_t>(const bf16_t *p) { return double
 // round-robin to the 4 wavefronts, which all read the block's rows (their
 // shared lines come from L1) and write disjoint tiles of one partial.  With
 // SYM (A == B) only tiles p <= q are formed and mirrored on output.
-template <typename T1, typename T2, int MAXT, bool SYM, bool ROWSPLIT>
-__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, const T1 *__restrict__ A,
-                                                      int64_t lda, const T2 *__restrict__ B, int64_t ldb,
+template <typename LD, int MAXT, bool SYM, bool ROWSPLIT>
+__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, LD ld,
                                                       int64_t rows_per_block, double *__restrict__ partials) {
   constexpr int KU = MAXT <= 4 ? 4 : 1;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
@@ -74,8 +99,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
         a[u][t] = b[u][t] = 0.0;
         if (t < nt && rok) {
           const int ca = tp[t] * 16 + li, cb = tq[t] * 16 + li;
-          if (ca < ka) a[u][t] = load_as_double(A + row * lda + ca);
-          if (cb < kb) b[u][t] = load_as_double(B + row * ldb + cb);
+          if (ca < ka) a[u][t] = ld.a(row, ca);
+          if (cb < kb) b[u][t] = ld.b(row, cb);
         }
       }
     }
@@ -117,10 +142,8 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
 // wavefronts then add their tiles into one LDS copy in wavefront order (fixed
 // order: deterministic) and the block writes one partial.
 constexpr int kNarrowBlock = 1024;
-template <typename T1, typename T2, int TA, int TB, bool SYM>
-__global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, int ka, int kb,
-                                                                   const T1 *__restrict__ A, int64_t lda,
-                                                                   const T2 *__restrict__ B, int64_t ldb,
+template <typename LD, int TA, int TB, bool SYM>
+__global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, int ka, int kb, LD ld,
                                                                    int64_t rows_per_block,
                                                                    double *__restrict__ partials) {
   constexpr int KU = 4;
@@ -144,13 +167,13 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
 #pragma unroll
       for (int p = 0; p < TA; ++p) {
         const int c = p * 16 + li;
-        fa[u][p] = (rok && c < ka) ? load_as_double(A + row * lda + c) : 0.0;
+        fa[u][p] = (rok && c < ka) ? ld.a(row, c) : 0.0;
       }
       if (!SYM) {
 #pragma unroll
         for (int q = 0; q < TB; ++q) {
           const int c = q * 16 + li;
-          fb[u][q] = (rok && c < kb) ? load_as_double(B + row * ldb + c) : 0.0;
+          fb[u][q] = (rok && c < kb) ? ld.b(row, c) : 0.0;
         }
       }
     }
@@ -244,36 +267,6 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int ko
   VecIO<TO, VEC>::store(O + row * ldo + c0, o);
 }
 
-// partial[b][c] = sum over this block's rows of (Z[r,c] - theta[c] Q[r,c])^2
-template <typename TQ>
-__global__ __launch_bounds__(kBlock) void resid_kernel(int64_t n, int k, const float *__restrict__ Z, int64_t ldz,
-                                                        const TQ *__restrict__ Q, int64_t ldq,
-                                                        const double *__restrict__ theta,
-                                                        double *__restrict__ partials) {
-  // thread layout: column c = threadIdx.x % kc, row lane = threadIdx.x / kc
-  const int kc = k <= kBlock ? k : kBlock;
-  const int rl = threadIdx.x / kc, nrl = kBlock / kc;
-  const int c = threadIdx.x - rl * kc;
-  __shared__ double red[kBlock];
-  double s = 0.0;
-  if (rl < nrl) {
-    const double th = theta[c];
-    for (int64_t r = int64_t(blockIdx.x) * nrl + rl; r < n; r += int64_t(gridDim.x) * nrl) {
-      double d = double(Z[r * ldz + c]) - th * double(to_f32<TQ>(Q[r * ldq + c]));
-      s += d * d;
-    }
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (threadIdx.x < kc) {
-    double t = 0.0;
-    for (int i = 0; i < nrl; ++i) t += red[i * kc + threadIdx.x];
-    partials[int64_t(blockIdx.x) * k + threadIdx.x] = t;
-  }
-}
-
-
-constexpr int kResidBlocks = 512;
 
 struct GramPlan {
   int nblocks, nparts, maxt;
@@ -304,43 +297,77 @@ GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
   return p;
 }
 
-template <typename T1, typename T2, int MAXT, bool SYM, bool RS>
-sped_status launch_gram_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
-                          double *partials, const GramPlan &p, hipStream_t s) {
-  hipLaunchKernelGGL((gram_kernel<T1, T2, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb,
-                     static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb, p.rows_per_block, partials);
+template <typename LD, int MAXT, bool SYM, bool RS>
+sped_status launch_gram_t(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
+                          hipStream_t s) {
+  hipLaunchKernelGGL((gram_kernel<LD, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb, ld,
+                     p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
 
-template <typename T1, typename T2, int TA, int TB, bool SYM>
-sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
-                                 double *partials, const GramPlan &p, hipStream_t s) {
-  hipLaunchKernelGGL((gram_narrow_kernel<T1, T2, TA, TB, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb,
-                     static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb, p.rows_per_block, partials);
+template <typename LD, int TA, int TB, bool SYM>
+sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL((gram_narrow_kernel<LD, TA, TB, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb,
+                     ld, p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
+}
+
+template <typename LD, bool SYM>
+sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
+                             hipStream_t s) {
+  if (p.narrow) {
+    const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
+    if (TA == 1 && TB == 1) return launch_gram_narrow_t<LD, 1, 1, SYM>(n, ka, kb, ld, partials, p, s);
+    if (TA == 1 && TB == 2) return launch_gram_narrow_t<LD, 1, 2, SYM>(n, ka, kb, ld, partials, p, s);
+    if (TA == 2 && TB == 1) return launch_gram_narrow_t<LD, 2, 1, SYM>(n, ka, kb, ld, partials, p, s);
+    return launch_gram_narrow_t<LD, 2, 2, SYM>(n, ka, kb, ld, partials, p, s);
+  }
+  if (p.rowsplit) {
+    if (p.maxt <= 1) return launch_gram_t<LD, 1, SYM, true>(n, ka, kb, ld, partials, p, s);
+    if (p.maxt <= 2) return launch_gram_t<LD, 2, SYM, true>(n, ka, kb, ld, partials, p, s);
+    return launch_gram_t<LD, 4, SYM, true>(n, ka, kb, ld, partials, p, s);
+  }
+  if (p.maxt <= 2) return launch_gram_t<LD, 2, SYM, false>(n, ka, kb, ld, partials, p, s);
+  if (p.maxt <= 4) return launch_gram_t<LD, 4, SYM, false>(n, ka, kb, ld, partials, p, s);
+  if (p.maxt <= 8) return launch_gram_t<LD, 8, SYM, false>(n, ka, kb, ld, partials, p, s);
+  return launch_gram_t<LD, 16, SYM, false>(n, ka, kb, ld, partials, p, s);
 }
 
 template <typename T1, typename T2, bool SYM>
-sped_status launch_gram_maxt(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B,
-                             int64_t ldb, double *partials, const GramPlan &p, hipStream_t s) {
-  if (p.narrow) {
-    const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-    if (TA == 1 && TB == 1) return launch_gram_narrow_t<T1, T2, 1, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (TA == 1 && TB == 2) return launch_gram_narrow_t<T1, T2, 1, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (TA == 2 && TB == 1) return launch_gram_narrow_t<T1, T2, 2, 1, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    return launch_gram_narrow_t<T1, T2, 2, 2, SYM>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+sped_status launch_gram_plain(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
+                              double *partials, const GramPlan &p, hipStream_t s) {
+  PlainLoad<T1, T2> ld{static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb};
+  return launch_gram_maxt<PlainLoad<T1, T2>, SYM>(n, ka, kb, ld, partials, p, s);
+}
+
+// From G = R^T R (k x k): resid[i] = sqrt(G_ii) for i < k, and
+// *norm2 = sqrt(min(max_{i<kn} sum_{j<kn} |G_ij|, sum_{i<kn} G_ii)), an upper
+// bound on the spectral norm of the first kn columns of R (the largest
+// eigenvalue of their Gram block is at most both its infinity norm and its
+// trace).
+__global__ void resid_norms_kernel(int k, int kn, const double *__restrict__ G, double *__restrict__ resid,
+                                   double *__restrict__ norm2) {
+  __shared__ double rs[kBlock];
+  double best = 0.0;
+  for (int i = threadIdx.x; i < k; i += kBlock) {
+    resid[i] = sqrt(fmax(G[i * k + i], 0.0));
+    if (i < kn) {
+      double sum = 0.0;
+      for (int j = 0; j < kn; ++j) sum += fabs(G[i * k + j]);
+      best = fmax(best, sum);
+    }
   }
-  if (p.rowsplit) {
-    if (p.maxt <= 1) return launch_gram_t<T1, T2, 1, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    if (p.maxt <= 2) return launch_gram_t<T1, T2, 2, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-    return launch_gram_t<T1, T2, 4, SYM, true>(n, ka, kb, A, lda, B, ldb, partials, p, s);
+  rs[threadIdx.x] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0, tr = 0.0;
+    for (int i = 0; i < kBlock; ++i) m = fmax(m, rs[i]);
+    for (int i = 0; i < kn; ++i) tr += fmax(G[i * k + i], 0.0);
+    *norm2 = sqrt(fmin(m, tr));
   }
-  if (p.maxt <= 2) return launch_gram_t<T1, T2, 2, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  if (p.maxt <= 4) return launch_gram_t<T1, T2, 4, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  if (p.maxt <= 8) return launch_gram_t<T1, T2, 8, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
-  return launch_gram_t<T1, T2, 16, SYM, false>(n, ka, kb, A, lda, B, ldb, partials, p, s);
 }
 
 template <typename TX, typename TO>
@@ -386,16 +413,16 @@ sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, i
   if ((ta != SPED_F32 && ta != SPED_BF16) || (tb != SPED_F32 && tb != SPED_BF16))
     return fail(SPED_E_UNSUPPORTED, "gram dtype");
   if (sym)
-    st = a32 ? launch_gram_maxt<float, float, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
-             : launch_gram_maxt<bf16_t, bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+    st = a32 ? launch_gram_plain<float, float, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s)
+             : launch_gram_plain<bf16_t, bf16_t, true>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else if (a32 && b32)
-    st = launch_gram_maxt<float, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+    st = launch_gram_plain<float, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else if (!a32 && !b32)
-    st = launch_gram_maxt<bf16_t, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+    st = launch_gram_plain<bf16_t, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else if (!a32 && b32)
-    st = launch_gram_maxt<bf16_t, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+    st = launch_gram_plain<bf16_t, float, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   else
-    st = launch_gram_maxt<float, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
+    st = launch_gram_plain<float, bf16_t, false>(n, ka, kb, A, lda, B, ldb, partials, plan, s);
   if (st != SPED_OK) return st;
   return launch_sum_partials(partials, plan.nparts, int64_t(ka) * kb, G, false, s);
 }
@@ -410,19 +437,25 @@ sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx
   return fail(SPED_E_UNSUPPORTED, "tsmm dtype");
 }
 
-size_t resid_ws_doubles(int64_t k) { return size_t(kResidBlocks) * k; }
 
-sped_status launch_resid(int64_t n, int k, const float *Z, int64_t ldz, const void *Q, int64_t ldq, int tq,
-                         const double *theta, double *resid, double *partials, hipStream_t s) {
-  if (k > kBlock) return fail(SPED_E_UNSUPPORTED, "resid width > 256");
-  if (tq == SPED_F32)
-    hipLaunchKernelGGL(resid_kernel<float>, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz,
-                       static_cast<const float *>(Q), ldq, theta, partials);
-  else
-    hipLaunchKernelGGL(resid_kernel<bf16_t>, dim3(kResidBlocks), dim3(kBlock), 0, s, n, k, Z, ldz,
-                       static_cast<const bf16_t *>(Q), ldq, theta, partials);
+sped_status launch_resid(int64_t n, int k, int kn, const float *Z, const void *Q, int64_t ld, int tq,
+                         const double *theta, double *G, double *resid, double *norm2, double *partials,
+                         hipStream_t s) {
+  if (k < 1 || k > kMaxK || kn < 1 || kn > k) return fail(SPED_E_UNSUPPORTED, "resid width outside [1, 128]");
+  const GramPlan plan = gram_plan(n, k, k, true);
+  sped_status st;
+  if (tq == SPED_F32) {
+    ResidLoad<float> ld_{Z, static_cast<const float *>(Q), ld, theta};
+    st = launch_gram_maxt<ResidLoad<float>, true>(n, k, k, ld_, partials, plan, s);
+  } else {
+    ResidLoad<bf16_t> ld_{Z, static_cast<const bf16_t *>(Q), ld, theta};
+    st = launch_gram_maxt<ResidLoad<bf16_t>, true>(n, k, k, ld_, partials, plan, s);
+  }
+  if (st != SPED_OK) return st;
+  SPED_TRY(launch_sum_partials(partials, plan.nparts, int64_t(k) * k, G, false, s));
+  hipLaunchKernelGGL(resid_norms_kernel, dim3(1), dim3(kBlock), 0, s, k, kn, G, resid, norm2);
   SPED_CHECK_HIP(hipGetLastError());
-  return launch_sum_partials(partials, kResidBlocks, k, resid, true, s);
+  return SPED_OK;
 }
 
 }  // namespace sped

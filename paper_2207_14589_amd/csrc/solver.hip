@@ -3,7 +3,8 @@
 //   W = M Q                 M = p(L), or lambda_bound I - L for the plain solver
 //   Q = W R^{-1}            Cholesky QR (twice by default), float64 Gram
 //   every c iterations:     Rayleigh-Ritz on L: Z = L Q, H = Q^T Z = S Theta S^T,
-//                           Q <- Q S, residuals ||Z s_i - theta_i q_i||
+//                           Q <- Q S, residual block R = Z S - Q Theta and its
+//                           float64 Gram R^T R (column norms, ||R||_2 bound)
 // Block Oja with step eta iterates on M + I/eta (the same subspace update).
 // The host loop only reads 2(k + guard) doubles and 3 flags per check.
 #include <chrono>
@@ -71,14 +72,15 @@ sped_status cholqr(int64_t n, int k, const void *W, void *Q, int64_t ld, int dt,
 struct RRWs {
   float *Z, *ZS;
   void *Qtmp;
-  double *H, *S, *theta, *resid, *partials, *rpartials;
+  double *H, *S, *theta, *resid, *partials, *G, *norm2;
   int *flags;
 };
 
 // Rayleigh-Ritz of L on span(Q) (Q of storage type dt, Z = L Q in float32);
-// the Ritz vectors are written to Qtmp.
-sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, const void *Q, int64_t ld, int dt, const RRWs &w,
-                          hipStream_t s) {
+// the Ritz vectors are written to Qtmp, the residual Gram to w.G, and
+// *w.norm2 bounds the spectral norm of the first kn residual columns.
+sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, int kn, const void *Q, int64_t ld, int dt,
+                          const RRWs &w, hipStream_t s) {
   StepArgs a{};
   a.U = Q; a.ldu = ld; a.tu = dt;
   a.V = nullptr; a.ldv = ld; a.tv = dt;
@@ -89,7 +91,7 @@ sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, const void *Q, in
   SPED_TRY(launch_jacobi(k, w.H, w.theta, w.S, w.flags, s));
   SPED_TRY(launch_tsmm(n, k, k, Q, ld, dt, w.S, w.Qtmp, ld, dt, s));
   SPED_TRY(launch_tsmm(n, k, k, w.Z, ld, SPED_F32, w.S, w.ZS, ld, SPED_F32, s));
-  SPED_TRY(launch_resid(n, k, w.ZS, ld, w.Qtmp, ld, dt, w.theta, w.resid, w.rpartials, s));
+  SPED_TRY(launch_resid(n, k, kn, w.ZS, w.Qtmp, ld, dt, w.theta, w.G, w.resid, w.norm2, w.partials, s));
   return SPED_OK;
 }
 
@@ -147,7 +149,8 @@ extern "C" sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q,
   w.theta = theta;
   w.resid = resid;
   w.partials = c.take<double>(gram_ws_doubles(n, k, k));
-  w.rpartials = c.take<double>(resid_ws_doubles(k));
+  w.G = c.take<double>(size_t(k) * k);
+  w.norm2 = c.take<double>(1);
   w.flags = c.take<int>(4);
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
@@ -155,7 +158,7 @@ extern "C" sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q,
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
-  SPED_TRY(rayleigh_ritz(L, n, int(k), Q, ldq, SPED_F32, w, s));
+  SPED_TRY(rayleigh_ritz(L, n, int(k), int(k), Q, ldq, SPED_F32, w, s));
   SPED_TRY(copy_block(n, int(k), w.Qtmp, ldq, SPED_F32, Q, ldq, SPED_F32, s));
   return SPED_OK;
 }
@@ -224,7 +227,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   rw.S = c.take<double>(size_t(kb) * kb);
   rw.theta = c.take<double>(size_t(kb));
   rw.resid = c.take<double>(size_t(kb));
-  rw.rpartials = c.take<double>(resid_ws_doubles(kb));
+  rw.G = c.take<double>(size_t(kb) * kb);
+  rw.norm2 = c.take<double>(1);
   rw.partials = ow.partials;
   int *flags = c.take<int>(4);
   ow.flags = rw.flags = flags;
@@ -239,6 +243,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   SPED_CHECK_HIP(hipGetLastError());
 
   std::vector<double> h_theta(kb), h_resid(kb);
+  double h_norm2 = 0.0;
   int h_flags[4] = {0, 0, 0, 0};
   int t = 0;
   // One phase of iterations with the iterate stored as dt in (Q, W); returns
@@ -264,19 +269,19 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
         rw.Z = bufA;
         rw.ZS = bufB;
         rw.Qtmp = W;
-        SPED_TRY(rayleigh_ritz(L, n, int(kb), Q, kb, dt, rw, s));
+        SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), Q, kb, dt, rw, s));
         std::swap(Q, W);  // Ritz vectors now in Q
         stats.spmm_count += 1;
         SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
+        SPED_CHECK_HIP(hipMemcpyAsync(&h_norm2, rw.norm2, sizeof(double), hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipStreamSynchronize(s));
         if (h_flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
-        double rmax = 0.0, rf2 = 0.0;
-        bool finite = true;
+        double rmax = 0.0;
+        bool finite = std::isfinite(h_norm2);
         for (int i = 0; i < k; ++i) {
           rmax = std::max(rmax, h_resid[i]);
-          rf2 += h_resid[i] * h_resid[i];
           finite = finite && std::isfinite(h_resid[i]) && std::isfinite(h_theta[i]);
         }
         if (!finite) return fail(SPED_E_NUMERIC, "non-finite Ritz value or residual");
@@ -285,8 +290,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
         double gap = h_theta[k] - h_resid[k] - h_theta[k - 1];
         stats.gap_estimate = gap;
         stats.max_residual = rmax;
-        // Davis-Kahan: sin of the largest angle <= ||R||_2 / gap <= ||R||_F / gap
-        stats.bound = gap > 0 ? std::sqrt(rf2) / gap : INFINITY;
+        // Davis-Kahan: sin of the largest angle <= ||R||_2 / gap, with
+        // ||R||_2 <= sqrt(min(||R^T R||_inf, ||R||_F^2)); the infinity norm is
+        // the tighter one when the residual columns are nearly orthogonal
+        stats.bound = gap > 0 ? h_norm2 / gap : INFINITY;
         if (stats.bound <= tol) {
           *done = true;
           return SPED_OK;

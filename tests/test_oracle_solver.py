@@ -31,6 +31,38 @@ def test_metrics_known_angles():
     assert osol.eigenvector_streak(A, B, eps=0.5) == 3
 
 
+def test_residual_norm_bound_cases():
+    """rho >= ||R||_2 always, <= ||R||_F, and exact for orthogonal columns
+    (||R||_2 is then the largest column norm) and for rank one."""
+    g = np.random.default_rng(3)
+    for _ in range(20):
+        R = g.standard_normal((40, 6)) * g.uniform(0.1, 3.0, 6)
+        rho = osol.residual_norm_bound(R)
+        assert np.linalg.norm(R, 2) <= rho * (1 + 1e-12)
+        assert rho <= np.linalg.norm(R) * (1 + 1e-12)
+    Q, _ = np.linalg.qr(g.standard_normal((40, 5)))
+    D = Q * np.array([0.5, 2.0, 1.0, 0.1, 1.5])
+    assert osol.residual_norm_bound(D) == pytest.approx(2.0, rel=1e-12)
+    u, v = g.standard_normal(40), g.standard_normal(5)
+    assert osol.residual_norm_bound(np.outer(u, v)) == pytest.approx(
+        np.linalg.norm(u) * np.linalg.norm(v), rel=1e-12)
+
+
+def test_stop_bound_dominates_true_angle(sbm2000):
+    """Davis-Kahan: at every check the stopping quantity is at least the sine
+    of the largest principal angle to the true bottom-k subspace."""
+    lap, labels, lam, U, full = sbm2000
+    k = 10
+    V0 = synth.gaussian_block(lap.n, k + 4, 4)
+    res = osol.subspace_iteration(lap.L, lambda Q: opoly.apply_terms(lap.L, opoly.limit_exp(8), Q), k, V0,
+                                  max_iters=120, tol=0.0, guard=4, Vstar=U)
+    # above the float64 floor of the dense reference itself (~1e-14)
+    checked = [h for h in res.history if 1e-12 < h["bound"] < 1.0]
+    assert len(checked) > 10
+    for h in checked:
+        assert np.sin(h["angle"]) <= h["bound"] * (1 + 1e-9)
+
+
 @pytest.fixture(scope="module")
 def sbm2000():
     n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
