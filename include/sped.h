@@ -70,13 +70,19 @@ typedef enum {
  */
 #define SPED_LIGHT_MAX 128
 #define SPED_MEDIUM_MAX 8192
-/* Packed records read by the walk estimators: one 16-byte load per move.
- *  sped_walk_entry[p] = (col[p], val[p], rev[p] - rowptr[col[p]], 0)
+/* Packed records read by the walk estimators.  An entry record carries what a
+ * walk needs about the entry's far endpoint v = col[p], so a move is one
+ * 32-byte load (one cache line):
+ *  sped_walk_entry[p] = (v, val[p], rev[p] - rowptr[v], rowptr[v+1] - rowptr[v],
+ *                        rowptr[v], sqrt(scale[v]), 0)
  *  sped_walk_node[u]  = (rowptr[u], rowptr[u+1] - rowptr[u], sqrt(scale[u])) */
 typedef struct {
   int32_t col;
   float val;
   int32_t rev_local;
+  int32_t degree;     /* of col */
+  int64_t start;      /* rowptr[col] */
+  float root_scale;   /* sqrt(scale[col]) */
   int32_t pad;
 } sped_walk_entry;
 typedef struct {

@@ -220,13 +220,17 @@ __global__ void reverse_positions(int64_t nnz, const uint64_t *__restrict__ keys
 
 __global__ void walk_entry_records(int64_t nnz, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                    const float *__restrict__ val, const int64_t *__restrict__ rev,
-                                   sped_walk_entry *__restrict__ we) {
+                                   const float *__restrict__ scale, sped_walk_entry *__restrict__ we) {
   GRID_STRIDE(p, nnz) {
     const int32_t c = col[p];
+    const int64_t c0 = rowptr[c];
     sped_walk_entry e;
     e.col = c;
     e.val = val[p];
-    e.rev_local = int32_t(rev[p] - rowptr[c]);
+    e.rev_local = int32_t(rev[p] - c0);
+    e.degree = int32_t(rowptr[c + 1] - c0);
+    e.start = c0;
+    e.root_scale = sqrtf(scale[c]);
     e.pad = 0;
     we[p] = e;
   }
@@ -443,7 +447,7 @@ extern "C" sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *s
     }
     if (out->wentry && nnz > 0) {
       hipLaunchKernelGGL(walk_entry_records, dim3(grid_for(nnz)), dim3(kBlock), 0, s, nnz, out->rowptr, out->col,
-                         out->val, out->rev, out->wentry);
+                         out->val, out->rev, out->scale, out->wentry);
       SPED_CHECK_HIP(hipGetLastError());
     }
     if (out->wnode) {

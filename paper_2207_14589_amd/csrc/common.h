@@ -12,6 +12,10 @@
 
 namespace sped {
 
+// the walk estimators read an entry record with one 32-byte load
+static_assert(sizeof(sped_walk_entry) == 32 && alignof(sped_walk_entry) == 8, "walk entry layout");
+static_assert(sizeof(sped_walk_node) == 16, "walk node layout");
+
 // ---------------------------------------------------------------- errors
 sped_status fail(sped_status st, const std::string &msg);
 void clear_error();

@@ -74,57 +74,110 @@ __device__ inline void edge_entries(Edge &e, float val) {
 // receives the position of the edge's copy in the other endpoint's row.
 __device__ inline Edge first_edge(const Graph &g, int32_t r, const sped_walk_node &nr, int64_t p, int64_t *rev_p) {
   const sped_walk_entry en = g.we[p];
-  const sped_walk_node nb = g.wn[en.col];
   Edge e;
   e.p = p;
   e.a = r; e.a0 = nr.start; e.a1 = nr.start + nr.degree; e.ra = nr.root_scale;
-  e.b = en.col; e.b0 = nb.start; e.b1 = nb.start + nb.degree; e.rb = nb.root_scale;
+  e.b = en.col; e.b0 = en.start; e.b1 = en.start + en.degree; e.rb = en.root_scale;
   edge_entries(e, en.val);
-  *rev_p = nb.start + en.rev_local;
+  *rev_p = en.start + en.rev_local;
   return e;
 }
 
-// Move along H to neighbour number t of e (t < deg_H(e) = d_a + d_b - 1):
-// t < d_a picks entry t of row a (t = p - a0 is e itself, H's self-loop),
-// otherwise entry t - d_a of row b skipping b's copy of e at *rev_p.  Two
-// dependent 16-byte loads (entry record, then node record); *rev_p is updated
-// for the new edge.  Returns x_e^T x_f.
-__device__ inline float move(const Graph &g, Edge &e, uint32_t t, int64_t *rev_p) {
+// Neighbour number t of e on H (t < deg_H(e) = d_a + d_b - 1): t < d_a picks
+// entry t of row a (t = p - a0 is e itself, H's self-loop), otherwise entry
+// t - d_a of row b, skipping b's copy of e at rev_p.  Returns the entry's CSR
+// position; *fa tells whether it lies in row a.
+__device__ inline int64_t pick(const Edge &e, uint32_t t, int64_t rev_p, bool *fa) {
   const int64_t da = e.a1 - e.a0;
-  const bool fa = int64_t(t) < da;
+  *fa = int64_t(t) < da;
   int64_t qb = e.b0 + (int64_t(t) - da);
-  qb += qb >= *rev_p ? 1 : 0;
-  const int64_t q = fa ? e.a0 + int64_t(t) : qb;
-  const int32_t u = fa ? e.a : e.b;
-  const int64_t u0 = fa ? e.a0 : e.b0, u1 = fa ? e.a1 : e.b1;
-  const float ru = fa ? e.ra : e.rb;
-  const float h_eu = fa ? e.ha : e.hb;
-  const sped_walk_entry en = g.we[q];
-  const sped_walk_node nv = g.wn[en.col];
+  qb += qb >= rev_p ? 1 : 0;
+  return *fa ? e.a0 + int64_t(t) : qb;
+}
+
+// Step from e to the edge f at position q (picked by `pick`, record en: one
+// 32-byte load that carries the far endpoint's row range and scale); *rev_p
+// is updated for f.  Returns x_e^T x_f.
+__device__ inline float advance(Edge &e, int64_t q, bool fa, const sped_walk_entry &en, int64_t *rev_p) {
   const float dot_same = e.ha * e.ha + e.hb * e.hb;
+  const float h_eu = fa ? e.ha : e.hb;
   Edge f;
   f.p = q;
-  f.a = u; f.a0 = u0; f.a1 = u1; f.ra = ru;
-  f.b = en.col; f.b0 = nv.start; f.b1 = nv.start + nv.degree; f.rb = nv.root_scale;
+  f.a = fa ? e.a : e.b;
+  f.a0 = fa ? e.a0 : e.b0;
+  f.a1 = fa ? e.a1 : e.b1;
+  f.ra = fa ? e.ra : e.rb;
+  f.b = en.col; f.b0 = en.start; f.b1 = en.start + en.degree; f.rb = en.root_scale;
   edge_entries(f, en.val);
-  *rev_p = nv.start + en.rev_local;
-  const float dot = (q == e.p) ? dot_same : h_eu * f.ha;  // f.ha: entry of f at u
+  *rev_p = en.start + en.rev_local;
+  const float dot = (q == e.p) ? dot_same : h_eu * f.ha;  // f.ha: entry of f at the shared node
   e = f;
   return dot;
 }
 
+__device__ inline float move(const Graph &g, Edge &e, uint32_t t, int64_t *rev_p) {
+  bool fa;
+  const int64_t q = pick(e, t, *rev_p, &fa);
+  const sped_walk_entry en = g.we[q];
+  return advance(e, q, fa, en, rev_p);
+}
+
+// Row gathers of up to 8 walks of a group: lane j of the group holds the
+// weight w_j and node_j of walk j0 + j.  issue() starts the loads of
+// X[node_j, c0 .. c0+VEC) for all 8 slots; consume() adds w_j times them to acc
+// for the slots below nlive with nonzero weight.  Slots past nlive re-read a
+// valid row of the group and are discarded.
+template <typename TX, int VEC>
+struct RowBatch {
+  float w[8];
+  float x[8][VEC];
+  __device__ void issue(const TX *__restrict__ X, int64_t ldx, int cc, int G, int j0, float wl, int32_t node) {
+    int32_t nj[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      w[u] = __shfl(wl, (j0 + u) & (G - 1), G);
+      nj[u] = __shfl(node, (j0 + u) & (G - 1), G);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) VecIO<TX, VEC>::load(X + int64_t(nj[u]) * ldx + cc, x[u]);
+  }
+  __device__ void consume(bool col_ok, int j0, int nlive, float (&acc)[VEC]) const {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool use = col_ok && (j0 + u < nlive) && w[u] != 0.f;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] = use ? fmaf(w[u], x[u][v], acc[v]) : acc[v];
+    }
+  }
+};
+
+template <typename TX, int VEC>
+__device__ inline void gather_weighted_rows(const TX *__restrict__ X, int64_t ldx, int c0, bool col_ok, int G,
+                                            int nlive, float w, int32_t node, float (&acc)[VEC]) {
+  const int cc = col_ok ? c0 : 0;
+  RowBatch<TX, VEC> rb;
+  for (int j0 = 0; j0 < nlive; j0 += 8) {
+    rb.issue(X, ldx, cc, G, j0, w, node);
+    rb.consume(col_ok, j0, nlive, acc);
+  }
+}
+
 // One group of G lanes owns output row r.  Lane j of the group drives the
 // control path (random draws, index loads, weights) of walks j, j + G, ...
-// so G walks advance in parallel; after each step the group visits those
-// walks one by one, every lane gathering its VEC columns of the two rows of
-// the walk's current edge, and accumulates into the row's sum.  All walks of a
-// row meet in the same registers: one store per row, no atomics.
+// so G walks advance in parallel; after each step the group gathers, for all
+// of those walks at once, the X row of the node each walk just left (every
+// lane its VEC columns) and adds them into the row's sum in walk order.  All
+// walks of a row meet in the same registers: one store per row, no atomics.
 template <typename TX, typename TY, int VEC>
 __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
-    int64_t n, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
+    int64_t n, int64_t nb, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
     TY *__restrict__ Y, int64_t ldy, int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, Coefs cf) {
+  // each XCD takes a contiguous range of rows, so walks that stay near their
+  // start (clustered graphs) reuse that XCD's L2
+  const int64_t lb = xcd_logical_block(nb);
+  if (lb >= nb) return;  // padding block (no barriers below)
   const int lig = threadIdx.x & (G - 1);
-  const int64_t r = int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG);
+  const int64_t r = lb * (kBlock >> lgG) + (threadIdx.x >> lgG);
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   const bool col_ok = c0 < k;
   const bool row_ok = r < n;
@@ -183,27 +236,9 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
           leave = e.a;
           wleave = pa;
         }
-        for (int j = 0; j < nlive; ++j) {
-          const float wj = __shfl(float(wleave), j, G);
-          const int32_t nj = __shfl(leave, j, G);
-          if (col_ok && wj != 0.f) {
-            float xv[VEC];
-            VecIO<TX, VEC>::load(X + int64_t(nj) * ldx + c0, xv);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wj, xv[v], acc[v]);
-          }
-        }
+        gather_weighted_rows<TX, VEC>(X, ldx, c0, col_ok, G, nlive, float(wleave), leave, acc);
       }
-      for (int j = 0; j < nlive; ++j) {
-        const float wj = __shfl(float(pb), j, G);
-        const int32_t nj = __shfl(e.b, j, G);
-        if (col_ok && wj != 0.f) {
-          float xv[VEC];
-          VecIO<TX, VEC>::load(X + int64_t(nj) * ldx + c0, xv);
-#pragma unroll
-          for (int v = 0; v < VEC; ++v) acc[v] = fmaf(wj, xv[v], acc[v]);
-        }
-      }
+      gather_weighted_rows<TX, VEC>(X, ldx, c0, col_ok, G, nlive, float(pb), e.b, acc);
     }
   }
   if (row_ok && col_ok) {
@@ -327,9 +362,10 @@ sped_status launch_is(const sped_csr *L, int64_t k, const void *X, int64_t ldx, 
   int lgG = ilog2(G);
   Graph g{L->rowptr, L->wentry, L->wnode};
   const int64_t rows_per_block = kBlock >> lgG;
-  const dim3 grid = dim3(unsigned((L->n + rows_per_block - 1) / rows_per_block), unsigned(ytiles));
+  const int64_t nb = (L->n + rows_per_block - 1) / rows_per_block;
+  const dim3 grid = dim3(unsigned(xcd_padded_grid(nb)), unsigned(ytiles));
 #define SPED_IS(V)                                                                                      \
-  hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, int(k), G, lgG, g, \
+  hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, nb, int(k), G, lgG, g, \
                      ell, static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr, cf)
   if (vec == 4) SPED_IS(4);
   else if (vec == 2) SPED_IS(2);

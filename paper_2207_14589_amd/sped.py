@@ -153,7 +153,7 @@ def _call_ws(fn, where, args_before_ws, device, allow=()):
 class Laplacian:
     """Device split CSR of L = diag - S built by sped_laplacian_csr."""
 
-    def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda"):
+    def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda", walk_records=True):
         dev = torch.device(device)
 
         def dev_tensor(x, dt):
@@ -177,13 +177,14 @@ class Laplacian:
         self.scale = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
         self.bins = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
         self.old_of_new = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
-        self.wentry = torch.empty(max(2 * m, 1) * 4, dtype=torch.int32, device=dev)   # 16-byte records
-        self.wnode = torch.empty(max(n, 1) * 2, dtype=torch.int64, device=dev)        # 16-byte records
+        # walk records (32-byte entries, 16-byte nodes) for the stochastic estimators
+        self.wentry = (torch.empty(max(2 * m, 1) * 8, dtype=torch.int32, device=dev) if walk_records else None)
+        self.wnode = torch.empty(max(n, 1) * 2, dtype=torch.int64, device=dev) if walk_records else None
         c = CSR()
         c.rowptr, c.col, c.val, c.rev = (self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
                                          self.rev.data_ptr())
         c.diag, c.scale, c.bins = self.diag.data_ptr(), self.scale.data_ptr(), self.bins.data_ptr()
-        c.wentry, c.wnode = self.wentry.data_ptr(), self.wnode.data_ptr()
+        c.wentry, c.wnode = (self.wentry.data_ptr(), self.wnode.data_ptr()) if walk_records else (None, None)
         kind_i = {"sym": SYM_NORMALIZED, "combinatorial": COMBINATORIAL}[kind] if isinstance(kind, str) else kind
         self.kind = kind_i
         fn = lib().sped_laplacian_csr

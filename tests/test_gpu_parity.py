@@ -96,10 +96,13 @@ def test_laplacian_build(sped, kind, lcc):
     np.testing.assert_array_equal(col[rev], row_of)
     np.testing.assert_array_equal(rev[rev], np.arange(L.nnz))
     # packed walk records agree with the CSR arrays and the oracle's adjacency
-    we = L.wentry[: 4 * L.nnz].view(L.nnz, 4).cpu().numpy()
+    we = L.wentry[: 8 * L.nnz].view(L.nnz, 8).cpu().numpy()
     np.testing.assert_array_equal(we[:, 0], r_col)
     np.testing.assert_array_equal(we[:, 1].view(np.float32), val)
     np.testing.assert_array_equal(we[:, 2], rev - rowptr[r_col])
+    np.testing.assert_array_equal(we[:, 3], np.diff(r_rowptr)[r_col])
+    np.testing.assert_array_equal(we[:, 4:6].copy().view(np.int64)[:, 0], rowptr[r_col])
+    np.testing.assert_allclose(we[:, 6].view(np.float32), np.sqrt(ref.scale)[r_col], rtol=3 * U32)
     wn = L.wnode[: 2 * L.n].view(L.n, 2).cpu().numpy()
     np.testing.assert_array_equal(wn[:, 0], rowptr[:-1])
     np.testing.assert_array_equal((wn[:, 1] & 0xFFFFFFFF).astype(np.int64), np.diff(r_rowptr))
