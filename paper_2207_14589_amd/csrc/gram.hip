@@ -2,7 +2,7 @@
 //   gram   G = A^T B in float64 on the float64 matrix cores
 //          (v_mfma_f64_16x16x4f64), one 16x16 output tile per MFMA chain;
 //   tsmm   O = X T for a small k_in x k_out matrix T (float64 in memory, float
-//          in LDS), one lane group per row like the sparse step;
+//          in LDS) on the float32 matrix cores (v_mfma_f32_16x16x4f32);
 //   resid  R^T R for R = Z - Q diag(theta) formed on the fly (same Gram
 //          kernels), column norms and an upper bound on ||R||_2.
 // Split over rows, every block writes its own partial; a second pass adds the
@@ -14,7 +14,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kMaxK = 128;        // ka, kb <= kMaxK
-constexpr int kGramBlocks = 512;
+constexpr int kGramBlocks = 512;   // narrow Gram
+constexpr int kWideBlocks = 1024;  // wide Gram
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -50,65 +51,71 @@ struct ResidLoad {
   __device__ double b(int64_t r, int c) const { return a(r, c); }
 };
 
-// Each wavefront streams its rows straight from global memory (16 rows per
-// round: lane (li, lk) reads element [row + 4u + lk][16 tile + li], u = 0..3)
-// into float64 MFMA operands; no LDS and no barriers.  With few output tiles
-// (ROWSPLIT) every wavefront forms all tiles over its own quarter of the
-// block's rows and writes its own partial; otherwise the tiles are dealt
-// round-robin to the 4 wavefronts, which all read the block's rows (their
-// shared lines come from L1) and write disjoint tiles of one partial.  With
-// SYM (A == B) only tiles p <= q are formed and mirrored on output.
-template <typename LD, int MAXT, bool SYM, bool ROWSPLIT>
-__global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb, LD ld,
-                                                      int64_t rows_per_block, double *__restrict__ partials) {
-  constexpr int KU = MAXT <= 4 ? 4 : 1;
+// Wide Gram (a width above 32, both <= 128).  The block has NW wavefronts;
+// wavefront p owns the 16-row output block p (waves past the last block exit
+// at once) and forms its tiles (p, q) for every q < TB (q >= p when SYM) over
+// all of the block's rows, 4 KU rows per round: lane (li, lk) holds element
+// [row + 4u + lk][16 block + li] of each operand fragment (the float64 MFMA
+// operand layout).  Every load is unconditional: column indices are clamped
+// into range (a padded column only feeds output entries that are never
+// written) and rows past the end are clamped to the block's first row and
+// scaled by zero, so no branch separates the loads of a round.  Two fragment
+// buffers alternate, the next round's loads being issued before the current
+// round's MFMAs.  Wavefronts write disjoint tiles of the block's partial; with
+// SYM the tiles above the diagonal are mirrored.
+template <typename LD, int TBM, int NW, bool SYM>
+__global__ __launch_bounds__(64 * NW) void gram_wide_kernel(int64_t n, int ka, int kb, LD ld,
+                                                            int64_t rows_per_block, double *__restrict__ partials) {
+  constexpr int KU = TBM <= 4 ? 4 : 2;
+  constexpr int STEP = 4 * KU;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // wave-uniform (read from lane 0), so the tile tests below are scalar branches
+  const int pb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (pb >= TA) return;  // no barriers in this kernel
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-
-  int tp[MAXT], tq[MAXT];
-  int nt = 0;
-  {
-    int idx = 0;
-    for (int p = 0; p < TA; ++p)
-      for (int q = SYM ? p : 0; q < TB; ++q) {
-        if ((ROWSPLIT || idx % 4 == wave) && nt < MAXT) {
-          tp[nt] = p;
-          tq[nt] = q;
-          ++nt;
-        }
-        ++idx;
-      }
-  }
-  double4_t acc[MAXT];
-#pragma unroll
-  for (int t = 0; t < MAXT; ++t) acc[t] = double4_t{0.0, 0.0, 0.0, 0.0};
-
   const int64_t r_begin = int64_t(blockIdx.x) * rows_per_block;
   const int64_t r_end = min(n, r_begin + rows_per_block);
-  const int64_t first = r_begin + (ROWSPLIT ? 4 * KU * wave : 0);
-  const int64_t stride = ROWSPLIT ? 16 * KU : 4 * KU;
-  for (int64_t r = first; r < r_end; r += stride) {
-    double a[KU][MAXT], b[KU][MAXT];
+  const int ca = min(pb * 16 + li, ka - 1);
+  int cb[TBM];
+#pragma unroll
+  for (int q = 0; q < TBM; ++q) cb[q] = min(q * 16 + li, kb - 1);
+  double4_t acc[TBM];
+#pragma unroll
+  for (int q = 0; q < TBM; ++q) acc[q] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  struct Frag {
+    double a[KU], b[KU][TBM];
+  };
+  auto load = [&](int64_t r, Frag &f) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const int64_t row = r + 4 * u + lk;
       const bool rok = row < r_end;
+      const int64_t rc = rok ? row : r_begin;
+      const double rm = rok ? 1.0 : 0.0;
+      f.a[u] = ld.a(rc, ca) * rm;
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t) {
-        a[u][t] = b[u][t] = 0.0;
-        if (t < nt && rok) {
-          const int ca = tp[t] * 16 + li, cb = tq[t] * 16 + li;
-          if (ca < ka) a[u][t] = ld.a(row, ca);
-          if (cb < kb) b[u][t] = ld.b(row, cb);
-        }
-      }
+      for (int q = 0; q < TBM; ++q) f.b[u][q] = ld.b(rc, cb[q]) * rm;
     }
+  };
+  auto mma = [&](const Frag &f) {
 #pragma unroll
-    for (int u = 0; u < KU; ++u)
+    for (int q = 0; q < TBM; ++q)
+      if (q < TB && (!SYM || q >= pb))
 #pragma unroll
-      for (int t = 0; t < MAXT; ++t)
-        if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[u][t], acc[t], 0, 0, 0);
+        for (int u = 0; u < KU; ++u) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[u], f.b[u][q], acc[q], 0, 0, 0);
+  };
+
+  if (r_begin < r_end) {
+    Frag f0, f1;
+    load(r_begin, f0);
+    for (int64_t r = r_begin; r < r_end; r += 2 * STEP) {
+      load(r + STEP, f1);  // rows past the end load as zeros
+      mma(f0);
+      load(r + 2 * STEP, f0);
+      mma(f1);
+    }
   }
   // Which (row, column) of the 16x16 tile each of this lane's 4 accumulator
   // slots holds is read off the matrix core itself: with A[i][0] = i,
@@ -120,17 +127,16 @@ __global__ __launch_bounds__(kBlock) void gram_kernel(int64_t n, int ka, int kb,
                                                                zero4, 0, 0, 0);
   const double4_t colid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? 1.0 : 0.0, lk == 0 ? double(li) : 0.0,
                                                                zero4, 0, 0, 0);
-  const int64_t slot = ROWSPLIT ? int64_t(blockIdx.x) * 4 + wave : int64_t(blockIdx.x);
-  double *out = partials + slot * ka * kb;
+  double *out = partials + int64_t(blockIdx.x) * ka * kb;
 #pragma unroll
-  for (int t = 0; t < MAXT; ++t) {
-    if (t < nt) {
+  for (int q = 0; q < TBM; ++q) {
+    if (q < TB && (!SYM || q >= pb)) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int i = tp[t] * 16 + int(rowid[r]);
-        int j = tq[t] * 16 + int(colid[r]);
-        if (i < ka && j < kb) out[i * kb + j] = acc[t][r];
-        if (SYM && tp[t] != tq[t] && j < ka && i < kb) out[j * kb + i] = acc[t][r];
+        const int ii = pb * 16 + int(rowid[r]);
+        const int jj = q * 16 + int(colid[r]);
+        if (ii < ka && jj < kb) out[ii * kb + jj] = acc[q][r];
+        if (SYM && pb != q && jj < ka && ii < kb) out[jj * kb + ii] = acc[q][r];
       }
     }
   }
@@ -238,69 +244,123 @@ sped_status launch_sum_partials(const double *partials, int nparts, int64_t coun
   return SPED_OK;
 }
 
-// O[r, :] = X[r, :] T, T kin x kout float64 -> float in LDS.
-template <typename TX, typename TO, int VEC>
-__global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int kout, int G, int lgG,
-                                                      const TX *__restrict__ X, int64_t ldx,
-                                                      const double *__restrict__ T, TO *__restrict__ O,
+// O = X T for a small kin x kout T on the float32 matrix cores
+// (v_mfma_f32_16x16x4f32).  T (float64 in memory) is staged as float in LDS,
+// zero-padded to a multiple of 16 rows, with a row stride of 16 mod 64 floats
+// so that the four k-rows a wavefront reads at once fall in distinct banks.
+// Each wavefront forms 16-row strips of O (all TBO 16-column tiles at once),
+// striding over the strips of the grid; lane (li, lk) streams X[row + li][k +
+// lk], four k-steps per batch.  Rows past n are clamped (their outputs are not
+// stored); columns past kin are clamped and zeroed bitwise, so non-finite
+// data never meets the zero padding of T.  A strip's inputs are all read
+// before its outputs are written, so O may alias X.
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+inline int tsmm_lds_stride(int w) { return ((w - 16 + 63) / 64) * 64 + 16; }
+
+template <typename TX, typename TO, int TBO>
+__global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int kout, const TX *__restrict__ X,
+                                                      int64_t ldx, const double *__restrict__ T, TO *O,
                                                       int64_t ldo) {
   extern __shared__ float sT[];
-  const int kop = (kout + 3) & ~3;
-  for (int i = threadIdx.x; i < kin * kop; i += kBlock) {
-    int r = i / kop, c = i - r * kop;
-    sT[i] = c < kout ? float(T[r * kout + c]) : 0.f;
+  const int S = ((16 * TBO - 16 + 63) / 64) * 64 + 16;
+  const int kin16 = (kin + 15) & ~15;
+  for (int i = threadIdx.x; i < kin16 * 16 * TBO; i += kBlock) {
+    const int r = i / (16 * TBO), c = i - r * (16 * TBO);
+    sT[r * S + c] = (r < kin && c < kout) ? float(T[r * kout + c]) : 0.f;
   }
   __syncthreads();
-  const int lig = threadIdx.x & (G - 1);
-  const int64_t row = int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG);
-  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
-  if (row >= n || c0 >= kout) return;
-  float o[VEC];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const float4_t zero4 = float4_t{0.f, 0.f, 0.f, 0.f};
+  // output slot layout read off the matrix core (as for the float64 Gram)
+  const float4_t rowid =
+      __builtin_amdgcn_mfma_f32_16x16x4f32(lk == 0 ? float(li) : 0.f, lk == 0 ? 1.f : 0.f, zero4, 0, 0, 0);
+  const float4_t colid =
+      __builtin_amdgcn_mfma_f32_16x16x4f32(lk == 0 ? 1.f : 0.f, lk == 0 ? float(li) : 0.f, zero4, 0, 0, 0);
+  const int64_t strips = (n + 15) / 16;
+  for (int64_t st = int64_t(blockIdx.x) * 4 + wave; st < strips; st += int64_t(gridDim.x) * 4) {
+    const int64_t row0 = st * 16;
+    const int64_t row = min(row0 + li, n - 1);
+    const TX *xr = X + row * ldx;
+    float4_t acc[TBO];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) o[v] = 0.f;
-  const TX *xr = X + row * ldx;
-  for (int j = 0; j < kin; ++j) {
-    float x = to_f32<TX>(xr[j]);
+    for (int q = 0; q < TBO; ++q) acc[q] = zero4;
+    for (int k0 = 0; k0 < kin16; k0 += 16) {
+      float x[4];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) o[v] = fmaf(x, sT[j * kop + c0 + v], o[v]);
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k0 + 4 * j + lk;
+        const float v = to_f32<TX>(xr[min(kk, kin - 1)]);
+        x[j] = __uint_as_float(__float_as_uint(v) & (kk < kin ? 0xffffffffu : 0u));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < TBO; ++q)
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[j], sT[(k0 + 4 * j + lk) * S + q * 16 + li], acc[q], 0,
+                                                        0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < TBO; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t orow = row0 + int(rowid[r]);
+        const int oc = q * 16 + int(colid[r]);
+        if (orow < n && oc < kout) O[orow * ldo + oc] = from_f32<TO>(acc[q][r]);
+      }
   }
-  VecIO<TO, VEC>::store(O + row * ldo + c0, o);
 }
 
+template <typename TX, typename TO>
+sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t ldx, const double *T, void *O,
+                          int64_t ldo, hipStream_t s) {
+  const int TBO = (kout + 15) / 16;
+  const size_t shm = size_t((kin + 15) & ~15) * tsmm_lds_stride(16 * TBO) * sizeof(float);
+  const int64_t strips = (n + 15) / 16;
+  const int64_t want = (strips + 31) / 32;  // about 8 strips per wavefront
+  const unsigned blocks = unsigned(want < 1 ? 1 : (want > 2048 ? 2048 : want));
+#define SPED_TSMM(B)                                                                                     \
+  {                                                                                                      \
+    SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, B>, shm));                                                  \
+    hipLaunchKernelGGL((tsmm_kernel<TX, TO, B>), dim3(blocks), dim3(kBlock), shm, s, n, kin, kout,       \
+                       static_cast<const TX *>(X), ldx, T, static_cast<TO *>(O), ldo);                   \
+  }
+  if (TBO <= 1) SPED_TSMM(1)
+  else if (TBO <= 2) SPED_TSMM(2)
+  else if (TBO <= 4) SPED_TSMM(4)
+  else SPED_TSMM(8)
+#undef SPED_TSMM
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
 
 struct GramPlan {
-  int nblocks, nparts, maxt;
-  bool rowsplit, narrow;
+  int nblocks, nparts;
+  bool narrow;
   int64_t rows_per_block;
 };
 
 GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
+  (void)sym;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  const int tiles = sym ? TA * (TA + 1) / 2 : TA * TB;
   GramPlan p;
-  p.rowsplit = tiles <= 4;
-  const int per_wave = p.rowsplit ? tiles : (tiles + 3) / 4;
-  p.maxt = per_wave <= 1 ? 1 : per_wave <= 2 ? 2 : per_wave <= 4 ? 4 : per_wave <= 8 ? 8 : 16;
-  int64_t blocks = (n + 255) / 256;
-  p.nblocks = int(blocks < kGramBlocks ? (blocks > 0 ? blocks : 1) : kGramBlocks);
-  int64_t rpb = (n + p.nblocks - 1) / p.nblocks;
-  p.rows_per_block = (rpb + 63) / 64 * 64;
-  p.nparts = p.rowsplit ? 4 * p.nblocks : p.nblocks;
   p.narrow = TA <= 2 && TB <= 2;
-  if (p.narrow) {
-    int64_t nb = (n + 1023) / 1024;
-    p.nblocks = int(nb < kGramBlocks ? (nb > 0 ? nb : 1) : kGramBlocks);
-    int64_t r = (n + p.nblocks - 1) / p.nblocks;
-    p.rows_per_block = (r + 255) / 256 * 256;
-    p.nparts = p.nblocks;
-  }
+  const int64_t unit = p.narrow ? 1024 : 128;  // rows per block at least
+  const int64_t align = p.narrow ? 256 : 64;
+  const int64_t cap = p.narrow ? kGramBlocks : kWideBlocks;
+  int64_t nb = (n + unit - 1) / unit;
+  p.nblocks = int(nb < cap ? (nb > 0 ? nb : 1) : cap);
+  int64_t r = (n + p.nblocks - 1) / p.nblocks;
+  p.rows_per_block = (r + align - 1) / align * align;
+  p.nparts = p.nblocks;
   return p;
 }
 
-template <typename LD, int MAXT, bool SYM, bool RS>
-sped_status launch_gram_t(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
-                          hipStream_t s) {
-  hipLaunchKernelGGL((gram_kernel<LD, MAXT, SYM, RS>), dim3(p.nblocks), dim3(kBlock), 0, s, n, ka, kb, ld,
+template <typename LD, int TBM, int NW, bool SYM>
+sped_status launch_gram_wide_t(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
+                               hipStream_t s) {
+  hipLaunchKernelGGL((gram_wide_kernel<LD, TBM, NW, SYM>), dim3(p.nblocks), dim3(64 * NW), 0, s, n, ka, kb, ld,
                      p.rows_per_block, partials);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
@@ -318,22 +378,18 @@ sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const LD &ld, double
 template <typename LD, bool SYM>
 sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
                              hipStream_t s) {
+  const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
   if (p.narrow) {
-    const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
     if (TA == 1 && TB == 1) return launch_gram_narrow_t<LD, 1, 1, SYM>(n, ka, kb, ld, partials, p, s);
     if (TA == 1 && TB == 2) return launch_gram_narrow_t<LD, 1, 2, SYM>(n, ka, kb, ld, partials, p, s);
     if (TA == 2 && TB == 1) return launch_gram_narrow_t<LD, 2, 1, SYM>(n, ka, kb, ld, partials, p, s);
     return launch_gram_narrow_t<LD, 2, 2, SYM>(n, ka, kb, ld, partials, p, s);
   }
-  if (p.rowsplit) {
-    if (p.maxt <= 1) return launch_gram_t<LD, 1, SYM, true>(n, ka, kb, ld, partials, p, s);
-    if (p.maxt <= 2) return launch_gram_t<LD, 2, SYM, true>(n, ka, kb, ld, partials, p, s);
-    return launch_gram_t<LD, 4, SYM, true>(n, ka, kb, ld, partials, p, s);
+  if (TA <= 4) {
+    if (TB <= 4) return launch_gram_wide_t<LD, 4, 4, SYM>(n, ka, kb, ld, partials, p, s);
+    return launch_gram_wide_t<LD, 8, 4, SYM>(n, ka, kb, ld, partials, p, s);
   }
-  if (p.maxt <= 2) return launch_gram_t<LD, 2, SYM, false>(n, ka, kb, ld, partials, p, s);
-  if (p.maxt <= 4) return launch_gram_t<LD, 4, SYM, false>(n, ka, kb, ld, partials, p, s);
-  if (p.maxt <= 8) return launch_gram_t<LD, 8, SYM, false>(n, ka, kb, ld, partials, p, s);
-  return launch_gram_t<LD, 16, SYM, false>(n, ka, kb, ld, partials, p, s);
+  return launch_gram_wide_t<LD, 8, 8, SYM>(n, ka, kb, ld, partials, p, s);
 }
 
 template <typename T1, typename T2, bool SYM>
@@ -370,31 +426,6 @@ __global__ void resid_norms_kernel(int k, int kn, const double *__restrict__ G, 
   }
 }
 
-template <typename TX, typename TO>
-sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t ldx, const double *T, void *O,
-                          int64_t ldo, hipStream_t s) {
-  int vec = pick_vec(kout, {ldo}, {O}, {int(sizeof(TO))});
-  int lanes = (kout + vec - 1) / vec;
-  int ytiles = (lanes + 63) / 64;
-  int G = lanes >= 64 ? 64 : next_pow2(lanes);
-  int lgG = ilog2(G);
-  int64_t blocks = (n + (kBlock >> lgG) - 1) / (kBlock >> lgG);
-  size_t shm = size_t(kin) * ((kout + 3) & ~3) * sizeof(float);
-  const dim3 grid = dim3(unsigned(blocks), unsigned(ytiles));
-  SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, 4>, shm));
-  SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, 2>, shm));
-  SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, 1>, shm));
-#define SPED_TSMM(V)                                                                          \
-  hipLaunchKernelGGL((tsmm_kernel<TX, TO, V>), grid, dim3(kBlock), shm, s, n, kin, kout, G, lgG, \
-                     static_cast<const TX *>(X), ldx, T, static_cast<TO *>(O), ldo)
-  if (vec == 4) SPED_TSMM(4);
-  else if (vec == 2) SPED_TSMM(2);
-  else SPED_TSMM(1);
-#undef SPED_TSMM
-  SPED_CHECK_HIP(hipGetLastError());
-  return SPED_OK;
-}
-
 }  // namespace
 
 size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb) {
@@ -429,6 +460,7 @@ sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, i
 
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
                         void *O, int64_t ldo, int to, hipStream_t s) {
+  if (kin < 1 || kout < 1 || kin > kMaxK || kout > kMaxK) return fail(SPED_E_UNSUPPORTED, "tsmm width outside [1, 128]");
   if (n == 0) return SPED_OK;
   if (tx == SPED_F32 && to == SPED_F32) return launch_tsmm_t<float, float>(n, kin, kout, X, ldx, T, O, ldo, s);
   if (tx == SPED_F32 && to == SPED_BF16) return launch_tsmm_t<float, bf16_t>(n, kin, kout, X, ldx, T, O, ldo, s);

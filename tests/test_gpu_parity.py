@@ -278,12 +278,17 @@ def test_stochastic_unbiased(sped):
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-def test_gram_parity(sped, dt):
-    _say(f"gram {dt}")
-    g = np.random.default_rng(1)
+@pytest.mark.parametrize("ka,kb", [(20, 36), (56, 56), (61, 128), (100, 7), (128, 128)])
+def test_gram_parity(sped, dt, ka, kb):
+    """G = A^T B against float64 numpy on the same (rounded) operands: narrow
+    (both widths <= 32), wide with 4 or 8 wavefronts per block, odd widths and
+    a ragged row count; the symmetric form is exactly symmetric and the
+    reduction order is fixed."""
+    _say(f"gram {dt} {ka}x{kb}")
+    g = np.random.default_rng(ka * 1000 + kb)
     n = 100_003
-    A = torch.from_numpy(g.standard_normal((n, 20)).astype(np.float32))
-    B = torch.from_numpy(g.standard_normal((n, 36)).astype(np.float32))
+    A = torch.from_numpy(g.standard_normal((n, ka)).astype(np.float32))
+    B = torch.from_numpy(g.standard_normal((n, kb)).astype(np.float32))
     tdt = torch.float32 if dt == "f32" else torch.bfloat16
     Ad, Bd = A.to(tdt).cuda(), B.to(tdt).cuda()
     G = sped.gram(Ad, Bd).cpu().numpy()
@@ -291,22 +296,27 @@ def test_gram_parity(sped, dt):
     Bn = Bd.float().cpu().numpy().astype(np.float64)
     Gr = An.T @ Bn
     assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
-    S = sped.gram(Ad).cpu().numpy()
-    np.testing.assert_allclose(S, An.T @ An, rtol=1e-12, atol=1e-12 * n)
-    np.testing.assert_array_equal(S, S.T)
+    for X, Xn in ((Ad, An), (Bd, Bn)):
+        S = sped.gram(X).cpu().numpy()
+        np.testing.assert_allclose(S, Xn.T @ Xn, rtol=1e-12, atol=1e-12 * n)
+        np.testing.assert_array_equal(S, S.T)
     G2 = sped.gram(Ad, Bd).cpu().numpy()
     np.testing.assert_array_equal(G, G2)   # fixed reduction order
 
 
-def test_orthonormalize_and_rr(sped):
-    _say("CholQR2 and Rayleigh-Ritz")
+@pytest.mark.parametrize("k", [14, 57, 96])
+def test_orthonormalize_and_rr(sped, k):
+    """CholQR2 (fused Cholesky and triangular inverse) and Rayleigh-Ritz
+    (Jacobi eigensolver, odd widths padded) against the oracle's Householder
+    basis and dense Ritz pairs."""
+    _say(f"CholQR2 and Rayleigh-Ritz k={k}")
     n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
     L = sped.Laplacian(n, s, d, kind="sym")
     ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
-    V = synth.gaussian_block(n, 14, 2).astype(np.float32)
+    V = synth.gaussian_block(n, k, 2).astype(np.float32)
     Vd = torch.from_numpy(V).cuda()
     Q = sped.orthonormalize(Vd.clone(), passes=2).cpu().numpy().astype(np.float64)
-    assert np.abs(Q.T @ Q - np.eye(14)).max() < 2e-6
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 2e-6
     assert osol.max_principal_angle(V.astype(np.float64), Q) < 1e-5
     Qd = torch.from_numpy(Q.astype(np.float32)).cuda()
     theta, resid = sped.rayleigh_ritz(L, Qd)
