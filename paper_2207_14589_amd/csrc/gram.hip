@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
   constexpr int KU = 4;
   constexpr int NW = kNarrowBlock / 64;
   __shared__ double red[TA * 16 * TB * 16];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   double4_t acc[TA][TB];
 #pragma unroll
@@ -164,25 +165,33 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
     for (int q = 0; q < TB; ++q) acc[p][q] = double4_t{0.0, 0.0, 0.0, 0.0};
   const int64_t r_begin = int64_t(blockIdx.x) * rows_per_block;
   const int64_t r_end = min(n, r_begin + rows_per_block);
-  for (int64_t r = r_begin + 4 * KU * wave; r < r_end; r += 4 * KU * NW) {
-    double fa[KU][TA], fb[KU][TB];
+  // Loads are unconditional (clamped columns feed only output entries that are
+  // never written; rows past the end re-read the block's first row, scaled by
+  // zero), and two fragment buffers alternate so that the next chunk's loads
+  // are in flight during the current chunk's MFMAs.
+  int ca[TA], cb[TB];
+#pragma unroll
+  for (int p = 0; p < TA; ++p) ca[p] = min(p * 16 + li, ka - 1);
+#pragma unroll
+  for (int q = 0; q < TB; ++q) cb[q] = min(q * 16 + li, kb - 1);
+  struct Frag {
+    double a[KU][TA], b[KU][TB];
+  };
+  auto load = [&](int64_t r, Frag &f) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
       const int64_t row = r + 4 * u + lk;
       const bool rok = row < r_end;
+      const int64_t rc = rok ? row : r_begin;
+      const double rm = rok ? 1.0 : 0.0;
 #pragma unroll
-      for (int p = 0; p < TA; ++p) {
-        const int c = p * 16 + li;
-        fa[u][p] = (rok && c < ka) ? ld.a(row, c) : 0.0;
-      }
-      if (!SYM) {
+      for (int p = 0; p < TA; ++p) f.a[u][p] = ld.a(rc, ca[p]) * rm;
+      if (!SYM)
 #pragma unroll
-        for (int q = 0; q < TB; ++q) {
-          const int c = q * 16 + li;
-          fb[u][q] = (rok && c < kb) ? ld.b(row, c) : 0.0;
-        }
-      }
+        for (int q = 0; q < TB; ++q) f.b[u][q] = ld.b(rc, cb[q]) * rm;
     }
+  };
+  auto mma = [&](const Frag &f) {
 #pragma unroll
     for (int u = 0; u < KU; ++u)
 #pragma unroll
@@ -190,7 +199,20 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
 #pragma unroll
         for (int q = 0; q < TB; ++q)
           if (!SYM || p <= q)
-            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[u][p], SYM ? fa[u][q] : fb[u][q], acc[p][q], 0, 0, 0);
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[u][p], SYM ? f.a[u][q] : f.b[u][q], acc[p][q], 0,
+                                                             0, 0);
+  };
+  constexpr int64_t STRIDE = 4 * KU * NW;
+  const int64_t first = r_begin + 4 * KU * wave;
+  if (first < r_end) {
+    Frag f0, f1;
+    load(first, f0);
+    for (int64_t r = first; r < r_end; r += 2 * STRIDE) {
+      load(r + STRIDE, f1);  // rows past the end load as zeros
+      mma(f0);
+      load(r + 2 * STRIDE, f0);
+      mma(f1);
+    }
   }
   const double4_t zero4 = double4_t{0.0, 0.0, 0.0, 0.0};
   const double4_t rowid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? double(li) : 0.0, lk == 0 ? 1.0 : 0.0,
