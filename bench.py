@@ -254,6 +254,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--tolerance-only", action="store_true",
+                    help="run only the time-to-tolerance comparisons (profiling the solver)")
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
@@ -285,6 +287,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.tolerance_only:
+        out = {"time_to_tolerance": time_to_tolerance(sped, synth, torch, np),
+               "time_to_tolerance_sbm500k": time_to_tolerance_sbm500k(sped, synth, torch, np)}
+        print(json.dumps(out), flush=True)
+        return
     k, ell, walks = 32, 16, 8
     t0 = time.perf_counter()
     n, s, d, _ = synth.sbm_from_degrees(1_000_000, 100, 19.0, 1.0, seed=1)
