@@ -247,6 +247,41 @@ def time_to_tolerance_sbm500k(sped, synth, torch, np):
     return out
 
 
+def mu_eg_streak_sbm2000(sped, synth, torch, np):
+    """mu-EigenGame on the 2,000-node SBM (k = 10 + 4 guard players): the
+    eigenvector streak (Sec. 5.2, eps = pi/8) against the dense eigenvectors
+    after T iterations, for the plain operator 2I - L and the degree-8 limit
+    operator, each with step 0.5 / rho(M) (rho = 2 and 1).  Every point is a
+    fresh deterministic run of T iterations from the same start block."""
+    from paper_2207_14589_amd import metrics
+
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    rowptr, col, val, diag, _ = L.host_csr()
+    Ld = np.diag(diag.astype(np.float64))
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    Ld[rows, col] -= val.astype(np.float64)
+    lam, U = np.linalg.eigh(Ld)
+    k, guard = 10, 4
+    Uref = torch.from_numpy(U[:, :k].astype(np.float32)).cuda()
+    V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 2).astype(np.float32)).cuda()
+    checkpoints = [10, 40, 160, 640, 2560, 10240]
+    out = {"workload": "SBM n=2000, 10 blocks, k=10 (+4 guard players); streak eps = pi/8",
+           "checkpoints": checkpoints}
+    for name, p, eta in (("plain", None, 0.25), ("sped_limit8", sped.transform("limit", 8), 0.5)):
+        streaks, secs = [], []
+        for T in checkpoints:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=T, check_every=T, solver="mu_eg",
+                             eta=eta)
+            secs.append(round(time.perf_counter() - t0, 4))
+            streaks.append(metrics.eigenvector_streak(Uref, r.V))
+        full = [T for T, st in zip(checkpoints, streaks) if st == k]
+        out[name] = {"eta": eta, "streak": streaks, "seconds": secs, "first_full_streak_iters": full[0] if full else None}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +324,8 @@ def main():
     torch.cuda.set_device(0)
     if args.tolerance_only:
         out = {"time_to_tolerance": time_to_tolerance(sped, synth, torch, np),
-               "time_to_tolerance_sbm500k": time_to_tolerance_sbm500k(sped, synth, torch, np)}
+               "time_to_tolerance_sbm500k": time_to_tolerance_sbm500k(sped, synth, torch, np),
+               "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np)}
         print(json.dumps(out), flush=True)
         return
     k, ell, walks = 32, 16, 8
@@ -369,6 +405,7 @@ def main():
     if not args.no_solve and not args.chain_only:
         line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
         line["time_to_tolerance_sbm500k"] = time_to_tolerance_sbm500k(sped, synth, torch, np)
+        line["mu_eg_streak"] = mu_eg_streak_sbm2000(sped, synth, torch, np)
     if not args.no_cpu_baseline and not args.chain_only:
         line["cpu_baseline"] = cpu_baseline_leg(n, s, d, X, ell, per_launch)
     print(json.dumps(line), flush=True)

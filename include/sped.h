@@ -273,7 +273,11 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  * subspace iteration (or block Oja with step eta) on the reversed operator
  * M = p(L) (eq. reveig; p = NULL means the identity transform reversed,
  * M = lambda_bound I - L), Cholesky-QR2 after every application, and a
- * Rayleigh-Ritz step on L every check_every iterations.  The block carries
+ * Rayleigh-Ritz step on L every check_every iterations.  mu-EigenGame (the
+ * other solver Sec. 5 names) instead moves each unit vector v_i along its
+ * projected gradient M v_i - sum_{j<i} <v_i, M v_j> v_j (minus its v_i part)
+ * with step eta and renormalises; its checks run Rayleigh-Ritz on an
+ * orthonormalised copy.  The block carries
  * k + guard columns; the stopping test is
  *     rho / (theta_k - ||r_k|| - theta_{k-1}) <= tol,   R = [L q_i - theta_i q_i]_{i<k}
  * with rho = sqrt(min(||R^T R||_inf, ||R||_F^2)) >= ||R||_2 (R^T R in float64)
@@ -281,20 +285,23 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  * subspace; the gap is estimated from the first guard Ritz value theta_k
  * lowered by its residual r_k; guard >= 1).
  *  V0      DEVICE F32 n x (k+guard) (ldv0): start block
- *  V_out   DEVICE F32 n x k (ldvo): Ritz vectors, ascending
+ *  V_out   DEVICE F32 n x k (ldvo): Ritz vectors, ascending (mu-EigenGame: the
+ *          game's own unit vectors, players in order)
  *  vdt     storage of the iterate: F32, or BF16 (float32 sums, float64 Gram,
  *          Cholesky and Rayleigh-Ritz) until the bound reaches coarse_tol or
  *          stops improving (8 checks without a 2% drop: bf16's rounding floor),
  *          followed by a float32 refinement sweep down to tol
- *  evals   HOST double [k]: Ritz values of L, ascending
+ *  evals   HOST double [k]: Ritz values of L, ascending (for mu-EigenGame those
+ *          of L on the span of its vectors)
  *  resid   HOST double [k] or NULL: final residual norms
  *  o, st   HOST options / statistics
  * Synchronous.  Returns SPED_E_NOT_CONVERGED (with outputs and stats filled)
  * when max_iters is reached first.
  */
 typedef struct {
-  int32_t solver;          /* 0 = subspace iteration (eta = inf), 1 = block Oja */
-  double eta;              /* Oja step: iterate on M + I/eta */
+  int32_t solver;          /* 0 = subspace iteration (eta = inf), 1 = block Oja,
+                              2 = mu-EigenGame (F32 storage only) */
+  double eta;              /* Oja step (iterate on M + I/eta), or the mu-EigenGame step */
   double tol;              /* stopping bound */
   int32_t max_iters;
   int32_t check_every;     /* Rayleigh-Ritz cadence, >= 1 */

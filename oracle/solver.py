@@ -11,6 +11,8 @@ Sec. 5.2 metrics: subspace error delta = 1 - tr(U* P)/k with U*, P the
 orthogonal projectors of the true and estimated subspaces, which equals the
 mean squared sine of the principal angles; and the eigenvector streak, the
 number of leading estimated vectors each within an angle eps of its true one.
+mu-EigenGame (the other solver Sec. 5 cites) recovers the eigenvectors one by
+one in order, which is what the streak measures.
 """
 from __future__ import annotations
 
@@ -127,6 +129,35 @@ def subspace_iteration(L, apply_M, k: int, V0, max_iters: int, tol: float = 0.0,
     if theta is None:
         theta, Q, res = rayleigh_ritz(L, Q)
     return SolveResult(theta[:k], Q[:, :k], max_iters, res[:k], hist, False)
+
+
+def mu_eigengame(apply_M, V0, eta: float, iters: int, Vstar=None, eps: float = np.pi / 8,
+                 record_every: int = 1):
+    """mu-EigenGame on the top-k eigenvectors of M (the solver family Sec. 5
+    runs on the transformed matrix).  Player i holds a unit vector v_i and
+    moves along the Riemannian projection of its utility gradient
+        grad_i = M v_i - sum_{j<i} <v_i, M v_j> v_j,
+        grad_i <- grad_i - <grad_i, v_i> v_i,
+        v_i <- (v_i + eta grad_i) / ||v_i + eta grad_i||,
+    all players at once.  Only players j < i penalise player i, so player 1
+    runs Oja's rule for the top eigenvector and player i the same on the
+    deflation by the players above it: the fixed point is the ordered top-k
+    eigenbasis.  With Vstar given, records the eigenvector streak (Sec. 5.2)
+    every `record_every` iterations.  Returns (V, history)."""
+    V = np.asarray(V0, dtype=np.float64)
+    V = V / np.linalg.norm(V, axis=0)
+    hist = []
+    for t in range(1, iters + 1):
+        W = apply_M(V)
+        G = V.T @ W                       # G[j, i] = <v_j, M v_i> = <v_i, M v_j>
+        grad = W - V @ np.triu(G, 1)      # column i subtracts sum_{j<i} G[j, i] v_j
+        grad = grad - V * np.sum(grad * V, axis=0)
+        V = V + eta * grad
+        V = V / np.linalg.norm(V, axis=0)
+        if Vstar is not None and t % record_every == 0:
+            hist.append({"iter": t, "streak": eigenvector_streak(Vstar, V, eps),
+                         "angles": vector_angles(Vstar, V)})
+    return V, hist
 
 
 def dense_bottom_k(L_dense, k: int):

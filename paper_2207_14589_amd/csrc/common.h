@@ -328,8 +328,10 @@ sped_status launch_dot(int64_t n, int64_t k, const float *A, int64_t lda, const 
 size_t gram_ws_doubles(int64_t n, int64_t ka, int64_t kb);
 sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, int ta, const void *B, int64_t ldb,
                         int tb, double *G, double *partials, hipStream_t s);
+// O = X T (+ beta Y when Y is given; O may alias X or Y; Y and O float32)
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
-                        void *O, int64_t ldo, int to, hipStream_t s);
+                        void *O, int64_t ldo, int to, hipStream_t s, const void *Y = nullptr, int64_t ldy = 0,
+                        float beta = 0.f);
 // G = R^T R for R = Z - Q diag(theta) (k columns, shared leading dimension
 // ld), resid[i] = ||R e_i||, *norm2 >= ||R||_2 of the first kn columns.
 // partials as for the symmetric Gram of width k.

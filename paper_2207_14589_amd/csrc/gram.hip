@@ -275,15 +275,17 @@ sped_status launch_sum_partials(const double *partials, int nparts, int64_t coun
 // lk], four k-steps per batch.  Rows past n are clamped (their outputs are not
 // stored); columns past kin are clamped and zeroed bitwise, so non-finite
 // data never meets the zero padding of T.  A strip's inputs are all read
-// before its outputs are written, so O may alias X.
+// before its outputs are written, so O may alias X.  With ADD the stored value
+// is X T + beta Y (Y read element by element just before the store, so O may
+// alias Y as well).
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
 inline int tsmm_lds_stride(int w) { return ((w - 16 + 63) / 64) * 64 + 16; }
 
-template <typename TX, typename TO, int TBO>
+template <typename TX, typename TO, int TBO, bool ADD>
 __global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int kout, const TX *__restrict__ X,
                                                       int64_t ldx, const double *__restrict__ T, TO *O,
-                                                      int64_t ldo) {
+                                                      int64_t ldo, const TO *Y, int64_t ldy, float beta) {
   extern __shared__ float sT[];
   const int S = ((16 * TBO - 16 + 63) / 64) * 64 + 16;
   const int kin16 = (kin + 15) & ~15;
@@ -329,14 +331,18 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int ko
       for (int r = 0; r < 4; ++r) {
         const int64_t orow = row0 + int(rowid[r]);
         const int oc = q * 16 + int(colid[r]);
-        if (orow < n && oc < kout) O[orow * ldo + oc] = from_f32<TO>(acc[q][r]);
+        if (orow < n && oc < kout) {
+          float v = acc[q][r];
+          if (ADD) v = fmaf(beta, to_f32<TO>(Y[orow * ldy + oc]), v);
+          O[orow * ldo + oc] = from_f32<TO>(v);
+        }
       }
   }
 }
 
-template <typename TX, typename TO>
+template <typename TX, typename TO, bool ADD>
 sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t ldx, const double *T, void *O,
-                          int64_t ldo, hipStream_t s) {
+                          int64_t ldo, const void *Y, int64_t ldy, float beta, hipStream_t s) {
   const int TBO = (kout + 15) / 16;
   const size_t shm = size_t((kin + 15) & ~15) * tsmm_lds_stride(16 * TBO) * sizeof(float);
   const int64_t strips = (n + 15) / 16;
@@ -344,9 +350,10 @@ sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t l
   const unsigned blocks = unsigned(want < 1 ? 1 : (want > 2048 ? 2048 : want));
 #define SPED_TSMM(B)                                                                                     \
   {                                                                                                      \
-    SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, B>, shm));                                                  \
-    hipLaunchKernelGGL((tsmm_kernel<TX, TO, B>), dim3(blocks), dim3(kBlock), shm, s, n, kin, kout,       \
-                       static_cast<const TX *>(X), ldx, T, static_cast<TO *>(O), ldo);                   \
+    SPED_TRY(set_max_lds(tsmm_kernel<TX, TO, B, ADD>, shm));                                             \
+    hipLaunchKernelGGL((tsmm_kernel<TX, TO, B, ADD>), dim3(blocks), dim3(kBlock), shm, s, n, kin, kout,  \
+                       static_cast<const TX *>(X), ldx, T, static_cast<TO *>(O), ldo,                    \
+                       static_cast<const TO *>(Y), ldy, beta);                                           \
   }
   if (TBO <= 1) SPED_TSMM(1)
   else if (TBO <= 2) SPED_TSMM(2)
@@ -481,13 +488,23 @@ sped_status launch_gram(int64_t n, int ka, int kb, const void *A, int64_t lda, i
 }
 
 sped_status launch_tsmm(int64_t n, int kin, int kout, const void *X, int64_t ldx, int tx, const double *T,
-                        void *O, int64_t ldo, int to, hipStream_t s) {
+                        void *O, int64_t ldo, int to, hipStream_t s, const void *Y, int64_t ldy, float beta) {
   if (kin < 1 || kout < 1 || kin > kMaxK || kout > kMaxK) return fail(SPED_E_UNSUPPORTED, "tsmm width outside [1, 128]");
   if (n == 0) return SPED_OK;
-  if (tx == SPED_F32 && to == SPED_F32) return launch_tsmm_t<float, float>(n, kin, kout, X, ldx, T, O, ldo, s);
-  if (tx == SPED_F32 && to == SPED_BF16) return launch_tsmm_t<float, bf16_t>(n, kin, kout, X, ldx, T, O, ldo, s);
-  if (tx == SPED_BF16 && to == SPED_F32) return launch_tsmm_t<bf16_t, float>(n, kin, kout, X, ldx, T, O, ldo, s);
-  if (tx == SPED_BF16 && to == SPED_BF16) return launch_tsmm_t<bf16_t, bf16_t>(n, kin, kout, X, ldx, T, O, ldo, s);
+  if (Y && to != SPED_F32) return fail(SPED_E_UNSUPPORTED, "tsmm addend needs a float32 output");
+  if (Y) {
+    if (tx == SPED_F32) return launch_tsmm_t<float, float, true>(n, kin, kout, X, ldx, T, O, ldo, Y, ldy, beta, s);
+    if (tx == SPED_BF16) return launch_tsmm_t<bf16_t, float, true>(n, kin, kout, X, ldx, T, O, ldo, Y, ldy, beta, s);
+    return fail(SPED_E_UNSUPPORTED, "tsmm dtype");
+  }
+  if (tx == SPED_F32 && to == SPED_F32)
+    return launch_tsmm_t<float, float, false>(n, kin, kout, X, ldx, T, O, ldo, nullptr, 0, 0.f, s);
+  if (tx == SPED_F32 && to == SPED_BF16)
+    return launch_tsmm_t<float, bf16_t, false>(n, kin, kout, X, ldx, T, O, ldo, nullptr, 0, 0.f, s);
+  if (tx == SPED_BF16 && to == SPED_F32)
+    return launch_tsmm_t<bf16_t, float, false>(n, kin, kout, X, ldx, T, O, ldo, nullptr, 0, 0.f, s);
+  if (tx == SPED_BF16 && to == SPED_BF16)
+    return launch_tsmm_t<bf16_t, bf16_t, false>(n, kin, kout, X, ldx, T, O, ldo, nullptr, 0, 0.f, s);
   return fail(SPED_E_UNSUPPORTED, "tsmm dtype");
 }
 

@@ -6,6 +6,9 @@
 //                           Q <- Q S, residual block R = Z S - Q Theta and its
 //                           float64 Gram R^T R (column norms, ||R||_2 bound)
 // Block Oja with step eta iterates on M + I/eta (the same subspace update).
+// mu-EigenGame (solver 2) replaces the Cholesky QR by the game's update,
+// V <- normalise(V + eta grad), which recovers the ordered eigenvectors one by
+// one; its checks run Rayleigh-Ritz on an orthonormalised copy of V.
 // The host loop only reads 2(k + guard) doubles and 3 flags per check.
 #include <chrono>
 #include <cmath>
@@ -46,6 +49,46 @@ sped_status copy_block(int64_t n, int k, const void *in, int64_t ldi, int ti, vo
   else if (ti == SPED_BF16 && to == SPED_BF16) SPED_COPY(bf16_t, bf16_t);
   else return fail(SPED_E_UNSUPPORTED, "copy dtype");
 #undef SPED_COPY
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+// mu-EigenGame coefficients, one thread per player i.  G1 = V^T (M V) and G3
+// is the Gram of the unnormalised iterate V' with V = V' D^{-1},
+// D = diag(sqrt(G3_ii)), so (V^T V)_ji = G3_ji / (D_j D_i).  The projected
+// gradient of player i is
+//   grad_i = M v_i - sum_{j<i} G1_ji v_j - d_i v_i,
+//   d_i = <M v_i - sum_{j<i} G1_ji v_j, v_i> = G1_ii - sum_{j<i} G1_ji (V^T V)_ji,
+// and V + eta grad = V A + eta M V with A = I - eta (striu(G1) + diag(d))
+// (A row-major, A[j][i] multiplies column j into column i).
+__global__ void mueg_coeffs_kernel(int k, const double *__restrict__ G1, const double *__restrict__ G3, double eta,
+                                   double *__restrict__ A) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double di_ = sqrt(G3[i * k + i]);
+    double d = G1[i * k + i];
+    for (int j = 0; j < i; ++j) d -= G1[j * k + i] * (G3[j * k + i] / (sqrt(G3[j * k + j]) * di_));
+    for (int r = 0; r < k; ++r) A[r * k + i] = (r == i) ? 1.0 - eta * d : (r < i ? -eta * G1[r * k + i] : 0.0);
+  }
+}
+
+// Q[:, c] = X[:, c] / sqrt(G3_cc): unit columns from the Gram of X.
+__global__ __launch_bounds__(kBlock) void scale_cols_kernel(int64_t n, int k, const float *__restrict__ X,
+                                                            int64_t ldx, const double *__restrict__ G3,
+                                                            float *__restrict__ Q, int64_t ldq) {
+  const int64_t total = n * k;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t r = i / k;
+    const int c = int(i - r * k);
+    Q[r * ldq + c] = float(double(X[r * ldx + c]) / sqrt(G3[c * k + c]));
+  }
+}
+
+sped_status scale_cols(int64_t n, int k, const float *X, int64_t ldx, const double *G3, float *Q, int64_t ldq,
+                       hipStream_t s) {
+  if (n == 0) return SPED_OK;
+  int64_t blocks = (n * k + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, n, k, X, ldx, G3, Q, ldq);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
@@ -181,8 +224,9 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (!V0 || !V_out || !evals) return fail(SPED_E_INVALID, "NULL pointer");
   if (o->max_iters < 1 || o->check_every < 1) return fail(SPED_E_INVALID, "max_iters/check_every");
   if (o->orth_passes < 1 || o->orth_passes > 4) return fail(SPED_E_INVALID, "orth_passes");
-  if (o->solver != 0 && o->solver != 1) return fail(SPED_E_INVALID, "solver");
-  if (o->solver == 1 && !(o->eta > 0.0 && std::isfinite(o->eta))) return fail(SPED_E_INVALID, "eta");
+  if (o->solver < 0 || o->solver > 2) return fail(SPED_E_INVALID, "solver");
+  if (o->solver != 0 && !(o->eta > 0.0 && std::isfinite(o->eta))) return fail(SPED_E_INVALID, "eta");
+  if (o->solver == 2 && vdt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "mu-EigenGame needs F32 storage");
   if (!(o->tol >= 0.0)) return fail(SPED_E_INVALID, "tol");
   if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
   if (o->stochastic_iters > 0 && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
@@ -232,6 +276,13 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   rw.partials = ow.partials;
   int *flags = c.take<int>(4);
   ow.flags = rw.flags = flags;
+  // mu-EigenGame: its Grams and update matrix, and a buffer for the Ritz
+  // vectors of the checks (the game's iterate itself is kept)
+  const bool mueg = o->solver == 2;
+  double *G1 = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
+  double *G3 = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
+  double *Amu = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
+  float *Rtmp = mueg ? c.take<float>(size_t(n) * kb) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -264,13 +315,29 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
       } else {
         SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, s, &stats.spmm_count));
       }
-      SPED_TRY(cholqr(n, int(kb), W, Q, kb, dt, o->orth_passes, nullptr, ow, s));
+      if (mueg) {
+        // V <- normalise(V + eta grad), grad the projected mu-EG gradients
+        SPED_TRY(launch_gram(n, int(kb), int(kb), Q, kb, dt, W, kb, dt, G1, ow.partials, s));
+        hipLaunchKernelGGL(mueg_coeffs_kernel, dim3(1), dim3(128), 0, s, int(kb), G1, G3, o->eta, Amu);
+        SPED_CHECK_HIP(hipGetLastError());
+        SPED_TRY(launch_tsmm(n, int(kb), int(kb), Q, kb, dt, Amu, W, kb, dt, s, W, kb, float(o->eta)));
+        SPED_TRY(launch_gram(n, int(kb), int(kb), W, kb, dt, W, kb, dt, G3, ow.partials, s));
+        SPED_TRY(scale_cols(n, int(kb), static_cast<const float *>(W), kb, G3, static_cast<float *>(Q), kb, s));
+      } else {
+        SPED_TRY(cholqr(n, int(kb), W, Q, kb, dt, o->orth_passes, nullptr, ow, s));
+      }
       if ((t - first + 1) % o->check_every == 0 || t == iter_cap) {
         rw.Z = bufA;
         rw.ZS = bufB;
-        rw.Qtmp = W;
-        SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), Q, kb, dt, rw, s));
-        std::swap(Q, W);  // Ritz vectors now in Q
+        if (mueg) {  // Ritz pairs of L on span(V), from an orthonormalised copy
+          SPED_TRY(cholqr(n, int(kb), Q, W, kb, dt, o->orth_passes, nullptr, ow, s));
+          rw.Qtmp = Rtmp;
+          SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), W, kb, dt, rw, s));
+        } else {
+          rw.Qtmp = W;
+          SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), Q, kb, dt, rw, s));
+          std::swap(Q, W);  // Ritz vectors now in Q
+        }
         stats.spmm_count += 1;
         SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
@@ -323,7 +390,12 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   } else {
     SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, W, kb, SPED_F32, s));
   }
-  SPED_TRY(cholqr(n, int(kb), W, Q, kb, SPED_F32, o->orth_passes, nullptr, ow, s));
+  if (mueg) {  // the game starts from V0 with unit columns
+    SPED_TRY(launch_gram(n, int(kb), int(kb), W, kb, SPED_F32, W, kb, SPED_F32, G3, ow.partials, s));
+    SPED_TRY(scale_cols(n, int(kb), static_cast<const float *>(W), kb, G3, static_cast<float *>(Q), kb, s));
+  } else {
+    SPED_TRY(cholqr(n, int(kb), W, Q, kb, SPED_F32, o->orth_passes, nullptr, ow, s));
+  }
   done = false;
   if (t < o->max_iters) SPED_TRY(phase(SPED_F32, Q, W, o->tol, o->max_iters, 0, &done));
   sped_status result = done ? SPED_OK : SPED_E_NOT_CONVERGED;

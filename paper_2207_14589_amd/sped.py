@@ -328,7 +328,7 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
     V_out = torch.empty(L.n, k, dtype=torch.float32, device=dev)
     ev = np.zeros(k)
     rs = np.zeros(k)
-    o = SolveOpts(solver={"subspace": 0, "oja": 1}[solver], eta=eta, tol=tol, max_iters=max_iters,
+    o = SolveOpts(solver={"subspace": 0, "oja": 1, "mu_eg": 2}[solver], eta=eta, tol=tol, max_iters=max_iters,
                   check_every=check_every, guard=guard, orth_passes=orth_passes,
                   stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
                   coarse_tol=coarse_tol)

@@ -499,3 +499,45 @@ def test_tuned_coefficients_converge_to_true_subspace(sped):
     assert np.sin(ang) <= r6.stats["bound"] <= 1e-6
     _say(f"  loss {hist[0]:.4f} -> {min(hist):.4f}; iters to 1e-5: tuned {r.stats['iters']} "
          f"vs limit {r0.stats['iters']}")
+
+
+def test_mu_eigengame_trajectory_parity(sped):
+    """mu-EigenGame on the GPU follows the oracle's trajectory: same start
+    block, same step, 60 iterations of the degree-8 limit operator on the
+    2,000-node SBM; every player's vector within 1e-4 rad of the oracle's (the
+    guard players do not act on the first k: penalties only come from players
+    above)."""
+    _say("mu-EigenGame trajectory parity, SBM n=2000, k=10 (+4)")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    k, guard, eta, iters = 10, 4, 0.5, 60
+    V0 = synth.gaussian_block(n, k + guard, 2).astype(np.float32)
+    r = sped.bottomk(L, k, sped.transform("limit", 8), V0=torch.from_numpy(V0).cuda(), guard=guard, tol=0.0,
+                     max_iters=iters, check_every=iters, solver="mu_eg", eta=eta)
+    assert r.stats["iters"] == iters
+    p = opoly.limit_exp(8)
+    Vo, _ = osol.mu_eigengame(lambda X: opoly.apply_terms(ref.L, p, X), V0[:, :k].astype(np.float64), eta, iters)
+    Vg = r.V.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(np.linalg.norm(Vg, axis=0), 1.0, rtol=1e-5)
+    assert osol.vector_angles(Vo, Vg).max() < 1e-4
+
+
+def test_mu_eigengame_recovers_path_eigenvectors(sped):
+    """On the path P_40 (distinct eigenvalues, closed-form eigenvectors) the
+    GPU game converges to each of the bottom 4 eigenvectors individually, in
+    order: full streak, every angle below 1e-3 (float32)."""
+    _say("mu-EigenGame on P_40, k=4 (+2)")
+    n, k, guard = 40, 4, 2
+    _, s, d = synth.path_graph(n)
+    L = sped.Laplacian(n, s, d, kind="combinatorial")
+    x = np.arange(n)
+    U = np.stack([np.cos(np.pi * j * (x + 0.5) / n) for j in range(k)], axis=1)
+    U /= np.linalg.norm(U, axis=0)
+    V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 4).astype(np.float32)).cuda()
+    r = sped.bottomk(L, k, sped.transform("limit", 16), V0=V0, guard=guard, tol=0.0, max_iters=6000,
+                     check_every=6000, solver="mu_eg", eta=0.5)
+    Vg = r.V.cpu().numpy().astype(np.float64)
+    ang = osol.vector_angles(U, Vg)
+    assert osol.eigenvector_streak(U, Vg) == k
+    assert ang.max() < 1e-3

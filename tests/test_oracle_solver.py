@@ -63,6 +63,53 @@ def test_stop_bound_dominates_true_angle(sbm2000):
         assert np.sin(h["angle"]) <= h["bound"] * (1 + 1e-9)
 
 
+def _path_eigvecs(n, k):
+    """Closed-form bottom eigenvectors of the combinatorial Laplacian of the
+    path P_n: u_j(x) = cos(pi j (x + 1/2) / n), eigenvalue 2 - 2 cos(pi j / n)."""
+    x = np.arange(n)
+    U = np.stack([np.cos(np.pi * j * (x + 0.5) / n) for j in range(k)], axis=1)
+    return U / np.linalg.norm(U, axis=0), 2 - 2 * np.cos(np.pi * np.arange(k) / n)
+
+
+@pytest.mark.parametrize("op", ["limit", "plain"])
+def test_mu_eigengame_recovers_ordered_eigenvectors(op):
+    """On P_12 (all eigenvalues distinct) mu-EG converges to each of the bottom
+    four eigenvectors of L individually and in order (the closed forms), for
+    the dilated operator and for plain L reversed."""
+    n, k = 12, 4
+    _, s, d = synth.path_graph(n)
+    lap = olap.laplacian(n, s, d, kind=olap.COMBINATORIAL)
+    U, lam = _path_eigvecs(n, k)
+    np.testing.assert_allclose(lap.L @ U, U * lam, atol=1e-12)
+    p = opoly.limit_exp(8) if op == "limit" else opoly.plain(lap.lambda_bound)
+    V0 = synth.gaussian_block(n, k, 3)
+    V, hist = osol.mu_eigengame(lambda X: opoly.apply_terms(lap.L, p, X), V0, eta=0.5, iters=4000,
+                                Vstar=U, record_every=500)
+    assert np.all(osol.vector_angles(U, V) < 1e-7)
+    assert hist[-1]["streak"] == k
+    np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-14)
+
+
+def test_mu_eigengame_fixed_point_and_first_player_is_oja():
+    """The ordered eigenbasis is a fixed point; player 1 alone follows Oja's
+    normalised rule for the top eigenvector, whatever the other players do."""
+    n, k = 12, 4
+    _, s, d = synth.path_graph(n)
+    lap = olap.laplacian(n, s, d, kind=olap.COMBINATORIAL)
+    U, _ = _path_eigvecs(n, k)
+    p = opoly.limit_exp(8)
+    apply_M = lambda X: opoly.apply_terms(lap.L, p, X)
+    V1, _ = osol.mu_eigengame(apply_M, U, eta=0.5, iters=1)
+    np.testing.assert_allclose(np.abs(np.sum(V1 * U, axis=0)), 1.0, atol=1e-13)
+    g = np.random.default_rng(5)
+    V0 = g.standard_normal((n, k))
+    V2, _ = osol.mu_eigengame(apply_M, V0, eta=0.3, iters=1)
+    v = V0[:, 0] / np.linalg.norm(V0[:, 0])
+    mv = apply_M(v[:, None])[:, 0]
+    w = v + 0.3 * (mv - (v @ mv) * v)
+    np.testing.assert_allclose(V2[:, 0], w / np.linalg.norm(w), rtol=1e-12)
+
+
 @pytest.fixture(scope="module")
 def sbm2000():
     n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
