@@ -282,6 +282,105 @@ def mu_eg_streak_sbm2000(sped, synth, torch, np):
     return out
 
 
+def _dense_lap(L, np):
+    rowptr, col, val, diag, _ = L.host_csr()
+    n = L.n
+    Ld = np.diag(diag.astype(np.float64))
+    Ld[np.repeat(np.arange(n), np.diff(rowptr)), col] -= val.astype(np.float64)
+    return np.linalg.eigh(Ld)
+
+
+def _sin_angle(U, V, np):
+    Q, _ = np.linalg.qr(V.astype(np.float64))
+    return float(np.linalg.norm(Q - U @ (U.T @ Q), 2))
+
+
+def paper_experiments(sped, synth, torch, np):
+    """Qualitative reproductions of the paper's own synthetic experiments on
+    the GPU solvers (combinatorial Laplacian, as there).
+    cliques: n nodes in c cliques joined by 0-25 random short-circuit edges per
+      clique pair (Sec. 5, cliques); subspace iteration to 1e-6 (cap 200) with
+      plain L reversed and the limit operator of degree 11/51/151/251 (App. A,
+      series accuracy): success means the bottom-c subspace was reached.
+    mdp_3room: the 3-room grid world, s = 2, h = 10 (Sec. 5, proto-value
+      functions), bottom 3 (the room modes; +2 guard): the paper's subspace
+      error 1 - ||U*^T Q||_F^2 / k against the dense eigenvectors after T
+      iterations of subspace iteration, block Oja and mu-EigenGame (step
+      0.5 / rho(M) for the last two), and the mu-EG eigenvector streak, for
+      the identity and the degree-251 limit and Taylor forms of -e^{-L}.  The
+      solver's own residual bound is not used here: at degree 251 float32
+      rounding leaves high-frequency noise whose residual overstates the angle
+      by about lambda_max / gap."""
+    from paper_2207_14589_amd import metrics
+
+    def solve(L, k, p, V0, U, guard, max_iters, tol=1e-6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=tol, max_iters=max_iters)
+        except RuntimeError as e:
+            return {"reached_bottom": False, "error": str(e).split(": ")[-1]}
+        sec = time.perf_counter() - t0
+        ang = _sin_angle(U, r.V.cpu().numpy(), np)
+        return {"reached_bottom": bool(r.converged and ang < 10 * tol), "iters": r.stats["iters"],
+                "seconds": round(sec, 4), "sin_angle_to_bottom": ang}
+
+    out = {"cliques": []}
+    for n, c in ((1000, 5), (2000, 5), (2000, 4)):
+        N, s, d, _ = synth.cliques_short_circuit(n, c, seed=1)
+        L = sped.Laplacian(N, s, d, kind="combinatorial")
+        lam, U = _dense_lap(L, np)
+        V0 = torch.from_numpy(synth.gaussian_block(N, c + 2, 2).astype(np.float32)).cuda()
+        rec = {"n": N, "c": c, "lambda_max": float(lam[-1]), "plain": solve(L, c, None, V0, U[:, :c], 2, 200)}
+        for ell in (11, 51, 151, 251):
+            rec[f"limit{ell}"] = dict(solve(L, c, sped.transform("limit", ell), V0, U[:, :c], 2, 200),
+                                      two_l_above_lambda_max=bool(2 * ell > lam[-1]))
+        out["cliques"].append(rec)
+
+    N, s, d = synth.three_room_grid(2, 10)
+    L = sped.Laplacian(N, s, d, kind="combinatorial")
+    lam, U = _dense_lap(L, np)
+    k, guard = 3, 2
+    V0 = torch.from_numpy(synth.gaussian_block(N, k + guard, 2).astype(np.float32)).cuda()
+    Uk = U[:, :k]
+    Uref = torch.from_numpy(Uk.astype(np.float32)).cuda()
+    checkpoints = [10, 40, 160, 640, 2560, 10240]
+    mdp = {"n": N, "k": k, "lambda_max": float(lam[-1]), "checkpoints": checkpoints,
+           "target_subspace_error": 1e-8}
+
+    def subspace_error(V):
+        Q, _ = np.linalg.qr(V.astype(np.float64))
+        return float(max(0.0, 1.0 - np.linalg.norm(Uk.T @ Q) ** 2 / k))
+
+    for name, p, rho in (("identity", None, L.lambda_bound),
+                         ("limit251", sped.transform("limit", 251), 1.0),
+                         ("taylor_exp251", sped.transform("taylor_exp", 251), 1.0)):
+        rec = {}
+        for solver, eta in (("subspace", 1.0), ("oja", 0.5 / rho), ("mu_eg", 0.5 / rho)):
+            errs, streaks = [], []
+            done = False
+            for T in checkpoints:  # later checkpoints are skipped once the target is met
+                if done:
+                    errs.append(None)
+                    if solver == "mu_eg":
+                        streaks.append(None)
+                    continue
+                r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=T, check_every=T, solver=solver,
+                                 eta=eta)
+                errs.append(subspace_error(r.V.cpu().numpy()))
+                if solver == "mu_eg":
+                    streaks.append(metrics.eigenvector_streak(Uref, r.V))
+                done = errs[-1] < 1e-8 and (solver != "mu_eg" or streaks[-1] == k)
+            hit = [T for T, e in zip(checkpoints, errs) if e is not None and e < 1e-8]
+            rec[solver] = {"eta": eta if solver != "subspace" else None, "subspace_error": errs,
+                           "first_checkpoint_below_target": hit[0] if hit else None}
+            if solver == "mu_eg":
+                rec[solver]["streak"] = streaks
+        mdp[name] = rec
+    out["mdp_3room"] = mdp
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,7 +424,8 @@ def main():
     if args.tolerance_only:
         out = {"time_to_tolerance": time_to_tolerance(sped, synth, torch, np),
                "time_to_tolerance_sbm500k": time_to_tolerance_sbm500k(sped, synth, torch, np),
-               "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np)}
+               "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np),
+               "paper_experiments": paper_experiments(sped, synth, torch, np)}
         print(json.dumps(out), flush=True)
         return
     k, ell, walks = 32, 16, 8
@@ -406,6 +506,7 @@ def main():
         line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
         line["time_to_tolerance_sbm500k"] = time_to_tolerance_sbm500k(sped, synth, torch, np)
         line["mu_eg_streak"] = mu_eg_streak_sbm2000(sped, synth, torch, np)
+        line["paper_experiments"] = paper_experiments(sped, synth, torch, np)
     if not args.no_cpu_baseline and not args.chain_only:
         line["cpu_baseline"] = cpu_baseline_leg(n, s, d, X, ell, per_launch)
     print(json.dumps(line), flush=True)

@@ -541,3 +541,35 @@ def test_mu_eigengame_recovers_path_eigenvectors(sped):
     ang = osol.vector_angles(U, Vg)
     assert osol.eigenvector_streak(U, Vg) == k
     assert ang.max() < 1e-3
+
+
+@pytest.mark.parametrize("n,c", [(2000, 5), (2000, 4)])
+def test_limit_degree_threshold_cliques_gpu(sped, n, c):
+    """The paper's clique experiments at full size on the GPU solver: with 5
+    cliques of 400 (lambda_max 404) the degree-251 limit operator reaches the
+    bottom-5 subspace and degree 151 does not; with 4 cliques of 500
+    (lambda_max 503 > 2 x 251) degree 251 fails too.  Plain L reversed always
+    succeeds; a successful limit operator needs far fewer iterations.  A failure
+    is a wrong subspace, a cap hit, or a non-finite operator in float32."""
+    _say(f"limit-degree threshold on cliques n={n} c={c}")
+    N, s, d, _ = synth.cliques_short_circuit(n, c, seed=1)
+    L = sped.Laplacian(N, s, d, kind="combinatorial")
+    ref = olap.laplacian(N, s, d, kind=olap.COMBINATORIAL)
+    lam, U, full = osol.dense_bottom_k(ref.dense(), c)
+    V0 = torch.from_numpy(synth.gaussian_block(N, c + 2, 2).astype(np.float32)).cuda()
+
+    def outcome(p):
+        try:
+            r = sped.bottomk(L, c, p, V0=V0, guard=2, tol=1e-6, max_iters=200)
+        except RuntimeError:
+            return False, None
+        ang = osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64))
+        return bool(r.converged and ang < 1e-4), r.stats["iters"]
+
+    ok, plain_iters = outcome(None)
+    assert ok
+    for ell in (151, 251):
+        ok, iters = outcome(sped.transform("limit", ell))
+        assert ok == (2 * ell > full[-1])
+        if ok:
+            assert iters * 5 < plain_iters

@@ -208,3 +208,30 @@ def test_gradient_finite_differences_and_adjoint():
     Xm[4, 1] -= h
     fd = (0.5 * np.sum(ograd.forward(lap.L, theta, Xp) ** 2) - 0.5 * np.sum(ograd.forward(lap.L, theta, Xm) ** 2)) / (2 * h)
     assert fd == pytest.approx(dX2[4, 1], rel=1e-6)
+
+
+def test_limit_degree_must_cover_the_spectrum_on_cliques():
+    """Sec. 5 (cliques) and App. A (series accuracy): the limit approximation
+    (I - L/l)^l of the combinatorial Laplacian reverses the spectrum only when
+    it is accurate up to lambda_max, i.e. 2 l > lambda_max (else |1 - lambda/l|^l
+    blows up at the top of the spectrum and the iteration locks onto the top
+    eigenvectors of L).  200 nodes in 4 cliques (lambda_max = 54.2): l = 11, 21,
+    25 end on a wrong subspace, l = 31, 51 reach the bottom-4 subspace in a few
+    iterations, far fewer than plain L reversed."""
+    N, s, d, _ = synth.cliques_short_circuit(200, 4, seed=1)
+    lap = olap.laplacian(N, s, d, kind=olap.COMBINATORIAL)
+    lam, U, full = osol.dense_bottom_k(lap.dense(), 4)
+    assert full[-1] == pytest.approx(54.16, abs=0.01)
+    V0 = synth.gaussian_block(N, 6, 2)
+    plain = osol.subspace_iteration(lap.L, lambda X: opoly.apply_terms(lap.L, opoly.plain(lap.lambda_bound), X), 4,
+                                    V0, max_iters=300, tol=1e-8, guard=2)
+    assert plain.converged and osol.max_principal_angle(U, plain.Q) < 1e-6
+    for ell in (11, 21, 25, 31, 51):
+        with np.errstate(all="ignore"):
+            r = osol.subspace_iteration(lap.L, lambda X, l=ell: opoly.apply_limit_product(lap.L, l, X), 4, V0,
+                                        max_iters=300, tol=1e-8, guard=2)
+        ang = osol.max_principal_angle(U, r.Q)
+        if 2 * ell > full[-1]:
+            assert r.converged and ang < 1e-6 and r.iters * 5 < plain.iters
+        else:
+            assert ang > 1.0
