@@ -255,6 +255,31 @@ def cliques_short_circuit(n: int, c: int, seed: int, max_cross: int = 25):
     return c * sz, a, b, labels
 
 
+def link_prediction_cliques(n: int, c: int, seed: int, p_remove: float = 0.2, max_cross: int = 25):
+    """The clique graph of `cliques_short_circuit` with each edge removed with
+    probability p_remove, then completed by common-neighbours link prediction:
+    every removed pair gets the number of neighbours its endpoints share in the
+    remaining graph, divided by the largest such score, as its weight (kept
+    edges weigh 1; removed pairs with no common neighbour stay absent).
+    Returns (n, src, dst, w, labels)."""
+    N, a, b, labels = cliques_short_circuit(n, c, seed, max_cross)
+    g = rng(seed + 1)
+    removed = g.random(a.shape[0]) < p_remove
+    ka, kb = a[~removed], b[~removed]
+    adj = [set() for _ in range(N)]
+    for u, v in zip(ka.tolist(), kb.tolist()):
+        adj[u].add(v)
+        adj[v].add(u)
+    ra, rb = a[removed], b[removed]
+    score = np.array([len(adj[u] & adj[v]) for u, v in zip(ra.tolist(), rb.tolist())], dtype=np.float64)
+    keep = score > 0
+    w_pred = score[keep] / score.max() if keep.any() else score[keep]
+    src = np.concatenate([ka, ra[keep]])
+    dst = np.concatenate([kb, rb[keep]])
+    w = np.concatenate([np.ones(ka.shape[0]), w_pred])
+    return N, src, dst, w, labels
+
+
 def three_room_grid(s: int = 2, h: int = 10):
     """State graph of a grid world (10s+1) tall and (30s+1) wide split into three
     rooms by two internal walls, each with a door (10s+1)//h cells tall; edges

@@ -573,3 +573,23 @@ def test_limit_degree_threshold_cliques_gpu(sped, n, c):
         assert ok == (2 * ell > full[-1])
         if ok:
             assert iters * 5 < plain_iters
+
+
+def test_weighted_link_prediction_graph(sped):
+    """Sec. 5 (link prediction): on cliques completed by common-neighbour
+    weights the degree-151 limit operator (2 x 151 > lambda_max) reaches the
+    oracle's bottom-5 subspace of the weighted combinatorial Laplacian in far
+    fewer iterations than plain L, and k-means on it recovers the cliques."""
+    _say("weighted link-prediction cliques n=500 c=5")
+    N, s, d, w, labels = synth.link_prediction_cliques(500, 5, seed=2)
+    L = sped.Laplacian(N, s, d, w, kind="combinatorial")
+    ref = olap.laplacian(N, s, d, w, kind=olap.COMBINATORIAL)
+    lam, U, full = osol.dense_bottom_k(ref.dense(), 5)
+    assert 2 * 151 > full[-1]
+    V0 = torch.from_numpy(synth.gaussian_block(N, 7, 2).astype(np.float32)).cuda()
+    r = sped.bottomk(L, 5, sped.transform("limit", 151), V0=V0, guard=2, tol=1e-6, max_iters=500)
+    r0 = sped.bottomk(L, 5, None, V0=V0, guard=2, tol=1e-6, max_iters=500)
+    assert r.converged and r0.converged and r.stats["iters"] * 5 < r0.stats["iters"]
+    assert osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64)) < 1e-4
+    lab, _, _, _ = sped.cluster_embed(r.V, 5, row_normalize=False, seed=1)
+    assert okm.adjusted_rand_index(labels, lab.cpu().numpy()) == pytest.approx(1.0)
