@@ -405,6 +405,33 @@ def paper_experiments(sped, synth, torch, np):
     return out
 
 
+def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
+    """The two unbiased estimates of (I - L/l)^l V at the same walks per row:
+    the importance edge-chain walk (Sec. 4.3) and the lazy node walk (bounded
+    weights, one row gather per walk), as relative Frobenius error against
+    the exact product, on the solver's current iterate Q (near the bottom
+    eigenvectors) and on the Gaussian block X; and the lazy walk's time."""
+    out = {"walks_per_row": walks}
+    for name, V in (("on_iterate", Q), ("on_gaussian", torch.from_numpy(X).cuda())):
+        exact = sped.apply_poly(L, p, V)
+        edge = sped.apply_poly_stochastic(L, coeffs, V, walks=walks, seed=7)
+        lazy = sped.apply_limit_lazy(L, ell, V, walks, seed=7)
+        nrm = float(exact.norm())
+        out[name] = {"rel_err_edge_walk": float((edge - exact).norm()) / nrm,
+                     "rel_err_lazy_walk": float((lazy - exact).norm()) / nrm}
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    Y = torch.empty_like(Q)
+    for i, (a, b) in enumerate(evs):
+        a.record(stream)
+        sped.apply_limit_lazy(L, ell, Q, walks, seed=11, counter=i, out=Y)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)[len(evs) // 2]
+    out["lazy_walk_ms"] = round(ms, 4)
+    out["lazy_walks_per_s"] = round(L.n * walks / (ms * 1e-3), 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,6 +553,8 @@ def main():
                              if "walk_estimate_ms" in parts else None),
         "setup": {"graph_gen_s": round(gen_s, 3), "laplacian_build_s": round(build_s, 3)},
     }
+    if not args.chain_only:
+        line["estimators"] = estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream)
     if not args.no_solve and not args.chain_only:
         line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
         line["time_to_tolerance_sbm500k"] = time_to_tolerance_sbm500k(sped, synth, torch, np)

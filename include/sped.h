@@ -219,6 +219,32 @@ sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, 
                                        sped_stream_t stream);
 
 /*
+ * sped_apply_limit_lazy -- unbiased random estimate of Y = (I - L/ell)^ell X,
+ * the limit approximation of Table 2 (the default dilation), by lazy random
+ * walks on the nodes: a lower-variance estimator than the edge chains of
+ * Sec. 4.3 for this polynomial (the variance question Sec. 6 leaves open).
+ * For the normalised L, I - L/ell = D^{1/2} P D^{-1/2} with P the lazy walk
+ * that stays with probability 1 - 1/ell and otherwise moves to neighbour j with
+ * probability w_ij / d_i, so Y_r = E[s_Z X_Z] / s_r over the walk's position Z
+ * after ell steps from r.  For the combinatorial L, I - L/ell is itself the
+ * lazy walk (move with probability d_z / ell; requires ell >= max_i d_i), and
+ * Y_r = E[X_Z].  Each output row averages `walks` walks; each walk gathers one
+ * row of X.  Draws: Philox4x32-10 keyed by seed, counter (r, walk, counter,
+ * step << 8 | j); moves propose uniform neighbours accepted with probability
+ * w_j / max w (ratios within 2^-20 of 1 accept), falling back after 16
+ * rejections to an exact inverse-CDF draw.
+ *  ell     1..255
+ *  X       DEVICE n x k (ldx), F32 or BF16; Y DEVICE n x k (ldy), F32 or BF16;
+ *          X and Y must not overlap
+ *  ws      DEVICE scratch (2n doubles) or the size-query form
+ * Asynchronous on `stream`.
+ */
+sped_status sped_apply_limit_lazy(const sped_csr *L, int32_t ell, int64_t k, const void *X,
+                                  int64_t ldx, int32_t xdt, void *Y, int64_t ldy, int32_t ydt,
+                                  int64_t walks, uint64_t seed, uint64_t counter, void *ws,
+                                  size_t *ws_bytes, sped_stream_t stream);
+
+/*
  * sped_poly_backward -- coefficient gradient of Y = sum_j theta_j Lt^j X
  * (learnable dilation coefficients, the meta-learning direction of Sec. 6):
  * dtheta[j] = <dY, Lt^j X>_F for j = 0..degree, with Lt = (L - shift I)/scale.
@@ -307,10 +333,12 @@ typedef struct {
   int32_t check_every;     /* Rayleigh-Ritz cadence, >= 1 */
   int32_t guard;           /* extra columns, >= 1 */
   int32_t orth_passes;     /* Cholesky-QR passes per iteration (1 or 2) */
-  int32_t stochastic_iters;/* first iterations use the importance-sampled estimate */
+  int32_t stochastic_iters;/* first iterations use the random estimate (stochastic_sampler) */
   int64_t walks_per_row;   /* walks per row for those iterations */
   uint64_t seed;           /* Philox key; iteration t uses counter t */
   double coarse_tol;       /* BF16 phase stops at this bound (<= 0: 1e-2) */
+  int32_t stochastic_sampler; /* 0 = importance edge walks (Sec. 4.3), 1 = lazy node walks
+                                 (sped_apply_limit_lazy; needs the limit polynomial, solver 0 or 2) */
 } sped_solve_opts;
 
 typedef struct {

@@ -1,0 +1,138 @@
+"""Lazy node-walk estimator of the limit polynomial (I - L/l)^l V (oracle; test
+infrastructure only).
+
+Variance of the edge-chain estimators is left open by the paper (Sec. 6);
+their weights grow with the product of H-degrees along a chain.  For the
+limit approximation of Table 2 (last row) there is a walk with bounded
+weights on the nodes of G:
+
+* normalised L = I - D^{-1/2} A D^{-1/2}: I - L/l = D^{1/2} P D^{-1/2} with
+  P = (1 - 1/l) I + (1/l) D^{-1} A, a lazy random walk (stay with probability
+  1 - 1/l, else move to neighbour j with probability w_ij / d_i); hence
+  ((I - L/l)^l V)_r = E[ s_Z V_Z ] / s_r over the walk's position Z after l
+  steps from r, s = d^{-1/2};
+* combinatorial L = D - A with l >= max_i d_i: I - L/l is itself stochastic
+  (stay with probability 1 - d_i/l, move to j with probability w_ij / l), so
+  ((I - L/l)^l V)_r = E[ V_Z ].
+Isolated nodes never move (their row of L is zero).
+
+Draws (both sides), key = seed, counter (r, w, c, step << 8 | j) for output row
+r, walk w, application counter c:
+* step t = 1..l: u = uniform53(step t); the walk moves when u < p_move(z),
+  p_move = 1/l (normalised, degree > 0) or d_z / l (combinatorial);
+* a move proposes neighbour number bounded(step 256 + 1024 t + a, deg z) for
+  attempt a = 0..15 and accepts it when its weight ratio x_j / max_row x is
+  at least 1 - 2^-20 (weights this close count as equal: unweighted graphs
+  never reach the test below) or when uniform53(step 2^20 + 1024 t + a) is
+  below the ratio; x_j = w_ij (combinatorial) or S_ij / s_j (normalised,
+  proportional to w_ij within a row), in the precision the device stores
+  (float32 S and s, ratios in float64);
+* after 16 rejections, neighbour j is the first whose running sum of x (row
+  order) exceeds uniform53(step 2^21 + t) times the row sum: rejection with a
+  cap followed by the exact inverse-CDF draw is still exact.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import rng
+from .laplacian import COMBINATORIAL, SYM_NORMALIZED, Laplacian
+
+_ATTEMPTS = 16
+_EQUAL = 1.0 - 2.0 ** -20
+
+
+def _device_weights(lap: Laplacian):
+    """Row-major adjacency (neighbours ascending), per stored entry the move
+    weight x in the device's precision, per row the largest x, and the
+    float32 scale."""
+    rowptr, col, w = lap.adjacency()
+    n = lap.n
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    if lap.kind == SYM_NORMALIZED:
+        s32 = lap.scale.astype(np.float32)
+        val32 = (w * lap.scale[rows] * lap.scale[col]).astype(np.float32)
+        x = val32.astype(np.float64) / s32[col].astype(np.float64)
+    elif lap.kind == COMBINATORIAL:
+        s32 = np.ones(n, dtype=np.float32)
+        x = w.astype(np.float32).astype(np.float64)
+    else:
+        raise ValueError(lap.kind)
+    xmax = np.zeros(n)
+    nz = np.nonzero(np.diff(rowptr) > 0)[0]
+    if nz.size:
+        xmax[nz] = np.maximum.reduceat(x, rowptr[nz])
+    return rowptr, col, x, xmax, s32
+
+
+def estimate_lazy(lap: Laplacian, ell: int, V, walks_per_row: int, seed: int, counter: int = 0, rows=None):
+    """Unbiased estimate of rows `rows` (default all) of (I - L/l)^l V from
+    `walks_per_row` lazy walks per row.  Returns float64 (len(rows), k)."""
+    V = np.asarray(V, dtype=np.float64)
+    n = lap.n
+    rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
+    rowptr, col, x, xmax, s32 = _device_weights(lap)
+    deg = np.diff(rowptr)
+    if lap.kind == SYM_NORMALIZED:
+        p_move = np.where(deg > 0, 1.0 / ell, 0.0)
+    else:
+        d32 = lap.degree.astype(np.float32).astype(np.float64)
+        if n and d32.max() > ell:
+            raise ValueError("combinatorial lazy walk needs l >= the largest weighted degree")
+        p_move = d32 / ell
+    r = np.repeat(rows, walks_per_row)
+    widx = np.tile(np.arange(walks_per_row), rows.shape[0])
+    z = r.copy()
+    for t in range(1, ell + 1):
+        u = rng.uniform53(seed, r, widx, counter, t)
+        movers = np.nonzero(u < p_move[z])[0]
+        chosen = np.full(movers.shape[0], -1, dtype=np.int64)
+        for a in range(_ATTEMPTS):
+            todo = np.nonzero(chosen < 0)[0]
+            if todo.size == 0:
+                break
+            m = movers[todo]
+            cand = rng.bounded(seed, r[m], widx[m], counter, 256 + 1024 * t + a, deg[z[m]]).astype(np.int64)
+            p = rowptr[z[m]] + cand
+            ratio = x[p] / xmax[z[m]]
+            acc = ratio >= _EQUAL
+            test = np.nonzero(~acc)[0]
+            if test.size:
+                u2 = rng.uniform53(seed, r[m[test]], widx[m[test]], counter, (1 << 20) + 1024 * t + a)
+                acc[test] = u2 < ratio[test]
+            chosen[todo[acc]] = p[acc]
+        left = np.nonzero(chosen < 0)[0]
+        for i in left:  # inverse CDF over the row: running sum in row order
+            m = movers[i]
+            zz = z[m]
+            a, b = rowptr[zz], rowptr[zz + 1]
+            run = np.cumsum(x[a:b])
+            target = rng.uniform53(seed, r[m], widx[m], counter, (1 << 21) + t) * run[-1]
+            hit = np.nonzero(run > target)[0]
+            chosen[i] = a + (hit[0] if hit.size else b - a - 1)
+        z[movers] = col[chosen]
+    weight = s32[z].astype(np.float64) / np.where(s32[r] > 0, s32[r], 1.0).astype(np.float64)
+    weight = np.where(s32[r] > 0, weight, 1.0)
+    est = weight[:, None] * V[z]
+    return est.reshape(rows.shape[0], walks_per_row, -1).mean(axis=1)
+
+
+def lazy_walk_matrix(lap: Laplacian, ell: int):
+    """The dense lazy-walk transition matrix P of the module header (for
+    checking the similarity to I - L/l)."""
+    n = lap.n
+    A = np.zeros((n, n))
+    np.add.at(A, (lap.eu, lap.ev), lap.ew)
+    np.add.at(A, (lap.ev, lap.eu), lap.ew)
+    d = lap.degree
+    P = np.zeros((n, n))
+    for i in range(n):
+        if d[i] == 0:
+            P[i, i] = 1.0
+        elif lap.kind == SYM_NORMALIZED:
+            P[i] = A[i] / d[i] / ell
+            P[i, i] += 1.0 - 1.0 / ell
+        else:
+            P[i] = A[i] / ell
+            P[i, i] += 1.0 - d[i] / ell
+    return P

@@ -349,6 +349,12 @@ sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degr
                                int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler, int64_t walks,
                                uint64_t seed, uint64_t counter, int64_t *accept_counts, hipStream_t s);
 
+// lazy node-walk estimate of (I - L/ell)^ell X; xmax, xsum: n doubles of scratch
+sped_status lazy_estimate_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
+                               int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, double *xmax,
+                               double *xsum, hipStream_t s);
+sped_status validate_lazy(const sped_csr *L, int ell, int64_t walks, uint64_t counter);
+
 sped_status apply_poly_impl(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
                             int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, float *bufA,
                             float *bufB, hipStream_t s, int64_t *spmm_count);

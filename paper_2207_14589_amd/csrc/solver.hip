@@ -229,8 +229,15 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->solver == 2 && vdt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "mu-EigenGame needs F32 storage");
   if (!(o->tol >= 0.0)) return fail(SPED_E_INVALID, "tol");
   if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
-  if (o->stochastic_iters > 0 && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
+  if (o->stochastic_sampler != 0 && o->stochastic_sampler != 1) return fail(SPED_E_INVALID, "stochastic_sampler");
+  const bool lazy = o->stochastic_iters > 0 && o->stochastic_sampler == 1;
+  if (o->stochastic_iters > 0 && !lazy && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
     return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and the walk records");
+  if (lazy) {
+    if (!p || p->kind != SPED_POLY_LIMIT) return fail(SPED_E_INVALID, "lazy walks estimate the limit polynomial only");
+    if (o->solver == 1) return fail(SPED_E_UNSUPPORTED, "lazy walks with block Oja (M + I/eta) are not supported");
+    SPED_TRY(validate_lazy(L, p->degree, o->walks_per_row, uint64_t(o->max_iters)));
+  }
 
   // the operator actually iterated on
   std::vector<double> plain_c = {L->lambda_bound, -1.0};
@@ -248,7 +255,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     M.coeffs = oja_c.data();
   }
   std::vector<double> walk_c;
-  if (o->stochastic_iters > 0) {
+  if (o->stochastic_iters > 0 && !lazy) {
     walk_c = monomial_in_L(M);
     if (M.degree > 255) return fail(SPED_E_UNSUPPORTED, "stochastic iterations need degree <= 255");
   }
@@ -283,6 +290,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   double *G3 = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
   double *Amu = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
   float *Rtmp = mueg ? c.take<float>(size_t(n) * kb) : nullptr;
+  double *lz_max = lazy ? c.take<double>(size_t(n)) : nullptr;
+  double *lz_sum = lazy ? c.take<double>(size_t(n)) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -309,7 +318,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     double best = INFINITY;
     int since_best = 0;
     for (t = first; t <= iter_cap; ++t) {
-      if (t <= o->stochastic_iters) {
+      if (t <= o->stochastic_iters && lazy) {
+        SPED_TRY(lazy_estimate_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
+                                    lz_max, lz_sum, s));
+      } else if (t <= o->stochastic_iters) {
         SPED_TRY(walk_estimate_impl(L, walk_c.data(), M.degree, kb, Q, kb, dt, W, kb, dt, 0, o->walks_per_row,
                                     o->seed, uint64_t(t), nullptr, s));
       } else {

@@ -252,6 +252,123 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
   }
 }
 
+// ---------------------------------------------------------------- lazy node walks
+// (I - L/l)^l X for the limit polynomial of Table 2 by lazy random walks on the
+// nodes.  Normalised L: I - L/l = D^{1/2} P D^{-1/2}, P = (1 - 1/l) I +
+// (1/l) D^{-1} A, so row r is E[s_Z X_Z] / s_r over the position Z after l
+// lazy steps from r.  Combinatorial L with l >= max d: I - L/l is itself
+// stochastic (move with probability d_z / l), row r is E[X_Z].  A move picks a
+// neighbour with probability proportional to w: up to 16 uniform proposals
+// accepted with probability x_j / max x (x = S_ij / s_j or w_ij, float64 from
+// the stored float32 values; ratios within 2^-20 of 1 count as 1), then an
+// exact inverse-CDF draw over the row.  Weights are bounded by max s / min s,
+// and each walk gathers one X row.
+constexpr int kLazyAttempts = 16;
+constexpr double kLazyEqual = 1.0 - 0x1.0p-20;
+
+__device__ inline double lazy_x(int kind, const int32_t *__restrict__ col, const float *__restrict__ val,
+                                const float *__restrict__ scale, int64_t p) {
+  return kind == SPED_LAP_SYM_NORMALIZED ? double(val[p]) / double(scale[col[p]]) : double(val[p]);
+}
+
+// Per row: the largest move weight and the sum of the weights in row order.
+__global__ __launch_bounds__(kBlock) void lazy_row_stats_kernel(int64_t n, int kind,
+                                                                const int64_t *__restrict__ rowptr,
+                                                                const int32_t *__restrict__ col,
+                                                                const float *__restrict__ val,
+                                                                const float *__restrict__ scale,
+                                                                double *__restrict__ xmax, double *__restrict__ xsum) {
+  for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < n; r += int64_t(gridDim.x) * kBlock) {
+    double m = 0.0, sum = 0.0;
+    for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
+      const double x = lazy_x(kind, col, val, scale, p);
+      m = fmax(m, x);
+      sum += x;
+    }
+    xmax[r] = m;
+    xsum[r] = sum;
+  }
+}
+
+template <typename TX, typename TY, int VEC>
+__global__ __launch_bounds__(kBlock) void walk_lazy_kernel(
+    int64_t n, int64_t nb, int k, int G, int lgG, int kind, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ scale,
+    const float *__restrict__ diag, const double *__restrict__ xmax, const double *__restrict__ xsum, int ell,
+    const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y, int64_t ldy, int64_t walks, uint32_t k0,
+    uint32_t k1, uint32_t ctr) {
+  const int64_t lb = xcd_logical_block(nb);
+  if (lb >= nb) return;  // padding block (no barriers below)
+  const int lig = threadIdx.x & (G - 1);
+  const int64_t r = lb * (kBlock >> lgG) + (threadIdx.x >> lgG);
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
+  const bool col_ok = c0 < k;
+  const bool row_ok = r < n;
+  const int cc = col_ok ? c0 : 0;
+  const bool norm = kind == SPED_LAP_SYM_NORMALIZED;
+  const double inv_ell = 1.0 / double(ell);
+  const double rs = row_ok ? double(scale[r]) : 1.0;
+  float acc[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+  if (row_ok) {
+    RowBatch<TX, VEC> rb;
+    for (int64_t wbase = 0; wbase < walks; wbase += G) {
+      const int64_t w = wbase + lig;
+      const bool live = w < walks;
+      const int nlive = int(min<int64_t>(G, walks - wbase));
+      int32_t z = int32_t(r);
+      if (live) {
+        int64_t z0 = rowptr[z];
+        int64_t dz = rowptr[z + 1] - z0;
+        for (int t = 1; t <= ell; ++t) {
+          if (dz == 0) break;  // an isolated node never moves
+          const double pm = norm ? inv_ell : double(diag[z]) * inv_ell;
+          if (!(uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(t)) < pm)) continue;
+          int64_t chosen = -1;
+          for (int a = 0; a < kLazyAttempts && chosen < 0; ++a) {
+            const uint32_t j = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 256u + 1024u * uint32_t(t) + a,
+                                           uint32_t(dz));
+            const int64_t p = z0 + j;
+            const double ratio = lazy_x(kind, col, val, scale, p) / xmax[z];
+            if (ratio >= kLazyEqual ||
+                uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, (1u << 20) + 1024u * uint32_t(t) + a) < ratio)
+              chosen = p;
+          }
+          if (chosen < 0) {  // exact inverse-CDF draw over the row
+            const double target = uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, (1u << 21) + uint32_t(t)) * xsum[z];
+            double run = 0.0;
+            chosen = z0 + dz - 1;
+            for (int64_t p = z0; p < z0 + dz; ++p) {
+              run += lazy_x(kind, col, val, scale, p);
+              if (run > target) {
+                chosen = p;
+                break;
+              }
+            }
+          }
+          z = col[chosen];
+          z0 = rowptr[z];
+          dz = rowptr[z + 1] - z0;
+        }
+      }
+      double wt = 0.0;
+      if (live) wt = (norm && rs > 0.0) ? double(scale[z]) / rs : 1.0;
+      for (int j0 = 0; j0 < nlive; j0 += 8) {
+        rb.issue(X, ldx, cc, G, j0, float(wt), z);
+        rb.consume(col_ok, j0, nlive, acc);
+      }
+    }
+  }
+  if (row_ok && col_ok) {
+    float o[VEC];
+    const float inv = float(1.0 / double(walks));
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) o[v] = acc[v] * inv;
+    VecIO<TY, VEC>::store(Y + r * ldy + c0, o);
+  }
+}
+
 template <typename TX>
 __global__ __launch_bounds__(kBlock) void scale_init_kernel(int64_t n, int k, const TX *__restrict__ X,
                                                              int64_t ldx, float *__restrict__ Y, int64_t ldy,
@@ -435,6 +552,30 @@ sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degr
   return launch_rej<bf16_t>(L, k, X, ldx, static_cast<float *>(Y), ldy, degree, walks, k0, k1, ctr, accept_counts, cf, s);
 }
 
+template <typename TX, typename TY>
+sped_status launch_lazy(const sped_csr *L, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, int ell,
+                        int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, const double *xmax,
+                        const double *xsum, hipStream_t s) {
+  int vec = pick_vec(k, {ldx, ldy}, {X, Y}, {int(sizeof(TX)), int(sizeof(TY))});
+  int lanes = int((k + vec - 1) / vec);
+  int ytiles = (lanes + 63) / 64;
+  int G = lanes >= 64 ? 64 : next_pow2(lanes);
+  int lgG = ilog2(G);
+  const int64_t rows_per_block = kBlock >> lgG;
+  const int64_t nb = (L->n + rows_per_block - 1) / rows_per_block;
+  const dim3 grid = dim3(unsigned(xcd_padded_grid(nb)), unsigned(ytiles));
+#define SPED_LZ(V)                                                                                          \
+  hipLaunchKernelGGL((walk_lazy_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, nb, int(k), G, lgG,     \
+                     int(L->kind), L->rowptr, L->col, L->val, L->scale, L->diag, xmax, xsum, ell,           \
+                     static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr)
+  if (vec == 4) SPED_LZ(4);
+  else if (vec == 2) SPED_LZ(2);
+  else SPED_LZ(1);
+#undef SPED_LZ
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
 }  // namespace sped
 
 using namespace sped;
@@ -469,4 +610,63 @@ extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const doubl
   if (query || L->n == 0) return SPED_OK;
   return walk_estimate_impl(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
                             accept_counts, as_stream(stream));
+}
+
+namespace sped {
+
+sped_status lazy_estimate_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
+                               int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, double *xmax,
+                               double *xsum, hipStream_t s) {
+  if (L->n == 0) return SPED_OK;
+  int64_t blocks = (L->n + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(lazy_row_stats_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, L->n, int(L->kind),
+                     L->rowptr, L->col, L->val, L->scale, xmax, xsum);
+  SPED_CHECK_HIP(hipGetLastError());
+  const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32), ctr = uint32_t(counter);
+  if (xdt == SPED_F32 && ydt == SPED_F32)
+    return launch_lazy<float, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+  if (xdt == SPED_F32 && ydt == SPED_BF16)
+    return launch_lazy<float, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+  if (xdt == SPED_BF16 && ydt == SPED_F32)
+    return launch_lazy<bf16_t, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+  return launch_lazy<bf16_t, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+}
+
+sped_status validate_lazy(const sped_csr *L, int ell, int64_t walks, uint64_t counter) {
+  if (ell < 1 || ell > kMaxDeg) return fail(SPED_E_INVALID, "ell outside [1, 255]");
+  if (walks < 1 || walks >= (int64_t(1) << 32)) return fail(SPED_E_INVALID, "walks per row outside [1, 2^32)");
+  if (counter >= (uint64_t(1) << 32)) return fail(SPED_E_INVALID, "counter >= 2^32");
+  if (L->n >= (int64_t(1) << 31)) return fail(SPED_E_UNSUPPORTED, "n >= 2^31");
+  // combinatorial: the stay probability 1 - d/l must be non-negative
+  if (L->kind == SPED_LAP_COMBINATORIAL && 0.5 * L->lambda_bound > double(ell))
+    return fail(SPED_E_INVALID, "combinatorial lazy walk needs ell >= the largest weighted degree");
+  return SPED_OK;
+}
+
+}  // namespace sped
+
+extern "C" sped_status sped_apply_limit_lazy(const sped_csr *L, int32_t ell, int64_t k, const void *X, int64_t ldx,
+                                             int32_t xdt, void *Y, int64_t ldy, int32_t ydt, int64_t walks,
+                                             uint64_t seed, uint64_t counter, void *ws, size_t *ws_bytes,
+                                             sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (k < 1) return fail(SPED_E_INVALID, "k < 1");
+  if (ldx < k || ldy < k) return fail(SPED_E_INVALID, "leading dimension < k");
+  if ((xdt != SPED_F32 && xdt != SPED_BF16) || (ydt != SPED_F32 && ydt != SPED_BF16))
+    return fail(SPED_E_UNSUPPORTED, "dtype");
+  if (L->n > 0 && (!X || !Y)) return fail(SPED_E_INVALID, "X or Y NULL");
+  SPED_TRY(validate_lazy(L, ell, walks, counter));
+  Carver c(ws);
+  double *xmax = c.take<double>(size_t(L->n > 0 ? L->n : 1));
+  double *xsum = c.take<double>(size_t(L->n > 0 ? L->n : 1));
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query || L->n == 0) return SPED_OK;
+  const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
+  size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
+  if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
+  return lazy_estimate_impl(L, ell, k, X, ldx, xdt, Y, ldy, ydt, walks, seed, counter, xmax, xsum,
+                            as_stream(stream));
 }

@@ -89,6 +89,16 @@ def test_invalid_arguments_rejected_on_host(lib):
                                           None, ctypes.byref(need), None) == sped.E_INVALID
     assert lib.sped_apply_poly_stochastic(ctypes.byref(c), cp, 1, 4, None, 4, 0, None, 4, 1, 1, 8, 1, 0, None,
                                           None, ctypes.byref(need), None) == sped.E_UNSUPPORTED
+    # lazy walk: ell outside [1, 255]; combinatorial with ell below the largest degree
+    assert lib.sped_apply_limit_lazy(ctypes.byref(c), 0, 4, None, 4, 0, None, 4, 0, 8, 1, 0, None,
+                                     ctypes.byref(need), None) == sped.E_INVALID
+    cc = sped.CSR()
+    cc.n, cc.nnz, cc.kind, cc.lambda_bound = 0, 0, sped.COMBINATORIAL, 40.0
+    assert lib.sped_apply_limit_lazy(ctypes.byref(cc), 16, 4, None, 4, 0, None, 4, 0, 8, 1, 0, None,
+                                     ctypes.byref(need), None) == sped.E_INVALID
+    assert b"largest weighted degree" in lib.sped_last_error()
+    assert lib.sped_apply_limit_lazy(ctypes.byref(cc), 20, 4, None, 4, 0, None, 4, 0, 8, 1, 0, None,
+                                     ctypes.byref(need), None) == sped.OK
     # orthonormalize: k > n
     assert lib.sped_orthonormalize(3, 5, None, 5, 0, 2, None, None, ctypes.byref(need), None) == sped.E_INVALID
     # cluster: too many clusters

@@ -593,3 +593,90 @@ def test_weighted_link_prediction_graph(sped):
     assert osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64)) < 1e-4
     lab, _, _, _ = sped.cluster_embed(r.V, 5, row_normalize=False, seed=1)
     assert okm.adjusted_rand_index(labels, lab.cpu().numpy()) == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------- lazy node walk (variance-reduced estimator)
+from oracle import lazywalk as olazy  # noqa: E402
+
+
+@pytest.mark.parametrize("kind,ell", [("sym", 16), ("combinatorial", 32)])
+def test_lazy_walk_same_walks(sped, kind, ell):
+    """Same seed, same draws: every walk of the GPU estimator ends where the
+    oracle's does, so the estimates agree to float32 summation (2,000-node
+    unweighted SBM, 10 columns, 8 walks per row; combinatorial needs l >= the
+    largest degree)."""
+    _say(f"lazy walk same walks {kind} l={ell}")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind=kind)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED if kind == "sym" else olap.COMBINATORIAL)
+    X = synth.gaussian_block(n, 10, 2).astype(np.float32)
+    Y = sped.apply_limit_lazy(L, ell, torch.from_numpy(X).cuda(), 8, seed=5, counter=3).cpu().numpy()
+    Yo = olazy.estimate_lazy(ref, ell, X.astype(np.float64), 8, seed=5, counter=3)
+    assert np.abs(Y - Yo).max() <= 2e-6 * np.abs(Yo).max()
+
+
+def test_lazy_walk_weighted_hub_graph(sped):
+    """Weighted graph with a 9,000-edge hub, repeated edges and self-loops:
+    moves use the rejection proposals and the inverse-CDF fallback; at least
+    99.5% of rows agree with the oracle's walks (a decision can differ where a
+    weight ratio's float32 inputs round differently on the two sides)."""
+    _say("lazy walk weighted hub graph")
+    n, src, dst, w = mixed_degree_graph()
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 6, 3).astype(np.float32)
+    Y = sped.apply_limit_lazy(L, 12, torch.from_numpy(X).cuda(), 4, seed=9).cpu().numpy()
+    Yo = olazy.estimate_lazy(ref, 12, X.astype(np.float64), 4, seed=9)
+    ok = np.all(np.abs(Y - Yo) <= 2e-6 * np.abs(Yo).max(), axis=1)
+    assert ok.mean() >= 0.995
+
+
+def test_lazy_walk_unbiased(sped):
+    """Mean over 64 seeds against the exact (I - L/16)^16 X: per-entry z-scores
+    from the spread over seeds stay within a Bonferroni bound."""
+    _say("lazy walk unbiasedness, 64 seeds")
+    n, s, d, _ = synth.sbm_bernoulli([40] * 5, 0.2, 0.01, seed=4)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 4, 1).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    est = np.stack([sped.apply_limit_lazy(L, 16, Xd, 16, seed=100 + i).cpu().numpy() for i in range(64)])
+    exact = opoly.apply_limit_product(ref.L, 16, X.astype(np.float64))
+    z = np.abs(est.mean(0) - exact) / (est.std(0, ddof=1) / 8.0 + 1e-12)
+    assert z.max() < 5.0
+
+
+def test_lazy_walk_full_size_sampled_rows(sped, c2_case):
+    """The 10^6-node SBM at the bench's shape (k = 32, l = 16, 8 walks per row):
+    2,000 sampled rows match the oracle's walks for those rows."""
+    L, ref, X = c2_case
+    _say("lazy walk full size, sampled rows")
+    Y = sped.apply_limit_lazy(L, 16, torch.from_numpy(X).cuda(), 8, seed=3).cpu().numpy()
+    rows = np.random.default_rng(0).choice(L.n, 2000, replace=False)
+    Yo = olazy.estimate_lazy(ref, 16, X.astype(np.float64), 8, seed=3, rows=rows)
+    assert np.abs(Y[rows] - Yo).max() <= 2e-6 * np.abs(Yo).max()
+
+
+def test_solver_stochastic_phase_lazy_vs_edge_walks(sped):
+    """Solver iterations driven only by random estimates (8 walks per row,
+    degree-8 limit operator, 2,000-node SBM, 40 iterations): the lazy node
+    walk leaves the iterate closer to the true bottom-10 subspace than the
+    edge-chain walk; followed by exact iterations both reach 1e-6."""
+    _say("solver stochastic phase: lazy vs edge walks")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    p = sped.transform("limit", 8)
+    err = {}
+    for sampler in ("importance", "lazy"):
+        r = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=0.0, max_iters=40, stochastic_iters=40, walks_per_row=8,
+                         sampler=sampler)
+        err[sampler] = osol.subspace_error(U, r.V.cpu().numpy().astype(np.float64))
+        r2 = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=1e-6, max_iters=3000, stochastic_iters=20,
+                          walks_per_row=8, sampler=sampler)
+        assert r2.converged
+        assert osol.max_principal_angle(U, r2.V.cpu().numpy().astype(np.float64)) < 1e-5
+    assert err["lazy"] < err["importance"]
+    _say(f"  subspace error after 40 random iterations: edge {err['importance']:.3e}, lazy {err['lazy']:.3e}")
