@@ -230,9 +230,10 @@ sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, 
  * lazy walk (move with probability d_z / ell; requires ell >= max_i d_i), and
  * Y_r = E[X_Z].  Each output row averages `walks` walks; each walk gathers one
  * row of X.  Draws: Philox4x32-10 keyed by seed, counter (r, walk, counter,
- * step << 8 | j); moves propose uniform neighbours accepted with probability
- * w_j / max w (ratios within 2^-20 of 1 accept), falling back after 16
- * rejections to an exact inverse-CDF draw.
+ * step << 8 | j); the stays before each move are drawn at once as a geometric
+ * variable (one draw per move, not per step); moves propose uniform
+ * neighbours accepted with probability w_j / max w (ratios within 2^-20 of 1
+ * accept), falling back after 16 rejections to an exact inverse-CDF draw.
  *  ell     1..255
  *  X       DEVICE n x k (ldx), F32 or BF16; Y DEVICE n x k (ldy), F32 or BF16;
  *          X and Y must not overlap

@@ -18,8 +18,13 @@ Isolated nodes never move (their row of L is zero).
 
 Draws (both sides), key = seed, counter (r, w, c, step << 8 | j) for output row
 r, walk w, application counter c:
-* step t = 1..l: u = uniform53(step t); the walk moves when u < p_move(z),
-  p_move = 1/l (normalised, degree > 0) or d_z / l (combinatorial);
+* the walk stays at z with probability 1 - p_move(z) per step, p_move = 1/l
+  (normalised, degree > 0) or d_z / l (combinatorial); the number of stays
+  before its m-th move (m = 0, 1, ...) is drawn at once as the geometric
+  variable G = floor(log(1 - u) / log1p(-p_move(z))), u = uniform53(step m),
+  which has the law of one Bernoulli draw per step; the move happens at step
+  t + G + 1 if that is at most l (t the steps taken so far), else the walk
+  stops;
 * a move proposes neighbour number bounded(step 256 + 1024 t + a, deg z) for
   attempt a = 0..15 and accepts it when its weight ratio x_j / max_row x is
   at least 1 - 2^-20 (weights this close count as equal: unweighted graphs
@@ -83,34 +88,47 @@ def estimate_lazy(lap: Laplacian, ell: int, V, walks_per_row: int, seed: int, co
     r = np.repeat(rows, walks_per_row)
     widx = np.tile(np.arange(walks_per_row), rows.shape[0])
     z = r.copy()
-    for t in range(1, ell + 1):
-        u = rng.uniform53(seed, r, widx, counter, t)
-        movers = np.nonzero(u < p_move[z])[0]
+    steps = np.zeros(r.shape[0], dtype=np.int64)
+    active = deg[z] > 0
+    for m in range(ell):
+        idx = np.nonzero(active)[0]
+        if idx.size == 0:
+            break
+        u = rng.uniform53(seed, r[idx], widx[idx], counter, m)
+        with np.errstate(divide="ignore"):
+            gap = np.floor(np.log(1.0 - u) / np.log1p(-p_move[z[idx]]))
+        go = gap < (ell - steps[idx])
+        active[idx[~go]] = False
+        movers = idx[go]
+        steps[movers] += gap[go].astype(np.int64) + 1
+        t = steps[movers]
         chosen = np.full(movers.shape[0], -1, dtype=np.int64)
         for a in range(_ATTEMPTS):
             todo = np.nonzero(chosen < 0)[0]
             if todo.size == 0:
                 break
-            m = movers[todo]
-            cand = rng.bounded(seed, r[m], widx[m], counter, 256 + 1024 * t + a, deg[z[m]]).astype(np.int64)
-            p = rowptr[z[m]] + cand
-            ratio = x[p] / xmax[z[m]]
+            mv = movers[todo]
+            tt = t[todo]
+            cand = rng.bounded(seed, r[mv], widx[mv], counter, 256 + 1024 * tt + a, deg[z[mv]]).astype(np.int64)
+            p = rowptr[z[mv]] + cand
+            ratio = x[p] / xmax[z[mv]]
             acc = ratio >= _EQUAL
             test = np.nonzero(~acc)[0]
             if test.size:
-                u2 = rng.uniform53(seed, r[m[test]], widx[m[test]], counter, (1 << 20) + 1024 * t + a)
+                u2 = rng.uniform53(seed, r[mv[test]], widx[mv[test]], counter, (1 << 20) + 1024 * tt[test] + a)
                 acc[test] = u2 < ratio[test]
             chosen[todo[acc]] = p[acc]
         left = np.nonzero(chosen < 0)[0]
         for i in left:  # inverse CDF over the row: running sum in row order
-            m = movers[i]
-            zz = z[m]
+            mv = movers[i]
+            zz = z[mv]
             a, b = rowptr[zz], rowptr[zz + 1]
             run = np.cumsum(x[a:b])
-            target = rng.uniform53(seed, r[m], widx[m], counter, (1 << 21) + t) * run[-1]
+            target = rng.uniform53(seed, r[mv], widx[mv], counter, (1 << 21) + t[i]) * run[-1]
             hit = np.nonzero(run > target)[0]
             chosen[i] = a + (hit[0] if hit.size else b - a - 1)
         z[movers] = col[chosen]
+        active[movers] = deg[z[movers]] > 0
     weight = s32[z].astype(np.float64) / np.where(s32[r] > 0, s32[r], 1.0).astype(np.float64)
     weight = np.where(s32[r] > 0, weight, 1.0)
     est = weight[:, None] * V[z]

@@ -280,15 +280,26 @@ __host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 
 // Lemire (2019) bounded draw in [0, s), 1 <= s < 2^32, from the word stream of
 // counter (c0, c1, c2, (step << 8) | j), j = 0, 1, ...
+// The rejection threshold (2^32 - s) mod s is below s, so a low word >= s is
+// always accepted and the (slow) modulo is only needed when the low word falls
+// below s; it is computed in 32 bits as (0 - s) mod s.  Same draws as testing
+// every word against the threshold.
 __host__ __device__ inline uint32_t lemire_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
                                                 uint32_t c2, uint32_t step, uint32_t s) {
-  uint32_t thresh = uint32_t((0x100000000ull - s) % s);
+  uint32_t thresh = 0;
+  bool have_thresh = false;
   for (uint32_t j = 0; j < 256; ++j) {
     Philox4 r = philox4x32_10(c0, c1, c2, (step << 8) | j, k0, k1);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      uint64_t m = uint64_t(r.w[i]) * s;
-      if (uint32_t(m) >= thresh) return uint32_t(m >> 32);
+      const uint64_t m = uint64_t(r.w[i]) * s;
+      const uint32_t lo = uint32_t(m);
+      if (lo >= s) return uint32_t(m >> 32);
+      if (!have_thresh) {
+        thresh = (0u - s) % s;
+        have_thresh = true;
+      }
+      if (lo >= thresh) return uint32_t(m >> 32);
     }
   }
   return 0;  // unreachable in practice: 1024 consecutive rejections

@@ -257,7 +257,8 @@ __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
 // nodes.  Normalised L: I - L/l = D^{1/2} P D^{-1/2}, P = (1 - 1/l) I +
 // (1/l) D^{-1} A, so row r is E[s_Z X_Z] / s_r over the position Z after l
 // lazy steps from r.  Combinatorial L with l >= max d: I - L/l is itself
-// stochastic (move with probability d_z / l), row r is E[X_Z].  A move picks a
+// stochastic (move with probability d_z / l), row r is E[X_Z].  The stays
+// between moves are drawn as geometric gaps (one draw per move).  A move picks a
 // neighbour with probability proportional to w: up to 16 uniform proposals
 // accepted with probability x_j / max x (x = S_ij / s_j or w_ij, float64 from
 // the stored float32 values; ratios within 2^-20 of 1 count as 1), then an
@@ -321,10 +322,17 @@ __global__ __launch_bounds__(kBlock) void walk_lazy_kernel(
       if (live) {
         int64_t z0 = rowptr[z];
         int64_t dz = rowptr[z + 1] - z0;
-        for (int t = 1; t <= ell; ++t) {
-          if (dz == 0) break;  // an isolated node never moves
+        // The stays between moves are geometric: from node z the next move
+        // comes after G = floor(log(1 - u) / log1p(-p_move(z))) more stays
+        // (u the m-th gap draw), the same law as one Bernoulli draw per step,
+        // at one draw per move.
+        int t = 0;
+        for (int m = 0; dz > 0; ++m) {  // an isolated node never moves
           const double pm = norm ? inv_ell : double(diag[z]) * inv_ell;
-          if (!(uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(t)) < pm)) continue;
+          const double u = uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, uint32_t(m));
+          const double gap = floor(log(1.0 - u) / log1p(-pm));
+          if (!(gap < double(ell - t))) break;  // no move within the remaining steps
+          t += int(gap) + 1;                     // the move happens at step t
           int64_t chosen = -1;
           for (int a = 0; a < kLazyAttempts && chosen < 0; ++a) {
             const uint32_t j = lemire_draw(k0, k1, uint32_t(r), uint32_t(w), ctr, 256u + 1024u * uint32_t(t) + a,
