@@ -126,6 +126,44 @@ def write_traffic(fetch_db, write_db):
     print(json.dumps(out))
 
 
+def mfma_summary(db):
+    """Per-kernel MFMA use from a rocprofv3 --pmc database holding
+    SQ_VALU_MFMA_BUSY_CYCLES, SQ_INSTS_VALU_MFMA_MOPS_F64/_F32 and
+    GRBM_GUI_ACTIVE: the SQ counters arrive once per shader engine and are
+    summed per dispatch; busy % = busy cycles / (GUI-active cycles x 1024
+    SIMDs); flops = MOPS x 512."""
+    import collections
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    meta = {}
+    for did, name, cn, v, d in con.execute(
+            "select dispatch_id, name, counter_name, counter_value, duration from pmc_events"):
+        per[did][cn].append(v)
+        meta[did] = (name, d)
+    agg = collections.defaultdict(list)
+    for did, cs in per.items():
+        name, d = meta[did]
+        nm = name.replace("sped::(anonymous namespace)::", "").replace("void ", "")
+        nm = nm[:nm.index("(")] if "(" in nm else nm
+        agg[nm].append((sum(cs.get("SQ_VALU_MFMA_BUSY_CYCLES", [0])), max(cs.get("GRBM_GUI_ACTIVE", [1])),
+                        512 * sum(cs.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [0])),
+                        512 * sum(cs.get("SQ_INSTS_VALU_MFMA_MOPS_F32", [0])), d))
+    print("| kernel | dispatches | MFMA busy (% of SIMD-cycles) | FP64 MFMA flop / dispatch | "
+          "FP32 MFMA flop / dispatch | avg duration us | achieved MFMA TFLOP/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for nm, recs in sorted(agg.items(), key=lambda kv: -sum(r[2] + r[3] for r in kv[1])):
+        m = len(recs)
+        flops = sum(r[2] + r[3] for r in recs) / m
+        if flops == 0:
+            continue
+        util = 100.0 * sum(r[0] for r in recs) / sum(r[1] * 1024 for r in recs)
+        dur = sum(r[4] for r in recs) / m
+        print(f"| `{nm}` | {m} | {util:.2f} | {sum(r[2] for r in recs) / m:.3e} | "
+              f"{sum(r[3] for r in recs) / m:.3e} | {dur / 1e3:.1f} | {flops / dur / 1e3:.2f} |")
+
+
 def locality_sweep():
     """Per-launch time of the fused step on SBMs of 1e6 nodes and mean degree
     20 whose block size sets how local each row's neighbourhood is, plus a
@@ -439,6 +477,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--mfma-summary", metavar="PMC_DB",
+                    help="print per-kernel MFMA use from a rocprofv3 --pmc database")
     ap.add_argument("--tolerance-only", action="store_true",
                     help="run only the time-to-tolerance comparisons (profiling the solver)")
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
@@ -454,6 +494,9 @@ def main():
         return
     if args.write_traffic:
         write_traffic(*args.write_traffic)
+        return
+    if args.mfma_summary:
+        mfma_summary(args.mfma_summary)
         return
     if args.traffic_probe:
         traffic_probe(args)
