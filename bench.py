@@ -470,6 +470,48 @@ def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
     return out
 
 
+def power_law_bf16(sped, synth, torch, np):
+    """The power-law workload at its full shape: a 4e6-node Chung-Lu graph
+    (exponent 2.1, mean degree 16, 256 planted communities, 95% of draws
+    inside the community), drawn on the device, largest component only, the
+    symmetric normalised L; a 64-column bf16 block.  Times the degree-16
+    limit application (bf16 in and out, float32 intermediates, as the
+    solver's bf16 phase uses it) and one all-bf16 fused step, with the
+    algorithmic bytes of each."""
+    n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    torch.cuda.empty_cache()
+    k, ell = 64, 16
+    X = synth.gaussian_block_device(L.n, k, seed=2, dtype=torch.bfloat16)
+    Y = torch.empty_like(X)
+    p = sped.transform("limit", ell)
+    one = sped.monomial([0.0, 1.0])
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    chain_ms = timed(lambda: sped.apply_poly(L, p, X, out=Y), 5)
+    step_ms = timed(lambda: sped.apply_poly(L, one, X, out=Y), 20)
+    idx = 8 * (L.n + 1) + L.nnz * 8 + 4 * L.n
+    step_bytes = idx + L.n * k * (2 + 2)                      # bf16 U in, bf16 O out
+    chain_bytes = ell * idx + L.n * k * (2 + 4 + (ell - 2) * 8 + 4 + 2)  # bf16 X, f32 between, bf16 Y
+    return {"workload": "Chung-Lu n=4e6 (device draw), exponent 2.1, mean degree 16, 256 communities; "
+                        "largest component; sym-normalised L; k=64 bf16",
+            "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree, "medium_rows": L.n_medium,
+            "heavy_rows": L.n_heavy, "xcd_rows": L.xcd_rows,
+            "chain_ms": round(chain_ms, 4), "chain_GBps": round(chain_bytes / (chain_ms * 1e-3) / 1e9, 1),
+            "bf16_step_us": round(step_ms * 1e3, 2), "bf16_step_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -482,6 +524,8 @@ def main():
     ap.add_argument("--tolerance-only", action="store_true",
                     help="run only the time-to-tolerance comparisons (profiling the solver)")
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
+    ap.add_argument("--power-law-only", action="store_true",
+                    help="run only the power-law bf16 workload (profiling the SpMM bins)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -521,6 +565,9 @@ def main():
                "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np),
                "paper_experiments": paper_experiments(sped, synth, torch, np)}
         print(json.dumps(out), flush=True)
+        return
+    if args.power_law_only:
+        print(json.dumps({"power_law_bf16_k64": power_law_bf16(sped, synth, torch, np)}), flush=True)
         return
     k, ell, walks = 32, 16, 8
     t0 = time.perf_counter()
@@ -598,6 +645,10 @@ def main():
     }
     if not args.chain_only:
         line["estimators"] = estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream)
+    if not args.chain_only and not args.no_solve:
+        del L, Q, W, S
+        torch.cuda.empty_cache()
+        line["power_law_bf16_k64"] = power_law_bf16(sped, synth, torch, np)
     if not args.no_solve and not args.chain_only:
         line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
         line["time_to_tolerance_sbm500k"] = time_to_tolerance_sbm500k(sped, synth, torch, np)

@@ -107,6 +107,14 @@ typedef struct {
   int32_t max_degree;   /* largest number of neighbours of any node (deg* of Sec. 4.3) */
   int32_t kind;         /* sped_lap_kind */
   double lambda_bound;  /* 2 (normalised) or 2 max_i d_i (combinatorial): >= lambda_max */
+  /* Row split of the light-row SpMM over the 8 XCDs (accelerator complex
+   * dies, each with its own L2): XCD x handles rows [xcd_rows[x],
+   * xcd_rows[x+1]), ranges of equal light-row work (entries plus a per-row
+   * cost), so a degree-sorted graph does not load one die with most of the
+   * entries.  Filled by sped_laplacian_csr; a caller-built struct sets all nine
+   * to zero (any array that is not 0 = x_0 <= ... <= x_8 = n is ignored and
+   * the rows are split evenly). */
+  int64_t xcd_rows[9];
 } sped_csr;
 
 /*
@@ -123,7 +131,7 @@ typedef struct {
  *  out         HOST struct; on entry its array pointers must point to DEVICE
  *              buffers of at least rowptr n+1, col/val/rev/wentry 2m,
  *              diag/scale/bins/wnode n elements (wentry, wnode may be NULL).  On return n, nnz, n_medium, n_heavy, max_degree,
- *              kind and lambda_bound are filled in.
+ *              kind, lambda_bound and xcd_rows are filled in.
  *  old_of_new  DEVICE int32 [n] or NULL: original id of each kept node
  * Synchronises `stream` before returning (sizes are read back).  Invalid
  * endpoints or weights found on the device return SPED_E_INVALID.

@@ -109,8 +109,20 @@ __global__ void compress_labels(int64_t n, int32_t *label) {
   GRID_STRIDE(i, n) label[i] = find_root(label, int32_t(i));
 }
 
+// Component sizes.  Most nodes of a real graph share one label (the giant
+// component), so one counter would take an atomic per node; lanes of a
+// wavefront whose label equals the first active lane's add once, as a group.
 __global__ void count_components(int64_t n, const int32_t *__restrict__ label, int32_t *__restrict__ size) {
-  GRID_STRIDE(i, n) atomicAdd(&size[label[i]], 1);
+  GRID_STRIDE(i, n) {
+    const int32_t l = label[i];
+    const int32_t lead = __builtin_amdgcn_readfirstlane(l);
+    const unsigned long long same = __ballot(l == lead);
+    if (l != lead) {
+      atomicAdd(&size[l], 1);
+    } else if (int(threadIdx.x & 63) == __ffsll(static_cast<long long>(same)) - 1) {
+      atomicAdd(&size[lead], __popcll(same));
+    }
+  }
 }
 
 // pick (largest size, then smallest root): max of size << 32 | ~root
@@ -256,6 +268,40 @@ __global__ void bin_flags(int64_t n, const int64_t *__restrict__ rowptr, char *_
   }
 }
 
+// Cost of a row for the light-row SpMM, in entry units: a light row pays its
+// entries (one neighbour-row gather each) plus the row pointers and its own
+// row's read and write; a medium or heavy row only the light kernel's early
+// exit.  Prefix sums of this give the XCD row split (sped_csr.xcd_rows).
+constexpr int64_t kLightRowCost = 2;
+
+__global__ void light_work(int64_t n, const int64_t *__restrict__ rowptr, int64_t *__restrict__ work) {
+  GRID_STRIDE(r, n + 1) {
+    int64_t w = 0;
+    if (r < n) {
+      const int64_t d = rowptr[r + 1] - rowptr[r];
+      w = d <= SPED_LIGHT_MAX ? d + kLightRowCost : 1;
+    }
+    work[r] = w;
+  }
+}
+
+// splits[x] = smallest r with prefix[r] >= x total / 8, prefix exclusive over
+// n + 1 entries (prefix[n] = total).  Work is >= 1 per row, so prefix is
+// strictly increasing, splits[0] = 0 and splits[8] = n.
+__global__ void xcd_splits(int64_t n, const int64_t *__restrict__ prefix, int64_t *__restrict__ splits) {
+  const int x = threadIdx.x;
+  if (x > kXcds) return;
+  const int64_t total = prefix[n];
+  const int64_t target = total / kXcds * x + total % kXcds * x / kXcds;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (prefix[mid] >= target) hi = mid;
+    else lo = mid + 1;
+  }
+  splits[x] = lo;
+}
+
 struct BuildWs {
   uint64_t *kA, *kB;
   float *vA, *vB;
@@ -266,7 +312,7 @@ struct BuildWs {
   double *deg, *sd, *dmax;
   char *fmed, *fheavy;
   int32_t *counting;
-  int64_t *nsel;
+  int64_t *nsel, *splits;
   unsigned long long *best;
   int *err, *changed, *maxcount;
   void *temp;
@@ -324,6 +370,7 @@ extern "C" sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *s
   b.fheavy = c.take<char>(n + 1);
   b.counting = c.take<int32_t>(n + 1);
   b.nsel = c.take<int64_t>(2);
+  b.splits = c.take<int64_t>(kXcds + 1);
   b.best = c.take<unsigned long long>(1);
   b.err = c.take<int>(4);
   b.changed = b.err + 1;
@@ -472,6 +519,15 @@ extern "C" sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *s
     SPED_CHECK_HIP(hipMemcpyAsync(&hmax, b.maxcount, sizeof(int), hipMemcpyDeviceToHost, s));
     SPED_CHECK_HIP(hipStreamSynchronize(s));
     lam = kind == SPED_LAP_SYM_NORMALIZED ? 2.0 : 2.0 * dmax;
+    hipLaunchKernelGGL(light_work, dim3(grid_for(n_out + 1)), dim3(kBlock), 0, s, n_out, out->rowptr, b.flags);
+    SPED_CHECK_HIP(hipGetLastError());
+    tb = b.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.flags, b.pos, n_out + 1, s));
+    hipLaunchKernelGGL(xcd_splits, dim3(1), dim3(64), 0, s, n_out, b.pos, b.splits);
+    SPED_CHECK_HIP(hipGetLastError());
+    SPED_CHECK_HIP(hipMemcpyAsync(out->xcd_rows, b.splits, (kXcds + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  } else {
+    for (int x = 0; x <= kXcds; ++x) out->xcd_rows[x] = 0;
   }
   SPED_CHECK_HIP(hipStreamSynchronize(s));
   out->n = n_out;

@@ -16,6 +16,7 @@
 // access (the next chunk's pairs are fetched while the current chunk's rows are
 // in flight), broadcast them by shuffle, and issue 8 neighbour-row gathers
 // before consuming any, so each lane keeps 8 row gathers in flight.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -126,22 +127,33 @@ __device__ inline double block_sum_double(double v, double *lds) {
   return t;
 }
 
+// Row ranges of the 8 XCDs: XCD x owns rows [r[x], r[x+1]).
+struct XcdRows {
+  int64_t r[kXcds + 1];
+};
+
+// Blocks are dealt to the XCDs round-robin (block b runs on XCD b % 8), so
+// block b takes the (b / 8)-th run of 256/G rows inside XCD (b % 8)'s range:
+// each die walks a contiguous stretch of rows (neighbour rows of nearby nodes
+// share its L2) and the ranges carry equal work.
 template <typename TU, typename TV, typename TO, int VEC, bool DOT>
 __global__ __launch_bounds__(kBlock) void spmm_light(
-    int64_t n, int64_t nb, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    XcdRows xr, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
     const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
     int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
   using S = Step<TU, TV, TO, VEC, DOT>;
-  const int64_t lb = xcd_logical_block(nb);
-  if (lb >= nb) return;  // padding block (uniform over the block)
+  const int x = blockIdx.x % kXcds;
+  const int64_t row0 = xr.r[x] + int64_t(blockIdx.x / kXcds) * (kBlock >> lgG);
+  const int64_t rend = xr.r[x + 1];
+  if (!DOT && row0 >= rend) return;  // past this XCD's range (uniform over the block)
   const int lig = threadIdx.x & (G - 1);
   const int grp = threadIdx.x >> lgG;
-  const int64_t row = lb * (kBlock >> lgG) + grp;
+  const int64_t row = row0 + grp;
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   const bool col_ok = c0 < k;
   double dsum = 0.0;
-  if (row < n) {
+  if (row < rend) {
     const int64_t beg = rowptr[row], end = rowptr[row + 1];
     if (end - beg <= SPED_LIGHT_MAX) {
       float acc[VEC];
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
   if (DOT) {
     __shared__ double red[kBlock / 64];
     double t = block_sum_double(dsum, red);
-    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * nb + lb] = t;
+    if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -246,8 +258,16 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double *_
 
 struct Geometry {
   int vec, G, lgG, ytiles;
+  XcdRows xr;
   int64_t light_blocks, medium_blocks, heavy_blocks;
 };
+
+bool valid_xcd_rows(const sped_csr *L) {
+  if (L->xcd_rows[0] != 0 || L->xcd_rows[kXcds] != L->n) return false;
+  for (int x = 0; x < kXcds; ++x)
+    if (L->xcd_rows[x + 1] < L->xcd_rows[x]) return false;
+  return true;
+}
 
 Geometry geometry(const sped_csr *L, int64_t k, int vec) {
   Geometry g;
@@ -256,7 +276,16 @@ Geometry geometry(const sped_csr *L, int64_t k, int vec) {
   g.ytiles = (lanes + 63) / 64;
   g.G = lanes >= 64 ? 64 : next_pow2(lanes);
   g.lgG = ilog2(g.G);
-  g.light_blocks = (L->n + (kBlock >> g.lgG) - 1) / (kBlock >> g.lgG);
+  const int64_t rpb = kBlock >> g.lgG;
+  if (L->n > 0 && valid_xcd_rows(L)) {
+    for (int x = 0; x <= kXcds; ++x) g.xr.r[x] = L->xcd_rows[x];
+  } else {  // even split in whole blocks
+    const int64_t per = ((L->n + rpb - 1) / rpb + kXcds - 1) / kXcds * rpb;
+    for (int x = 0; x <= kXcds; ++x) g.xr.r[x] = std::min<int64_t>(L->n, per * x);
+  }
+  int64_t most = 0;
+  for (int x = 0; x < kXcds; ++x) most = std::max(most, (g.xr.r[x + 1] - g.xr.r[x] + rpb - 1) / rpb);
+  g.light_blocks = most * kXcds;
   g.medium_blocks = (L->n_medium + 3) / 4;
   g.heavy_blocks = L->n_heavy;
   return g;
@@ -275,8 +304,8 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
   TO *O = static_cast<TO *>(a.O);
   double *part = a.dot_partials;
   if (g.light_blocks > 0) {
-    const dim3 grid = dim3(unsigned(xcd_padded_grid(g.light_blocks)), unsigned(g.ytiles));
-    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n, g.light_blocks, int(k),
+    const dim3 grid = dim3(unsigned(g.light_blocks), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, g.xr, int(k),
                        g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
                        cf, a.dotw, a.lddw, part);
     SPED_CHECK_HIP(hipGetLastError());

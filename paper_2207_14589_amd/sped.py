@@ -31,7 +31,7 @@ class CSR(ctypes.Structure):
     _fields_ = [("n", _c_i64), ("nnz", _c_i64), ("rowptr", _c_vp), ("col", _c_vp), ("val", _c_vp),
                 ("rev", _c_vp), ("diag", _c_vp), ("scale", _c_vp), ("bins", _c_vp),
                 ("wentry", _c_vp), ("wnode", _c_vp), ("n_medium", _c_i64), ("n_heavy", _c_i64), ("max_degree", _c_i32), ("kind", _c_i32),
-                ("lambda_bound", _c_f64)]
+                ("lambda_bound", _c_f64), ("xcd_rows", _c_i64 * 9)]
 
 
 class Poly(ctypes.Structure):
@@ -197,6 +197,7 @@ class Laplacian:
         self.n, self.nnz = c.n, c.nnz
         self.max_degree, self.lambda_bound = c.max_degree, c.lambda_bound
         self.n_medium, self.n_heavy = c.n_medium, c.n_heavy
+        self.xcd_rows = list(c.xcd_rows)
         self.old_of_new = self.old_of_new[: self.n]
 
     @property

@@ -200,6 +200,59 @@ def test_apply_poly_isolated_nodes(sped):
     np.testing.assert_allclose(Y[[4, 7, 8]], X[[4, 7, 8]], rtol=1e-6)   # zero rows: M = I there
 
 
+def test_xcd_row_split_power_law(sped):
+    """Degree-sorted power-law graph: the builder's 8 XCD row ranges carry
+    equal light-row work (recomputed here from the row pointers, exactly), and
+    the light SpMM gives the same rows bit for bit under that split, the even
+    split and a caller-built (zeroed or invalid) split; all match the oracle."""
+    n, src, dst, _ = synth.chung_lu(30000, 2.1, 12.0, 8, 0.7, seed=4)
+    _say(f"xcd split power-law n={n} m={src.shape[0]}")
+    L = sped.Laplacian(n, src, dst, kind="sym")
+    ref = olap.laplacian(n, src, dst, None, kind=olap.SYM_NORMALIZED)
+    d = np.diff(L.host_csr()[0])
+    work = np.where(d <= sped.LIGHT_MAX, d + 2, 1)
+    pre = np.concatenate([[0], np.cumsum(work)])
+    tot = int(pre[-1])
+    x = np.arange(9)
+    expect = np.searchsorted(pre, tot // 8 * x + tot % 8 * x // 8, side="left")
+    assert L.xcd_rows == expect.tolist()
+    assert L.xcd_rows[0] == 0 and L.xcd_rows[8] == n
+    per = np.diff(pre[expect])
+    assert per.max() - per.min() <= 2 * (sped.LIGHT_MAX + 2)
+    assert pre[n // 8] > 2 * tot / 8  # the even split would load the first die with > 2x
+    poly = sped.transform("limit", 16, L.lambda_bound)
+    for k in (32, 7):
+        X = synth.gaussian_block(n, k, 8).astype(np.float32)
+        Xd = torch.from_numpy(X).cuda()
+        Y = sped.apply_poly(L, poly, Xd).cpu().numpy()
+        Yr = opoly.apply_terms(ref.L, opoly.limit_exp(16), X.astype(np.float64))
+        assert _rel(Y.astype(np.float64), Yr) < 3e-5
+        saved = list(L.c.xcd_rows)
+        try:
+            for other in ([0] * 9, [0, 5, 4, 9, 9, 9, 9, 9, n], [0, n, n, n, n, n, n, n, n]):
+                L.c.xcd_rows[:] = other
+                Y2 = sped.apply_poly(L, poly, Xd).cpu().numpy()
+                np.testing.assert_array_equal(Y2, Y)
+        finally:
+            L.c.xcd_rows[:] = saved
+    # the inner-product path (partials per block) under both splits
+    g = np.random.default_rng(9)
+    X = g.standard_normal((n, 10)).astype(np.float32)
+    G = g.standard_normal((n, 10)).astype(np.float32)
+    Xd, Gd = torch.from_numpy(X).cuda(), torch.from_numpy(G).cuda()
+    dth = sped.poly_backward(L, 12, Xd, Gd).cpu().numpy()
+    saved = list(L.c.xcd_rows)
+    try:
+        L.c.xcd_rows[:] = [0] * 9
+        dth_even = sped.poly_backward(L, 12, Xd, Gd).cpu().numpy()
+    finally:
+        L.c.xcd_rows[:] = saved
+    theta = np.zeros(13)
+    dth_r, _ = ograd.backward(ref.L, theta, X.astype(np.float64), G.astype(np.float64))
+    np.testing.assert_allclose(dth, dth_r, rtol=5e-5, atol=5e-5 * np.abs(dth_r).max())
+    np.testing.assert_allclose(dth, dth_even, rtol=1e-6, atol=1e-6 * np.abs(dth_r).max())
+
+
 @pytest.fixture(scope="module")
 def c2_case(sped):
     """SBM, 10^6 nodes, 100 blocks, mean degree 20, 5% cross edges (k=32, l=16)."""
