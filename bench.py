@@ -444,11 +444,13 @@ def paper_experiments(sped, synth, torch, np):
 
 
 def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
-    """The two unbiased estimates of (I - L/l)^l V at the same walks per row:
-    the importance edge-chain walk (Sec. 4.3) and the lazy node walk (bounded
-    weights, one row gather per walk), as relative Frobenius error against
-    the exact product, on the solver's current iterate Q (near the bottom
-    eigenvectors) and on the Gaussian block X; and the lazy walk's time."""
+    """The unbiased estimates of (I - L/l)^l V at the same walks per row: the
+    importance edge-chain walk (Sec. 4.3), the lazy node walk (bounded
+    weights, one row gather per walk) and the edge walk with its first m
+    terms exact (m sparse steps, walks of length l - m), as relative
+    Frobenius error against the exact product, on the solver's current
+    iterate Q (near the bottom eigenvectors) and on the Gaussian block X; and
+    their times."""
     out = {"walks_per_row": walks}
     for name, V in (("on_iterate", Q), ("on_gaussian", torch.from_numpy(X).cuda())):
         exact = sped.apply_poly(L, p, V)
@@ -467,6 +469,23 @@ def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
     ms = sorted(a.elapsed_time(b) for a, b in evs)[len(evs) // 2]
     out["lazy_walk_ms"] = round(ms, 4)
     out["lazy_walks_per_s"] = round(L.n * walks / (ms * 1e-3), 1)
+    # exact low-order terms, sampled tail: error and time against the number of exact terms
+    hyb = {}
+    G = torch.from_numpy(X).cuda()
+    for m in (0, 1, 2, 3, 4):
+        row = {}
+        for name, V in (("on_iterate", Q), ("on_gaussian", G)):
+            exact = sped.apply_poly(L, p, V)
+            est = sped.apply_poly_hybrid(L, coeffs, V, m, walks=walks, seed=7)
+            row["rel_err_" + name] = float((est - exact).norm()) / float(exact.norm())
+        for i, (a, b) in enumerate(evs):
+            a.record(stream)
+            sped.apply_poly_hybrid(L, coeffs, Q, m, walks=walks, seed=11, counter=i, out=Y)
+            b.record(stream)
+        torch.cuda.synchronize()
+        row["ms"] = round(sorted(a.elapsed_time(b) for a, b in evs)[len(evs) // 2], 4)
+        hyb[f"exact_terms_{m}"] = row
+    out["exact_low_sampled_tail"] = hyb
     return out
 
 

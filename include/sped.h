@@ -227,6 +227,35 @@ sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, 
                                        sped_stream_t stream);
 
 /*
+ * sped_apply_poly_hybrid -- unbiased estimate of Y = sum_{i=0..degree} c_i L^i X
+ * with the low-order terms exact and only the tail sampled (a variance
+ * reduction of the Sec. 4.3 estimator; Sec. 6 leaves variance open):
+ *   Y = sum_{i<m} c_i L^i X + L^m T,  T = walk estimate of sum_{j>=0} c_{m+j} L^j X
+ * with m = exact_terms.  Since L^m commutes with the tail polynomial,
+ * E[L^m T] is the tail sum_{i>=m} c_i L^i X.  T is one
+ * sped_apply_poly_stochastic call with the shifted coefficients (c_m, ...,
+ * c_degree) and the same sampler, walks, seed and counter, so its walks are
+ * those of that call; then m fused sparse steps U <- L U + c_i X
+ * (i = m-1 .. 0, float32 intermediates) give Y.  m = 0 is the plain
+ * estimate; m = degree uses no walks (exact Horner evaluation, X scaled by
+ * c_degree in the first step).  Cost: m sparse steps plus walks of length
+ * degree - m.
+ *  coeffs     HOST [degree+1] monomial coefficients in L; degree 1..255
+ *  exact_terms 0..degree
+ *  X, Y       DEVICE n x k (ldx, ldy), F32 or BF16 each; must not overlap
+ *  sampler    0 importance, 1 rejection (with m = 0 the rejection sampler
+ *             needs a float32 Y; with m >= 1 its tail goes to float32 scratch)
+ *  ws         DEVICE scratch: n k floats for m = 1, 2 n k for m >= 2; or the
+ *             size query
+ * Asynchronous on `stream`.  Errors as sped_apply_poly_stochastic.
+ */
+sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *coeffs, int32_t degree,
+                                   int32_t exact_terms, int64_t k, const void *X, int64_t ldx,
+                                   int32_t xdt, void *Y, int64_t ldy, int32_t ydt, int32_t sampler,
+                                   int64_t walks, uint64_t seed, uint64_t counter, void *ws,
+                                   size_t *ws_bytes, sped_stream_t stream);
+
+/*
  * sped_apply_limit_lazy -- unbiased random estimate of Y = (I - L/ell)^ell X,
  * the limit approximation of Table 2 (the default dilation), by lazy random
  * walks on the nodes: a lower-variance estimator than the edge chains of
@@ -348,6 +377,8 @@ typedef struct {
   double coarse_tol;       /* BF16 phase stops at this bound (<= 0: 1e-2) */
   int32_t stochastic_sampler; /* 0 = importance edge walks (Sec. 4.3), 1 = lazy node walks
                                  (sped_apply_limit_lazy; needs the limit polynomial, solver 0 or 2) */
+  int32_t stochastic_exact_terms; /* sampler 0: the first m terms of the polynomial exact, the
+                                     tail sampled (sped_apply_poly_hybrid); 0..degree */
 } sped_solve_opts;
 
 typedef struct {

@@ -185,6 +185,31 @@ def estimate_reject(lap: Laplacian, coeffs, V, n_trials: int, seed: int,
     return Y, counts
 
 
+def estimate_hybrid(lap: Laplacian, coeffs, V, exact_terms: int, walks_per_row: int, seed: int,
+                    counter: int = 0, sampler: str = "importance", n_trials: int = 0):
+    """Exact low-order terms plus a sampled tail (the variance-reduction
+    direction Sec. 6 leaves open): with m = exact_terms,
+        Y = sum_{i<m} c_i L^i V + L^m T,   T = walk estimate of sum_j c_{m+j} L^j V,
+    unbiased because L^m commutes with the tail polynomial.  T uses the
+    shifted coefficients (c_m, ..., c_l) and the given sampler and seed; the
+    exact part is Horner's rule U <- L U + c_i V for i = m-1 .. 0 from U = T.
+    m = 0 is the plain estimate, m = l the exact polynomial (T = c_l V).
+    The rejection sampler takes n_trials trials.  Returns float64 (n, k)."""
+    c = np.asarray(coeffs, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    m = int(exact_terms)
+    if not 0 <= m <= c.shape[0] - 1:
+        raise ValueError("exact_terms outside [0, degree]")
+    tail = c[m:]
+    if sampler == "importance":
+        U = estimate_importance(lap, tail, V, walks_per_row, seed, counter)
+    else:
+        U, _ = estimate_reject(lap, tail, V, n_trials, seed, counter)
+    for i in range(m - 1, -1, -1):
+        U = lap.L @ U + c[i] * V
+    return U
+
+
 def edge_pair_product(lap: Laplacian, e, f):
     """x~_e^T x~_f for merged edges e, f (indices into lap.eu/ev), computed from
     the two incidence rows; the reference point for Table 1."""

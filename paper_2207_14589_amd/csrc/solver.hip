@@ -231,6 +231,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
   if (o->stochastic_sampler != 0 && o->stochastic_sampler != 1) return fail(SPED_E_INVALID, "stochastic_sampler");
   const bool lazy = o->stochastic_iters > 0 && o->stochastic_sampler == 1;
+  if (o->stochastic_exact_terms < 0 || (lazy && o->stochastic_exact_terms != 0))
+    return fail(SPED_E_INVALID, "stochastic_exact_terms (edge walks only, >= 0)");
   if (o->stochastic_iters > 0 && !lazy && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
     return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and the walk records");
   if (lazy) {
@@ -258,6 +260,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->stochastic_iters > 0 && !lazy) {
     walk_c = monomial_in_L(M);
     if (M.degree > 255) return fail(SPED_E_UNSUPPORTED, "stochastic iterations need degree <= 255");
+    if (o->stochastic_exact_terms > M.degree) return fail(SPED_E_INVALID, "stochastic_exact_terms > degree");
   }
 
   const bool two_phase = vdt == SPED_BF16;
@@ -322,8 +325,9 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
         SPED_TRY(lazy_estimate_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
                                     lz_max, lz_sum, s));
       } else if (t <= o->stochastic_iters) {
-        SPED_TRY(walk_estimate_impl(L, walk_c.data(), M.degree, kb, Q, kb, dt, W, kb, dt, 0, o->walks_per_row,
-                                    o->seed, uint64_t(t), nullptr, s));
+        SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb,
+                                      dt, 0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, s,
+                                      &stats.spmm_count));
       } else {
         SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, s, &stats.spmm_count));
       }

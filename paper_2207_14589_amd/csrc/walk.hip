@@ -588,14 +588,14 @@ sped_status launch_lazy(const sped_csr *L, int64_t k, const void *X, int64_t ldx
 
 using namespace sped;
 
-extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, int32_t degree,
-                                                  int64_t k, const void *X, int64_t ldx, int32_t xdt, void *Y,
-                                                  int64_t ldy, int32_t ydt, int32_t sampler, int64_t walks,
-                                                  uint64_t seed, uint64_t counter, int64_t *accept_counts,
-                                                  void *ws, size_t *ws_bytes, sped_stream_t stream) {
-  clear_error();
-  SPED_TRY(validate_csr(L));
-  if (degree < 1 || degree > kMaxDeg) return fail(SPED_E_INVALID, "degree outside [1, 255]");
+namespace sped {
+namespace {
+
+// Argument checks shared by the walk estimators (degree checked by the caller);
+// `walking` false checks only what an exact evaluation needs.
+sped_status validate_walk_args(const sped_csr *L, const double *coeffs, int degree, int64_t k, const void *X,
+                               int64_t ldx, int xdt, const void *Y, int64_t ldy, int ydt, int sampler,
+                               int64_t walks, uint64_t counter, bool walking = true) {
   if (!coeffs) return fail(SPED_E_INVALID, "coeffs NULL");
   for (int i = 0; i <= degree; ++i)
     if (!std::isfinite(coeffs[i])) return fail(SPED_E_INVALID, "coefficient not finite");
@@ -604,20 +604,121 @@ extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const doubl
   if ((xdt != SPED_F32 && xdt != SPED_BF16) || (ydt != SPED_F32 && ydt != SPED_BF16))
     return fail(SPED_E_UNSUPPORTED, "dtype");
   if (L->n > 0 && (!X || !Y)) return fail(SPED_E_INVALID, "X or Y NULL");
+  if (!walking) return SPED_OK;
   if (L->nnz > 0 && (!L->wentry || !L->wnode)) return fail(SPED_E_INVALID, "csr walk records NULL");
   if (sampler != 0 && sampler != 1) return fail(SPED_E_INVALID, "sampler must be 0 or 1");
   if (walks < 1) return fail(SPED_E_INVALID, "walks < 1");
   if (counter >= (uint64_t(1) << 32)) return fail(SPED_E_INVALID, "counter >= 2^32");
   if (sampler == 0 && walks >= (int64_t(1) << 32)) return fail(SPED_E_INVALID, "walks per row >= 2^32");
-  if (sampler == 1) {
-    if (ydt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "rejection sampler needs a float32 Y");
-    if (L->nnz >= (int64_t(1) << 32)) return fail(SPED_E_UNSUPPORTED, "rejection sampler needs nnz < 2^32");
-  }
+  if (sampler == 1 && L->nnz >= (int64_t(1) << 32))
+    return fail(SPED_E_UNSUPPORTED, "rejection sampler needs nnz < 2^32");
+  return SPED_OK;
+}
+
+}  // namespace
+}  // namespace sped
+
+extern "C" sped_status sped_apply_poly_stochastic(const sped_csr *L, const double *coeffs, int32_t degree,
+                                                  int64_t k, const void *X, int64_t ldx, int32_t xdt, void *Y,
+                                                  int64_t ldy, int32_t ydt, int32_t sampler, int64_t walks,
+                                                  uint64_t seed, uint64_t counter, int64_t *accept_counts,
+                                                  void *ws, size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (degree < 1 || degree > kMaxDeg) return fail(SPED_E_INVALID, "degree outside [1, 255]");
+  SPED_TRY(validate_walk_args(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, counter));
+  if (sampler == 1 && ydt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "rejection sampler needs a float32 Y");
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, 0, &query));
   if (query || L->n == 0) return SPED_OK;
   return walk_estimate_impl(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
                             accept_counts, as_stream(stream));
+}
+
+namespace sped {
+
+sped_status hybrid_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int m, int64_t k,
+                                 const void *X, int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler,
+                                 int64_t walks, uint64_t seed, uint64_t counter, float *T0, float *T1,
+                                 hipStream_t s, int64_t *spmm_count) {
+  if (L->n == 0) return SPED_OK;
+  if (m == 0)
+    return walk_estimate_impl(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
+                              nullptr, s);
+  float *T[2] = {T0, T1};
+  const bool sampled = m < degree;
+  // U starts as the sampled tail T (or, with no tail, as X scaled by c_degree in the first step)
+  const void *U = X;
+  int64_t ldu = ldx;
+  int tu = xdt;
+  float first_a = float(coeffs[degree]);
+  if (sampled) {
+    SPED_TRY(walk_estimate_impl(L, coeffs + m, degree - m, k, X, ldx, xdt, T[0], k, SPED_F32, sampler, walks, seed,
+                                counter, nullptr, s));
+    U = T[0];
+    ldu = k;
+    tu = SPED_F32;
+    first_a = 1.f;
+  }
+  int next = sampled ? 1 : 0;
+  for (int i = m - 1; i >= 0; --i) {
+    StepArgs a{};
+    a.U = U; a.ldu = ldu; a.tu = tu;
+    a.V = X; a.ldv = ldx; a.tv = xdt;
+    if (i == 0) {
+      a.O = Y; a.ldo = ldy; a.to = ydt;
+    } else {
+      a.O = T[next]; a.ldo = k; a.to = SPED_F32;
+    }
+    a.a = i == m - 1 ? first_a : 1.f;
+    a.b = 0.f;
+    a.g = float(coeffs[i]);
+    SPED_TRY(launch_spmm_step(L, k, a, s));
+    if (spmm_count) ++*spmm_count;
+    U = a.O;
+    ldu = a.ldo;
+    tu = a.to;
+    next ^= 1;
+  }
+  return SPED_OK;
+}
+
+}  // namespace sped
+
+// Exact low-order terms, sampled tail:
+//   Y = sum_{i<m} c_i L^i X + L^m T,   T = walk estimate of sum_{j>=0} c_{m+j} L^j X,
+// evaluated as m Horner steps U <- L U + c_i X (i = m-1 .. 0) starting from T.
+extern "C" sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *coeffs, int32_t degree,
+                                              int32_t exact_terms, int64_t k, const void *X, int64_t ldx,
+                                              int32_t xdt, void *Y, int64_t ldy, int32_t ydt, int32_t sampler,
+                                              int64_t walks, uint64_t seed, uint64_t counter, void *ws,
+                                              size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  if (degree < 1 || degree > kMaxDeg) return fail(SPED_E_INVALID, "degree outside [1, 255]");
+  if (exact_terms < 0 || exact_terms > degree) return fail(SPED_E_INVALID, "exact_terms outside [0, degree]");
+  const int m = exact_terms;
+  const bool sampled = m < degree;
+  if (sampled) {
+    SPED_TRY(validate_walk_args(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, counter));
+    if (sampler == 1 && m == 0 && ydt != SPED_F32)
+      return fail(SPED_E_UNSUPPORTED, "rejection sampler needs a float32 Y");
+  } else {
+    SPED_TRY(validate_walk_args(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, counter, false));
+  }
+  const int64_t n = L->n;
+  Carver c(ws);
+  float *T[2] = {nullptr, nullptr};
+  if (m >= 1) T[0] = c.take<float>(size_t(n > 0 ? n : 1) * size_t(k));
+  if (m >= 2) T[1] = c.take<float>(size_t(n > 0 ? n : 1) * size_t(k));
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query || n == 0) return SPED_OK;
+  const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
+  size_t xs = size_t((n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((n - 1) * ldy + k) * dtype_size(ydt);
+  if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
+  return hybrid_estimate_impl(L, coeffs, degree, m, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
+                              T[0], T[1], as_stream(stream));
 }
 
 namespace sped {

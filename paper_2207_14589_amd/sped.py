@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", _c_i32), ("eta", _c_f64), ("tol", _c_f64), ("max_iters", _c_i32),
                 ("check_every", _c_i32), ("guard", _c_i32), ("orth_passes", _c_i32),
                 ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64),
-                ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32)]
+                ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32), ("stochastic_exact_terms", _c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -62,6 +62,8 @@ SIGNATURES = {
                         _P(_c_sz), _c_vp],
     "sped_apply_poly_stochastic": [_P(CSR), _P(_c_f64), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
                                    _c_i32, _c_i32, _c_i64, _c_u64, _c_u64, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_apply_poly_hybrid": [_P(CSR), _P(_c_f64), _c_i32, _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp,
+                               _c_i64, _c_i32, _c_i32, _c_i64, _c_u64, _c_u64, _c_vp, _P(_c_sz), _c_vp],
     "sped_apply_limit_lazy": [_P(CSR), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_i64,
                               _c_u64, _c_u64, _c_vp, _P(_c_sz), _c_vp],
     "sped_poly_backward": [_P(CSR), _c_i32, _c_f64, _c_f64, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_vp,
@@ -280,6 +282,21 @@ def apply_poly_stochastic(L: Laplacian, coeffs, X, walks, seed, counter=0, sampl
     return (out, counts) if accept_counts else out
 
 
+def apply_poly_hybrid(L: Laplacian, coeffs, X, exact_terms, walks, seed, counter=0, sampler="importance",
+                      out=None, out_dtype=None):
+    """Estimate of sum_i c_i L^i X with terms i < exact_terms exact and the
+    tail sampled by walks (sped_apply_poly_hybrid)."""
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    k = X.shape[1]
+    smp = {"importance": 0, "reject": 1}[sampler]
+    if out is None:
+        out = torch.empty(L.n, k, dtype=out_dtype or X.dtype, device=X.device)
+    _call_ws(lib().sped_apply_poly_hybrid, "sped_apply_poly_hybrid",
+             (L.ref, c.ctypes.data_as(ctypes.POINTER(_c_f64)), len(c) - 1, int(exact_terms), k, _ptr(X), _ld(X),
+              _dt(X), _ptr(out), _ld(out), _dt(out), smp, int(walks), int(seed), int(counter)), X.device)
+    return out
+
+
 def apply_limit_lazy(L: Laplacian, ell, X, walks, seed, counter=0, out=None, out_dtype=None):
     """Unbiased lazy node-walk estimate of (I - L/ell)^ell X."""
     k = X.shape[1]
@@ -333,7 +350,7 @@ class SolveResult:
 
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
-            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance"):
+            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=0):
     dev = L.device
     kb = k + guard
     if V0 is None:
@@ -345,7 +362,8 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
     o = SolveOpts(solver={"subspace": 0, "oja": 1, "mu_eg": 2}[solver], eta=eta, tol=tol, max_iters=max_iters,
                   check_every=check_every, guard=guard, orth_passes=orth_passes,
                   stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
-                  coarse_tol=coarse_tol, stochastic_sampler={"importance": 0, "lazy": 1}[sampler])
+                  coarse_tol=coarse_tol, stochastic_sampler={"importance": 0, "lazy": 1}[sampler],
+                  stochastic_exact_terms=int(exact_terms))
     st = SolveStats()
     ps = poly.struct() if poly is not None else None
     status, _ = _call_ws(lib().sped_bottomk_solve, "sped_bottomk_solve",

@@ -124,3 +124,35 @@ def test_workspace_size_query_without_device(lib):
     aligned = (ctypes.addressof(ws) + 255) // 256 * 256
     assert lib.sped_gram(1000, 32, 32, 256, 32, 256, 32, 0, 512, aligned, ctypes.byref(small), None) == \
         sped.E_WORKSPACE
+
+
+def test_hybrid_validation(lib):
+    """exact_terms outside [0, degree]; the exact split (m = degree) needs no
+    walk records; X and Y may not overlap."""
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 0, 0, sped.SYM_NORMALIZED
+    coeffs = (ctypes.c_double * 5)(0.5, -0.5, 0.25, -0.1, 0.05)
+    need = ctypes.c_size_t(0)
+    for m in (-1, 5):
+        assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, m, 8, None, 8, 0, None, 8, 0, 0, 4, 1, 0,
+                                          None, ctypes.byref(need), None) == sped.E_INVALID
+        assert b"exact_terms" in lib.sped_last_error()
+    c.n, c.nnz = 100, 400
+    c.rowptr = c.diag = c.scale = c.col = c.val = c.bins = 16
+    assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 2, 8, 256, 8, 0, 512, 8, 0, 0, 4, 1, 0,
+                                      None, ctypes.byref(need), None) == sped.E_INVALID
+    assert b"walk records" in lib.sped_last_error()
+    assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 4, 8, 256, 8, 0, 512, 8, 0, 0, 4, 1, 0,
+                                      None, ctypes.byref(need), None) == sped.OK
+    assert need.value >= 2 * 100 * 8 * 4
+    assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 1, 8, 256, 8, 0, 512, 8, 0, 0, 4, 1, 0,
+                                      None, ctypes.byref(need), None) == sped.E_INVALID
+    c.wentry = c.wnode = 16
+    assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 1, 8, 256, 8, 0, 512, 8, 0, 0, 4, 1, 0,
+                                      None, ctypes.byref(need), None) == sped.OK
+    assert 100 * 8 * 4 <= need.value < 2 * 100 * 8 * 4
+    ws = ctypes.create_string_buffer(need.value + 512)
+    aligned = (ctypes.addressof(ws) + 255) // 256 * 256
+    assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 1, 8, 4096, 8, 0, 4096 + 64, 8, 0, 0, 4, 1,
+                                      0, aligned, ctypes.byref(need), None) == sped.E_INVALID
+    assert b"overlap" in lib.sped_last_error()

@@ -300,6 +300,64 @@ def test_stochastic_importance_same_walks(sped, kind):
     assert (np.abs(Y[rows] - Yr) / scale).max() < 1e-4
 
 
+@pytest.mark.parametrize("kind,m,ydt", [("sym", 1, "f32"), ("sym", 3, "bf16"), ("combinatorial", 2, "f32"),
+                                         ("sym", 4, "f32")])
+def test_hybrid_same_walks(sped, kind, m, ydt):
+    """Exact low-order terms plus sampled tail: the same walks as the oracle's
+    (m = 4 = degree: no walks, the exact polynomial)."""
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"hybrid parity kind={kind} m={m} y={ydt}")
+    L = sped.Laplacian(n, src, dst, w, kind=kind)
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED if kind == "sym" else olap.COMBINATORIAL)
+    X = synth.gaussian_block(n, 16, 5).astype(np.float32)
+    c = np.array([0.9, -0.5, 0.25, -0.1, 0.05]) / (1.0 if kind == "sym" else np.array([1, 100, 1e4, 1e6, 1e8]))
+    out_dt = torch.bfloat16 if ydt == "bf16" else torch.float32
+    Y = sped.apply_poly_hybrid(L, c, torch.from_numpy(X).cuda(), m, walks=6, seed=11, counter=4,
+                               out_dtype=out_dt).float().cpu().numpy()
+    Yr = owalk.estimate_hybrid(ref, c, X.astype(np.float64), m, 6, seed=11, counter=4)
+    scale = np.abs(Yr).max(axis=1, keepdims=True) + 1.0
+    tol = 8e-3 if ydt == "bf16" else 1e-4
+    assert (np.abs(Y - Yr) / scale).max() < tol
+
+
+def test_hybrid_reject_sampler_same_trials(sped):
+    _say("hybrid with the rejection sampler, m=2")
+    n, s, d, _ = synth.sbm_bernoulli([60, 80], 0.2, 0.02, seed=2)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 8, 6).astype(np.float32)
+    c = np.array([0.9, -0.5, 0.25, -0.1, 0.05])
+    trials = 200000
+    Y = sped.apply_poly_hybrid(L, c, torch.from_numpy(X).cuda(), 2, walks=trials, seed=5, counter=2,
+                               sampler="reject").cpu().numpy()
+    Yr = owalk.estimate_hybrid(ref, c, X.astype(np.float64), 2, 0, seed=5, counter=2, sampler="reject",
+                               n_trials=trials)
+    scale = np.abs(Yr).max(axis=1, keepdims=True) + 1.0
+    assert (np.abs(Y - Yr) / scale).max() < 1e-4
+
+
+def test_hybrid_full_size_sampled_rows(sped, c2_case):
+    """n = 1e6, k = 32, degree-16 limit polynomial, 8 walks per row, 2 exact
+    terms: sampled rows against the oracle, which needs the tail only on the
+    rows' 2-hop neighbourhoods."""
+    L, ref, X = c2_case
+    _say("hybrid m=2 at n=1e6, k=32, sampled rows")
+    c = opoly.limit_exp(16).coeffs
+    Y = sped.apply_poly_hybrid(L, c, torch.from_numpy(X).cuda(), 2, walks=8, seed=3, counter=1).cpu().numpy()
+    rows = np.concatenate([np.random.default_rng(1).choice(L.n, 48, replace=False), [0, L.n - 1]])
+    A = ref.L.tocsr()
+    n1 = np.unique(np.concatenate([rows, A[rows].indices]))
+    n2 = np.unique(np.concatenate([n1, A[n1].indices]))
+    X64 = X.astype(np.float64)
+    U = np.zeros_like(X64)
+    U[n2] = owalk.estimate_importance(ref, c[2:], X64, 8, seed=3, counter=1, rows=n2)
+    U1 = np.zeros_like(X64)
+    U1[n1] = A[n1] @ U + c[1] * X64[n1]
+    Yr = A[rows] @ U1 + c[0] * X64[rows]
+    err = np.abs(Y[rows] - Yr)
+    assert err.max() <= 1e-4 * max(1.0, np.abs(Yr).max())
+
+
 def test_stochastic_reject_same_walks(sped):
     _say("rejection walks parity")
     n, s, d, _ = synth.sbm_bernoulli([60, 80], 0.2, 0.02, seed=2)
@@ -733,3 +791,30 @@ def test_solver_stochastic_phase_lazy_vs_edge_walks(sped):
         assert osol.max_principal_angle(U, r2.V.cpu().numpy().astype(np.float64)) < 1e-5
     assert err["lazy"] < err["importance"]
     _say(f"  subspace error after 40 random iterations: edge {err['importance']:.3e}, lazy {err['lazy']:.3e}")
+
+
+def test_solver_stochastic_phase_exact_low_terms(sped):
+    """The same random-estimate phase with the first 3 terms of the degree-8
+    limit polynomial exact and the tail sampled: the iterate ends closer to
+    the true bottom-10 subspace than with the plain edge walk, each iteration
+    costs 3 sparse steps (counted), and exact iterations then reach 1e-6."""
+    _say("solver stochastic phase: exact low-order terms")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    p = sped.transform("limit", 8)
+    err = {}
+    for m in (0, 3):
+        r = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=0.0, max_iters=40, stochastic_iters=40, walks_per_row=8,
+                         exact_terms=m)
+        err[m] = osol.subspace_error(U, r.V.cpu().numpy().astype(np.float64))
+        rr_steps = r.stats["iters"] // 1  # one Rayleigh-Ritz sparse step per check (check_every = 1)
+        assert r.stats["spmm_count"] == 40 * m + rr_steps
+    assert err[3] < 0.5 * err[0]
+    r2 = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=1e-6, max_iters=3000, stochastic_iters=20, walks_per_row=8,
+                      exact_terms=3)
+    assert r2.converged
+    assert osol.max_principal_angle(U, r2.V.cpu().numpy().astype(np.float64)) < 1e-5
+    _say(f"  subspace error after 40 random iterations: m=0 {err[0]:.3e}, m=3 {err[3]:.3e}")

@@ -278,3 +278,59 @@ def test_lazy_walk_error_below_edge_walks():
     e_lazy = np.linalg.norm(lazy - exact) / np.linalg.norm(exact)
     e_edge = np.linalg.norm(edge - exact) / np.linalg.norm(exact)
     assert e_lazy < 0.8 * e_edge
+
+
+# ---------------------------------------------------------------- exact low-order terms, sampled tail
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_hybrid_special_cases(kind):
+    """m = 0 is the plain importance estimate (same walks, same numbers);
+    m = l uses no walks and is the polynomial itself (dense matrix powers)."""
+    lap = _tiny_graph(kind, weighted=True)
+    V = synth.gaussian_block(lap.n, 3, 9)
+    c = np.array([0.4, -0.6, 0.3, -0.2, 0.1])
+    np.testing.assert_array_equal(owalk.estimate_hybrid(lap, c, V, 0, 50, seed=2, counter=1),
+                                  owalk.estimate_importance(lap, c, V, 50, seed=2, counter=1))
+    np.testing.assert_allclose(owalk.estimate_hybrid(lap, c, V, 4, 50, seed=2), _exact_poly(lap, c, V),
+                               atol=1e-12)
+    with pytest.raises(ValueError):
+        owalk.estimate_hybrid(lap, c, V, 5, 50, seed=2)
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+@pytest.mark.parametrize("m", [1, 2])
+def test_hybrid_monte_carlo(kind, m):
+    """Unbiased for every split point: z-scores over independent seeds against
+    the dense polynomial (a wrong coefficient shift or Horner order biases it)."""
+    lap = _tiny_graph(kind, weighted=True)
+    V = synth.gaussian_block(lap.n, 2, 3)
+    c = np.array([0.5, -0.8, 0.45, -0.3, 0.2])
+    exact = _exact_poly(lap, c, V)
+    est = np.stack([owalk.estimate_hybrid(lap, c, V, m, 2000, seed=s) for s in range(24)])
+    mean, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(est.shape[0])
+    z = np.abs(mean - exact) / np.maximum(se, 1e-15)
+    assert z.max() < 5.0
+
+
+def test_hybrid_reject_sampler_unbiased():
+    lap = _tiny_graph(olap.COMBINATORIAL, weighted=False)
+    V = synth.gaussian_block(lap.n, 2, 6)
+    c = np.array([0.5, -0.5, 0.25, -0.125])
+    exact = _exact_poly(lap, c, V)
+    est = np.stack([owalk.estimate_hybrid(lap, c, V, 1, 0, seed=s, sampler="reject", n_trials=40000)
+                    for s in range(16)])
+    mean, se = est.mean(0), est.std(0, ddof=1) / np.sqrt(est.shape[0])
+    assert (np.abs(mean - exact) / np.maximum(se, 1e-15)).max() < 5.0
+
+
+def test_hybrid_error_falls_with_exact_terms():
+    """On the 2000-node SBM with the degree-8 limit polynomial and 8 walks per
+    row, the low-order terms carry most of the variance: each exact term cuts
+    the error several-fold (measured 1.10, 0.40, 0.11 relative error)."""
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=0)
+    lap = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    V = synth.gaussian_block(n, 8, 2)
+    c = opoly.limit_exp(8).coeffs
+    exact = opoly.apply_terms(lap.L, opoly.limit_exp(8), V)
+    err = [np.linalg.norm(owalk.estimate_hybrid(lap, c, V, m, 8, seed=1) - exact) / np.linalg.norm(exact)
+           for m in (0, 1, 2)]
+    assert err[1] < 0.6 * err[0] and err[2] < 0.5 * err[1]
