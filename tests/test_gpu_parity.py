@@ -456,6 +456,26 @@ def test_bottomk_solve_c1(sped, poly):
     _say(f"  iters={r.stats['iters']} spmm={r.stats['spmm_count']} angle={ang:.2e}")
 
 
+def test_bottomk_combinatorial_limit_cuts_iterations(sped):
+    """Combinatorial L of the 2,000-node SBM (lambda_bound = 2 d_max = 56):
+    the degree-32 limit operator (2l > lambda_bound) reaches the bottom-10
+    span at the 1e-5 bound in a handful of iterations and within 1e-5 of dense
+    eigh; the plain operator needs more than ten times as many iterations."""
+    _say("bottomk combinatorial C1: limit32 vs plain")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="combinatorial")
+    ref = olap.laplacian(n, s, d, kind=olap.COMBINATORIAL)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    r = sped.bottomk(L, 10, sped.transform("limit", 32, L.lambda_bound), V0=V0, guard=4, tol=1e-5, max_iters=200)
+    assert r.converged, r.stats
+    assert osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64)) <= 1e-5
+    np.testing.assert_allclose(r.evals[1:], lam[1:], rtol=1e-5)
+    rp = sped.bottomk(L, 10, None, V0=V0, guard=4, tol=1e-5, max_iters=10 * r.stats["iters"])
+    assert not rp.converged
+    _say(f"  limit32 iters={r.stats['iters']}; plain not converged after {rp.stats['iters']}")
+
+
 def test_bottomk_oja_and_stochastic_start(sped):
     _say("bottomk with Oja step and stochastic first iterations")
     n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
