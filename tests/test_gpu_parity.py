@@ -189,6 +189,32 @@ def test_apply_poly_padded_ld_and_tiny(sped):
     assert _rel(Y1, opoly.apply_terms(ref.L, opoly.taylor_exp(5), X1.cpu().numpy().astype(np.float64))) < 1e-5
 
 
+@pytest.mark.parametrize("k", [97, 300])
+def test_wide_blocks_span_column_tiles(sped, k):
+    """Blocks wider than one column tile (64 lanes x VEC columns: k = 97 has
+    VEC = 1, two tiles; k = 300 has VEC = 4, two tiles) on the mixed-degree
+    graph: the exact product, the inner-product path of the backward and the
+    walk estimate against the oracle."""
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"wide block k={k}")
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, k, 12).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Y = sped.apply_poly(L, sped.transform("limit", 6), Xd).cpu().numpy()
+    Yr = opoly.apply_terms(ref.L, opoly.limit_exp(6), X.astype(np.float64))
+    assert _rel(Y, Yr) < 3e-5
+    G = synth.gaussian_block(n, k, 13).astype(np.float32)
+    dth = sped.poly_backward(L, 4, Xd, torch.from_numpy(G).cuda()).cpu().numpy()
+    dth_r, _ = ograd.backward(ref.L, np.zeros(5), X.astype(np.float64), G.astype(np.float64))
+    np.testing.assert_allclose(dth, dth_r, rtol=5e-5, atol=5e-5 * np.abs(dth_r).max())
+    c = np.array([0.9, -0.5, 0.25])
+    Ys = sped.apply_poly_stochastic(L, c, Xd, walks=3, seed=2, counter=1).cpu().numpy()
+    rows = np.concatenate([np.arange(30), [0, 17, 1200], np.arange(n - 30, n)])
+    Ysr = owalk.estimate_importance(ref, c, X.astype(np.float64), 3, seed=2, counter=1, rows=rows)
+    assert (np.abs(Ys[rows] - Ysr) / (np.abs(Ysr).max(axis=1, keepdims=True) + 1.0)).max() < 1e-4
+
+
 def test_apply_poly_isolated_nodes(sped):
     _say("apply_poly with isolated nodes")
     src, dst = [0, 1, 2, 5], [1, 2, 3, 6]
