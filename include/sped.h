@@ -313,7 +313,8 @@ sped_status sped_gram(int64_t n, int64_t ka, int64_t kb, const void *A, int64_t 
  * sped_orthonormalize -- in place V <- V R^{-1} with R the Cholesky factor of
  * V^T V (Cholesky QR), repeated `passes` times (2 = CholQR2).  If a pivot
  * breaks down, the Gram matrix is shifted by a multiple of its trace and the
- * factorisation retried.  V DEVICE n x k (ldv), dtype F32; k <= 96.
+ * factorisation retried.  V DEVICE n x k (ldv), dtype F32 or BF16 (the Gram
+ * is float64 either way; products are rounded to V's dtype); k <= 96.
  * R_out DEVICE double k x k or NULL: R of the last pass (upper triangular).
  */
 sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_t ldv, int32_t dt,

@@ -340,9 +340,119 @@ __global__ __launch_bounds__(kBlock) void tsmm_kernel(int64_t n, int kin, int ko
   }
 }
 
+// The same product with 4-wide row loads, for kin a multiple of 4 and rows
+// aligned to 4 elements.  The contraction index is permuted inside each
+// 16-column chunk: lane (li, lk) loads columns 16c + 4lk .. 16c + 4lk + 3 of
+// its row as one vector and feeds the j-th of them to the j-th MFMA of the
+// chunk, and reads the matching row 16c + 4lk + j of T.  T's LDS row stride
+// is 4 mod 64 floats, so those four rows (4 apart) fall in distinct banks.
+// Each wavefront loads its next strip before the current strip's MFMAs.
+inline int tsmm4_lds_stride(int w) { return ((w + 63) / 64) * 64 + 4; }
+
+template <typename TX, typename TO, int TB, bool ADD>
+__global__ __launch_bounds__(kBlock) void tsmm4_kernel(int64_t n, int kin, int kout, const TX *__restrict__ X,
+                                                       int64_t ldx, const double *__restrict__ T, TO *O,
+                                                       int64_t ldo, const TO *Y, int64_t ldy, float beta) {
+  extern __shared__ float sT[];
+  const int S = ((16 * TB + 63) / 64) * 64 + 4;
+  const int kc = (kin + 15) >> 4;  // chunks of 16 input columns, <= TB
+  for (int i = threadIdx.x; i < kc * 16 * 16 * TB; i += kBlock) {
+    const int r = i / (16 * TB), c = i - r * (16 * TB);
+    sT[r * S + c] = (r < kin && c < kout) ? float(T[r * kout + c]) : 0.f;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const float4_t zero4 = float4_t{0.f, 0.f, 0.f, 0.f};
+  const float4_t rowid =
+      __builtin_amdgcn_mfma_f32_16x16x4f32(lk == 0 ? float(li) : 0.f, lk == 0 ? 1.f : 0.f, zero4, 0, 0, 0);
+  const float4_t colid =
+      __builtin_amdgcn_mfma_f32_16x16x4f32(lk == 0 ? 1.f : 0.f, lk == 0 ? float(li) : 0.f, zero4, 0, 0, 0);
+  const int64_t strips = (n + 15) / 16;
+  const int64_t step = int64_t(gridDim.x) * 4;
+  // lane's columns in chunk c: 16c + 4lk .. +3, all inside [0, kin) or all
+  // outside (then columns 0..3 are loaded, which exist since kin >= 4, and zeroed)
+  auto load_strip = [&](int64_t st, float (&xs)[TB][4]) {
+    const int64_t row = min(st * 16 + li, n - 1);
+    const TX *xr = X + row * ldx;
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+      const int col = 16 * c + 4 * lk;
+      VecIO<TX, 4>::load(xr + (col < kin ? col : 0), xs[c]);
+      const uint32_t keep = col < kin ? 0xffffffffu : 0u;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xs[c][j] = __uint_as_float(__float_as_uint(xs[c][j]) & keep);
+    }
+  };
+  int64_t st = int64_t(blockIdx.x) * 4 + wave;
+  if (st >= strips) return;
+  float xa[TB][4];
+  load_strip(st, xa);
+  for (; st < strips; st += step) {
+    float xb[TB][4];
+    const int64_t nx = st + step;
+    if (nx < strips) load_strip(nx, xb);
+    float4_t acc[TB];
+#pragma unroll
+    for (int q = 0; q < TB; ++q) acc[q] = zero4;
+#pragma unroll
+    for (int c = 0; c < TB; ++c) {
+      if (c < kc) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < TB; ++q)
+            acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[c][j], sT[(16 * c + 4 * lk + j) * S + q * 16 + li],
+                                                          acc[q], 0, 0, 0);
+      }
+    }
+    const int64_t row0 = st * 16;
+#pragma unroll
+    for (int q = 0; q < TB; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t orow = row0 + int(rowid[r]);
+        const int oc = q * 16 + int(colid[r]);
+        if (orow < n && oc < kout) {
+          float v = acc[q][r];
+          if (ADD) v = fmaf(beta, to_f32<TO>(Y[orow * ldy + oc]), v);
+          O[orow * ldo + oc] = from_f32<TO>(v);
+        }
+      }
+#pragma unroll
+    for (int c = 0; c < TB; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xa[c][j] = xb[c][j];
+  }
+}
+
 template <typename TX, typename TO, bool ADD>
 sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t ldx, const double *T, void *O,
                           int64_t ldo, const void *Y, int64_t ldy, float beta, hipStream_t s) {
+  const uintptr_t xa = reinterpret_cast<uintptr_t>(X);
+  const bool vec4 = kin % 4 == 0 && ldx % 4 == 0 && xa % (4 * sizeof(TX)) == 0;
+  if (vec4) {
+    const int kmax = kin > kout ? kin : kout;
+    const int TB = kmax <= 16 ? 1 : kmax <= 32 ? 2 : kmax <= 64 ? 4 : 8;
+    const size_t shm = size_t((kin + 15) & ~15) * tsmm4_lds_stride(16 * TB) * sizeof(float);
+    const int64_t strips = (n + 15) / 16;
+    const int64_t want = (strips + 15) / 16;  // about 4 strips per wavefront
+    const unsigned blocks = unsigned(want < 1 ? 1 : (want > 4096 ? 4096 : want));
+#define SPED_TSMM4(B)                                                                                     \
+  {                                                                                                       \
+    SPED_TRY(set_max_lds(tsmm4_kernel<TX, TO, B, ADD>, shm));                                             \
+    hipLaunchKernelGGL((tsmm4_kernel<TX, TO, B, ADD>), dim3(blocks), dim3(kBlock), shm, s, n, kin, kout,  \
+                       static_cast<const TX *>(X), ldx, T, static_cast<TO *>(O), ldo,                     \
+                       static_cast<const TO *>(Y), ldy, beta);                                            \
+  }
+    if (TB == 1) SPED_TSMM4(1)
+    else if (TB == 2) SPED_TSMM4(2)
+    else if (TB == 4) SPED_TSMM4(4)
+    else SPED_TSMM4(8)
+#undef SPED_TSMM4
+    SPED_CHECK_HIP(hipGetLastError());
+    return SPED_OK;
+  }
   const int TBO = (kout + 15) / 16;
   const size_t shm = size_t((kin + 15) & ~15) * tsmm_lds_stride(16 * TBO) * sizeof(float);
   const int64_t strips = (n + 15) / 16;

@@ -149,7 +149,7 @@ extern "C" sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_
   if (n < 0 || k < 1 || k > dense_max_k()) return fail(SPED_E_INVALID, "orthonormalize shape (k in [1, 96])");
   if (n < k) return fail(SPED_E_INVALID, "orthonormalize needs n >= k");
   if (ldv < k) return fail(SPED_E_INVALID, "ldv < k");
-  if (dt != SPED_F32) return fail(SPED_E_UNSUPPORTED, "orthonormalize dtype must be F32");
+  if (dt != SPED_F32 && dt != SPED_BF16) return fail(SPED_E_UNSUPPORTED, "orthonormalize dtype must be F32 or BF16");
   if (passes < 1 || passes > 4) return fail(SPED_E_INVALID, "passes outside [1, 4]");
   if (!V) return fail(SPED_E_INVALID, "V NULL");
   Carver c(ws);
@@ -164,7 +164,7 @@ extern "C" sped_status sped_orthonormalize(int64_t n, int64_t k, void *V, int64_
   hipStream_t s = as_stream(stream);
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, w.flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
-  SPED_TRY(cholqr(n, int(k), V, V, ldv, SPED_F32, passes, R_out, w, s));
+  SPED_TRY(cholqr(n, int(k), V, V, ldv, dt, passes, R_out, w, s));
   int flags[4];
   SPED_CHECK_HIP(hipMemcpyAsync(flags, w.flags, sizeof(flags), hipMemcpyDeviceToHost, s));
   SPED_CHECK_HIP(hipStreamSynchronize(s));

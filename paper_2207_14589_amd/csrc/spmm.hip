@@ -86,6 +86,58 @@ struct Step {
     }
   }
 
+  // The same sum with every load unconditional (no exec-mask branches):
+  // (col, val) indices are clamped into the row, and the neighbour rows of a
+  // partial batch of 8 re-read the batch's first row, their terms masked off
+  // bitwise.  Faster with 16 or more lanes per row (k >= 61 at 4 columns per
+  // lane: 12-17% on bf16 k = 64 blocks), slower with 8 (5-7% at k = 32).
+  __device__ static void gather_straight(const int32_t *__restrict__ col, const float *__restrict__ val,
+                                         const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end,
+                                         int G, int lig, int first, int stride, int c0, bool col_ok,
+                                         float (&acc)[VEC]) {
+    int64_t p = beg + int64_t(first) * G;
+    if (p >= end) return;
+    int32_t myc = ld_stream(col + min(p + lig, end - 1));
+    float myv = ld_stream(val + min(p + lig, end - 1));
+    for (; p < end; p += int64_t(stride) * G) {
+      const int cnt = int(min<int64_t>(G, end - p));
+      const int64_t pn = p + int64_t(stride) * G;
+      int32_t nc = 0;
+      float nv = 0.f;
+      if (pn < end) {  // uniform over the group
+        nc = ld_stream(col + min(pn + lig, end - 1));
+        nv = ld_stream(val + min(pn + lig, end - 1));
+      }
+      for (int t = 0; t < cnt; t += 8) {
+        int32_t j[8];
+        float sv[8];
+        uint32_t keep[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          j[u] = __shfl(myc, (t + u) & (G - 1), G);
+          sv[u] = __shfl(myv, (t + u) & (G - 1), G);
+          keep[u] = (t + u < cnt) ? 0xffffffffu : 0u;
+        }
+        if (col_ok) {
+          float x[8][VEC];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int32_t jj = (t + u < cnt) ? j[u] : j[0];
+            VecIO<TU, VEC>::load(U + int64_t(jj) * ldu + c0, x[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+              acc[v] = fmaf(__uint_as_float(__float_as_uint(sv[u]) & keep[u]),
+                            __uint_as_float(__float_as_uint(x[u][v]) & keep[u]), acc[v]);
+        }
+      }
+      myc = nc;
+      myv = nv;
+    }
+  }
+
   // O[row] = a (diag U[row] - acc) + b U[row] + g V[row]; returns <O[row], W[row]>
   // over this lane's columns when DOT.
   __device__ static double epilogue(int64_t row, int c0, const float *__restrict__ diag,
@@ -136,7 +188,7 @@ struct XcdRows {
 // block b takes the (b / 8)-th run of 256/G rows inside XCD (b % 8)'s range:
 // each die walks a contiguous stretch of rows (neighbour rows of nearby nodes
 // share its L2) and the ranges carry equal work.
-template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_light(
     XcdRows xr, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
@@ -159,7 +211,8 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
       float acc[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-      S::gather(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
+      if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
+      else S::gather(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
       if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
     }
   }
@@ -170,7 +223,7 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
   }
 }
 
-template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_medium(
     int64_t n_rows, const int32_t *__restrict__ rows, int k, int G, int lgG,
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
@@ -192,7 +245,8 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
     float acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-    S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+    if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+    else S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
     for (int off = G; off < 64; off <<= 1)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
@@ -205,7 +259,7 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
   }
 }
 
-template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_heavy(
     const int32_t *__restrict__ rows, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
@@ -223,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void spmm_heavy(
   float acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-  S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+  if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+  else S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
   __syncthreads();
@@ -303,27 +358,48 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
   const TV *V = static_cast<const TV *>(a.V);
   TO *O = static_cast<TO *>(a.O);
   double *part = a.dot_partials;
+  // unconditional gathers pay off with 16 or more lanes per row
+  const bool straight = VEC == 4 && g.G >= 16;
   if (g.light_blocks > 0) {
     const dim3 grid = dim3(unsigned(g.light_blocks), unsigned(g.ytiles));
-    hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, g.xr, int(k),
-                       g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
-                       cf, a.dotw, a.lddw, part);
+    if constexpr (VEC == 4) {
+      if (straight)
+        hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, true>), grid, dim3(kBlock), 0, s, g.xr, int(k),
+                           g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
+                           cf, a.dotw, a.lddw, part);
+    }
+    if (!straight)
+      hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, false>), grid, dim3(kBlock), 0, s, g.xr, int(k),
+                         g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
+                         cf, a.dotw, a.lddw, part);
     SPED_CHECK_HIP(hipGetLastError());
     if (DOT) part += g.light_blocks * g.ytiles;
   }
   if (g.medium_blocks > 0) {
     const dim3 grid = dim3(unsigned(g.medium_blocks), unsigned(g.ytiles));
-    hipLaunchKernelGGL((spmm_medium<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n_medium,
-                       L->bins, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu,
-                       V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part);
+#define SPED_MEDIUM(ST)                                                                                    \
+  hipLaunchKernelGGL((spmm_medium<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s, L->n_medium,      \
+                     L->bins, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, \
+                     O, a.ldo, cf, a.dotw, a.lddw, part)
+    if constexpr (VEC == 4) {
+      if (straight) SPED_MEDIUM(true);
+    }
+    if (!straight) SPED_MEDIUM(false);
+#undef SPED_MEDIUM
     SPED_CHECK_HIP(hipGetLastError());
     if (DOT) part += g.medium_blocks * g.ytiles;
   }
   if (g.heavy_blocks > 0) {
     const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
-    hipLaunchKernelGGL((spmm_heavy<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s,
-                       L->bins + L->n_medium, int(k), g.G, g.lgG, L->rowptr, L->col, L->val,
-                       L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part);
+#define SPED_HEAVY(ST)                                                                                     \
+  hipLaunchKernelGGL((spmm_heavy<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s,                    \
+                     L->bins + L->n_medium, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U,    \
+                     a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
+    if constexpr (VEC == 4) {
+      if (straight) SPED_HEAVY(true);
+    }
+    if (!straight) SPED_HEAVY(false);
+#undef SPED_HEAVY
     SPED_CHECK_HIP(hipGetLastError());
   }
   return SPED_OK;

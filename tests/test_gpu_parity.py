@@ -441,7 +441,7 @@ def test_gram_parity(sped, dt, ka, kb):
     np.testing.assert_array_equal(G, G2)   # fixed reduction order
 
 
-@pytest.mark.parametrize("k", [14, 57, 96])
+@pytest.mark.parametrize("k", [14, 56, 57, 96])
 def test_orthonormalize_and_rr(sped, k):
     """CholQR2 (fused Cholesky and triangular inverse) and Rayleigh-Ritz
     (Jacobi eigensolver, odd widths padded) against the oracle's Householder
@@ -460,6 +460,20 @@ def test_orthonormalize_and_rr(sped, k):
     th_r, Q_r, res_r = osol.rayleigh_ritz(ref.L, Qd.cpu().numpy().astype(np.float64))
     np.testing.assert_allclose(theta.cpu().numpy(), th_r, rtol=1e-5, atol=1e-6)
     np.testing.assert_allclose(resid.cpu().numpy(), res_r, rtol=1e-3, atol=1e-5)
+
+
+@pytest.mark.parametrize("k,rows", [(64, 5003), (8, 77), (96, 1000)])
+def test_orthonormalize_bf16(sped, k, rows):
+    """CholQR2 of a bf16 block (bf16 Gram operands, float64 Gram, bf16 output)
+    against the oracle's basis: orthonormal to bf16 rounding, same span; a
+    ragged row count and the widest block."""
+    _say(f"CholQR2 bf16 k={k} n={rows}")
+    V = synth.gaussian_block(rows, k, 4).astype(np.float32)
+    Vb = torch.from_numpy(V).cuda().to(torch.bfloat16)
+    Q = sped.orthonormalize(Vb.clone(), passes=2).float().cpu().numpy().astype(np.float64)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 3e-2
+    Vr = Vb.float().cpu().numpy().astype(np.float64)
+    assert osol.max_principal_angle(Vr, Q) < 2e-2
 
 
 @pytest.mark.parametrize("poly", ["limit", "plain"])
