@@ -365,6 +365,52 @@ def _sin_angle(U, V, np):
     return float(np.linalg.norm(Q - U @ (U.T @ Q), 2))
 
 
+def rmat26_solver(sped, synth, torch, np, iters=3):
+    """The R-MAT workload at its full shape: scale 26 (2^26 nodes, edge factor
+    16, a, b, c = 0.57, 0.19, 0.19, seeded vertex permutation), drawn on the
+    device, largest component, symmetric normalised L; bottom 64 (+8 guard)
+    with bf16 iterate storage.  A few solver iterations each with the plain
+    operator, the exact degree-16 limit polynomial, and the limit polynomial
+    estimated by 8 lazy node walks per row, timed end to end (iterations,
+    Cholesky-QR2 and Rayleigh-Ritz checks included).  Prints one progress line
+    per stage."""
+    t0 = time.perf_counter()
+    n0, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    print(json.dumps({"rmat26": "generated", "edges": int(src.numel()), "seconds": round(gen_s, 2)}), flush=True)
+    t0 = time.perf_counter()
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del src, dst
+    torch.cuda.empty_cache()
+    print(json.dumps({"rmat26": "built", "n_lcc": L.n, "nnz": L.nnz, "seconds": round(build_s, 2)}), flush=True)
+    k, guard = 64, 8
+    V0 = synth.gaussian_block_device(L.n, k + guard, seed=2)
+    out = {"workload": "R-MAT scale 26, edge factor 16 (0.57, 0.19, 0.19), device draw; largest component; "
+                       "sym-normalised L; bottom 64 (+8 guard), bf16 iterate storage",
+           "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree, "generate_s": round(gen_s, 2),
+           "build_s": round(build_s, 2)}
+    p16 = sped.transform("limit", 16)
+    runs = (("plain", None, {}), ("sped_limit16_exact", p16, {}),
+            ("sped_limit16_lazy_walks", p16, {"stochastic_iters": iters, "walks_per_row": 8, "sampler": "lazy"}))
+    sped.bottomk(L, k, None, V0=V0, guard=guard, tol=0.0, max_iters=1, storage="bf16")  # warm
+    for name, p, kw in runs:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=iters, storage="bf16", **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"iters": r.stats["iters"], "seconds": round(dt, 3),
+                     "seconds_per_iter": round(dt / max(r.stats["iters"], 1), 4), "spmm": r.stats["spmm_count"],
+                     "bound": r.stats["bound"], "gap_estimate": r.stats["gap_estimate"]}
+        print(json.dumps({"rmat26": name, **out[name]}), flush=True)
+        del r
+        torch.cuda.empty_cache()
+    return out
+
+
 def paper_experiments(sped, synth, torch, np):
     """Qualitative reproductions of the paper's own synthetic experiments on
     the GPU solvers (combinatorial Laplacian, as there).
@@ -577,6 +623,8 @@ def main():
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
     ap.add_argument("--power-law-only", action="store_true",
                     help="run only the power-law bf16 workload (profiling the SpMM bins)")
+    ap.add_argument("--rmat26", action="store_true",
+                    help="run only the R-MAT scale-26 solver iterations (minutes; not part of the default run)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -617,6 +665,9 @@ def main():
                "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np),
                "paper_experiments": paper_experiments(sped, synth, torch, np)}
         print(json.dumps(out), flush=True)
+        return
+    if args.rmat26:
+        print(json.dumps({"rmat26_solver": rmat26_solver(sped, synth, torch, np)}), flush=True)
         return
     if args.power_law_only:
         print(json.dumps({"power_law_bf16_k64": power_law_bf16(sped, synth, torch, np)}), flush=True)

@@ -274,7 +274,8 @@ sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *coeffs, int3
  *  ell     1..255
  *  X       DEVICE n x k (ldx), F32 or BF16; Y DEVICE n x k (ldy), F32 or BF16;
  *          X and Y must not overlap
- *  ws      DEVICE scratch (2n doubles) or the size-query form
+ *  ws      DEVICE scratch (n doubles: each row's largest move weight) or the
+ *          size-query form
  * Asynchronous on `stream`.
  */
 sped_status sped_apply_limit_lazy(const sped_csr *L, int32_t ell, int64_t k, const void *X,

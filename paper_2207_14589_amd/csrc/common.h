@@ -360,16 +360,18 @@ sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degr
                                int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler, int64_t walks,
                                uint64_t seed, uint64_t counter, int64_t *accept_counts, hipStream_t s);
 
-// lazy node-walk estimate of (I - L/ell)^ell X; xmax, xsum: n doubles of scratch
 // Y = sum_{i<m} c_i L^i X + L^m (walk estimate of the tail); T0 (m >= 1) and
 // T1 (m >= 2) are n x k float32 scratch; counts the sparse steps.
 sped_status hybrid_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int m, int64_t k,
                                  const void *X, int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler,
                                  int64_t walks, uint64_t seed, uint64_t counter, float *T0, float *T1,
                                  hipStream_t s, int64_t *spmm_count = nullptr);
-sped_status lazy_estimate_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
-                               int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, double *xmax,
-                               double *xsum, hipStream_t s);
+// lazy node walks: the per-row largest move weight (n doubles; depends on the
+// graph only), then the walk estimate of (I - L/ell)^ell X that uses it
+sped_status lazy_row_max(const sped_csr *L, double *xmax, hipStream_t s);
+sped_status lazy_walk_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
+                           int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, const double *xmax,
+                           hipStream_t s);
 sped_status validate_lazy(const sped_csr *L, int ell, int64_t walks, uint64_t counter);
 
 sped_status apply_poly_impl(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,

@@ -294,7 +294,6 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   double *Amu = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
   float *Rtmp = mueg ? c.take<float>(size_t(n) * kb) : nullptr;
   double *lz_max = lazy ? c.take<double>(size_t(n)) : nullptr;
-  double *lz_sum = lazy ? c.take<double>(size_t(n)) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -304,6 +303,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   sped_solve_stats stats{};
   hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(64), 0, s, flags, 4);
   SPED_CHECK_HIP(hipGetLastError());
+  if (lazy) SPED_TRY(lazy_row_max(L, lz_max, s));  // graph-only, shared by every iteration
 
   std::vector<double> h_theta(kb), h_resid(kb);
   double h_norm2 = 0.0;
@@ -322,8 +322,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     int since_best = 0;
     for (t = first; t <= iter_cap; ++t) {
       if (t <= o->stochastic_iters && lazy) {
-        SPED_TRY(lazy_estimate_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
-                                    lz_max, lz_sum, s));
+        SPED_TRY(lazy_walk_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
+                                lz_max, s));
       } else if (t <= o->stochastic_iters) {
         SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb,
                                       dt, 0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, s,

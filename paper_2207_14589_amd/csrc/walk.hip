@@ -272,22 +272,22 @@ __device__ inline double lazy_x(int kind, const int32_t *__restrict__ col, const
   return kind == SPED_LAP_SYM_NORMALIZED ? double(val[p]) / double(scale[col[p]]) : double(val[p]);
 }
 
-// Per row: the largest move weight and the sum of the weights in row order.
-__global__ __launch_bounds__(kBlock) void lazy_row_stats_kernel(int64_t n, int kind,
-                                                                const int64_t *__restrict__ rowptr,
-                                                                const int32_t *__restrict__ col,
-                                                                const float *__restrict__ val,
-                                                                const float *__restrict__ scale,
-                                                                double *__restrict__ xmax, double *__restrict__ xsum) {
-  for (int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x; r < n; r += int64_t(gridDim.x) * kBlock) {
-    double m = 0.0, sum = 0.0;
-    for (int64_t p = rowptr[r]; p < rowptr[r + 1]; ++p) {
-      const double x = lazy_x(kind, col, val, scale, p);
-      m = fmax(m, x);
-      sum += x;
-    }
-    xmax[r] = m;
-    xsum[r] = sum;
+// Per row: the largest move weight (one wavefront per row, lanes striding
+// over the entries; the maximum does not depend on the order).
+__global__ __launch_bounds__(kBlock) void lazy_row_max_kernel(int64_t n, int kind,
+                                                              const int64_t *__restrict__ rowptr,
+                                                              const int32_t *__restrict__ col,
+                                                              const float *__restrict__ val,
+                                                              const float *__restrict__ scale,
+                                                              double *__restrict__ xmax) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = int64_t(gridDim.x) * (kBlock / 64);
+  for (int64_t r = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6); r < n; r += waves) {
+    double m = 0.0;
+    const int64_t e = rowptr[r + 1];
+    for (int64_t p = rowptr[r] + lane; p < e; p += 64) m = fmax(m, lazy_x(kind, col, val, scale, p));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if (lane == 0) xmax[r] = m;
   }
 }
 
@@ -295,7 +295,7 @@ template <typename TX, typename TY, int VEC>
 __global__ __launch_bounds__(kBlock) void walk_lazy_kernel(
     int64_t n, int64_t nb, int k, int G, int lgG, int kind, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ scale,
-    const float *__restrict__ diag, const double *__restrict__ xmax, const double *__restrict__ xsum, int ell,
+    const float *__restrict__ diag, const double *__restrict__ xmax, int ell,
     const TX *__restrict__ X, int64_t ldx, TY *__restrict__ Y, int64_t ldy, int64_t walks, uint32_t k0,
     uint32_t k1, uint32_t ctr) {
   const int64_t lb = xcd_logical_block(nb);
@@ -343,8 +343,10 @@ __global__ __launch_bounds__(kBlock) void walk_lazy_kernel(
                 uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, (1u << 20) + 1024u * uint32_t(t) + a) < ratio)
               chosen = p;
           }
-          if (chosen < 0) {  // exact inverse-CDF draw over the row
-            const double target = uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, (1u << 21) + uint32_t(t)) * xsum[z];
+          if (chosen < 0) {  // exact inverse-CDF draw over the row (total summed in row order first)
+            double total = 0.0;
+            for (int64_t p = z0; p < z0 + dz; ++p) total += lazy_x(kind, col, val, scale, p);
+            const double target = uniform53(k0, k1, uint32_t(r), uint32_t(w), ctr, (1u << 21) + uint32_t(t)) * total;
             double run = 0.0;
             chosen = z0 + dz - 1;
             for (int64_t p = z0; p < z0 + dz; ++p) {
@@ -563,7 +565,7 @@ sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degr
 template <typename TX, typename TY>
 sped_status launch_lazy(const sped_csr *L, int64_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, int ell,
                         int64_t walks, uint32_t k0, uint32_t k1, uint32_t ctr, const double *xmax,
-                        const double *xsum, hipStream_t s) {
+                        hipStream_t s) {
   int vec = pick_vec(k, {ldx, ldy}, {X, Y}, {int(sizeof(TX)), int(sizeof(TY))});
   int lanes = int((k + vec - 1) / vec);
   int ytiles = (lanes + 63) / 64;
@@ -574,7 +576,7 @@ sped_status launch_lazy(const sped_csr *L, int64_t k, const void *X, int64_t ldx
   const dim3 grid = dim3(unsigned(xcd_padded_grid(nb)), unsigned(ytiles));
 #define SPED_LZ(V)                                                                                          \
   hipLaunchKernelGGL((walk_lazy_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, nb, int(k), G, lgG,     \
-                     int(L->kind), L->rowptr, L->col, L->val, L->scale, L->diag, xmax, xsum, ell,           \
+                     int(L->kind), L->rowptr, L->col, L->val, L->scale, L->diag, xmax, ell,                 \
                      static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr)
   if (vec == 4) SPED_LZ(4);
   else if (vec == 2) SPED_LZ(2);
@@ -723,23 +725,28 @@ extern "C" sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *c
 
 namespace sped {
 
-sped_status lazy_estimate_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
-                               int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, double *xmax,
-                               double *xsum, hipStream_t s) {
+sped_status lazy_row_max(const sped_csr *L, double *xmax, hipStream_t s) {
   if (L->n == 0) return SPED_OK;
-  int64_t blocks = (L->n + kBlock - 1) / kBlock;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(lazy_row_stats_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, L->n, int(L->kind),
-                     L->rowptr, L->col, L->val, L->scale, xmax, xsum);
+  int64_t blocks = (L->n + kBlock / 64 - 1) / (kBlock / 64);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(lazy_row_max_kernel, dim3(unsigned(blocks)), dim3(kBlock), 0, s, L->n, int(L->kind),
+                     L->rowptr, L->col, L->val, L->scale, xmax);
   SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+sped_status lazy_walk_impl(const sped_csr *L, int ell, int64_t k, const void *X, int64_t ldx, int xdt, void *Y,
+                           int64_t ldy, int ydt, int64_t walks, uint64_t seed, uint64_t counter, const double *xmax,
+                           hipStream_t s) {
+  if (L->n == 0) return SPED_OK;
   const uint32_t k0 = uint32_t(seed & 0xffffffffu), k1 = uint32_t(seed >> 32), ctr = uint32_t(counter);
   if (xdt == SPED_F32 && ydt == SPED_F32)
-    return launch_lazy<float, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+    return launch_lazy<float, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, s);
   if (xdt == SPED_F32 && ydt == SPED_BF16)
-    return launch_lazy<float, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+    return launch_lazy<float, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, s);
   if (xdt == SPED_BF16 && ydt == SPED_F32)
-    return launch_lazy<bf16_t, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
-  return launch_lazy<bf16_t, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, xsum, s);
+    return launch_lazy<bf16_t, float>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, s);
+  return launch_lazy<bf16_t, bf16_t>(L, k, X, ldx, Y, ldy, ell, walks, k0, k1, ctr, xmax, s);
 }
 
 sped_status validate_lazy(const sped_csr *L, int ell, int64_t walks, uint64_t counter) {
@@ -769,13 +776,13 @@ extern "C" sped_status sped_apply_limit_lazy(const sped_csr *L, int32_t ell, int
   SPED_TRY(validate_lazy(L, ell, walks, counter));
   Carver c(ws);
   double *xmax = c.take<double>(size_t(L->n > 0 ? L->n : 1));
-  double *xsum = c.take<double>(size_t(L->n > 0 ? L->n : 1));
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query || L->n == 0) return SPED_OK;
   const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
   size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
   if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
-  return lazy_estimate_impl(L, ell, k, X, ldx, xdt, Y, ldy, ydt, walks, seed, counter, xmax, xsum,
-                            as_stream(stream));
+  hipStream_t s = as_stream(stream);
+  SPED_TRY(lazy_row_max(L, xmax, s));
+  return lazy_walk_impl(L, ell, k, X, ldx, xdt, Y, ldy, ydt, walks, seed, counter, xmax, s);
 }
