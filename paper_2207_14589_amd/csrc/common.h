@@ -353,7 +353,10 @@ sped_status launch_resid(int64_t n, int k, int kn, const float *Z, const void *Q
 // dense.hip (flags: [0] Cholesky shifts, [1] Cholesky failures, [2] Jacobi caps)
 int dense_max_k();
 sped_status launch_chol_inv(int k, const double *G, double *T, double *R_out, int *flags, hipStream_t s);
-sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s);
+// Sweeps stop once the off-diagonal Frobenius norm is at most rel times the
+// whole matrix's.
+sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s,
+                          double rel = 1e-12);
 
 // walk.hip
 sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int64_t k, const void *X,

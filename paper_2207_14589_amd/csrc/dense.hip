@@ -96,7 +96,7 @@ constexpr int kVItems = (kMaxDense * kMaxPairs + kBlock - 1) / kBlock;     // V 
 // ranked ascending in parallel (ties by index).
 __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__restrict__ H,
                                                         double *__restrict__ theta, double *__restrict__ S,
-                                                        int *__restrict__ flags) {
+                                                        int *__restrict__ flags, double rel2) {
   // LDS rows are padded to ld = m + 1 doubles so that walking down a column
   // touches different banks.
   extern __shared__ double sm[];
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__r
       tot2 += red[1][w];
     }
     __syncthreads();  // red is rewritten next sweep
-    if (!(off2 > 1e-24 * tot2) || !(tot2 > 0.0)) break;
+    if (!(off2 > rel2 * tot2) || !(tot2 > 0.0)) break;
     for (int round = 0; round < m - 1; ++round) {
       if (threadIdx.x < npairs) {
         const int q = threadIdx.x;
@@ -244,12 +244,13 @@ sped_status launch_chol_inv(int k, const double *G, double *T, double *R_out, in
   return SPED_OK;
 }
 
-sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s) {
+sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s,
+                          double rel) {
   if (k < 1 || k > kMaxDense) return fail(SPED_E_UNSUPPORTED, "dense width outside [1, 96]");
   const int m = k + (k & 1);
   size_t shm = size_t(2) * m * (m + 1) * sizeof(double);
   SPED_TRY(set_max_lds(jacobi_kernel, shm));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBlock), shm, s, k, H, theta, S, flags);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBlock), shm, s, k, H, theta, S, flags, rel * rel);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }
