@@ -716,8 +716,11 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    chain_ms = np.mean([e[0].elapsed_time(e[1]) for e in evs])
-    parts = {"exact_pLV_ms": round(float(chain_ms), 4)}
+    chain_all = [e[0].elapsed_time(e[1]) for e in evs]
+    chain_ms = np.mean(chain_all)
+    parts = {"exact_pLV_ms": round(float(chain_ms), 4),
+             "exact_pLV_ms_median": round(float(np.median(chain_all)), 4),
+             "exact_pLV_ms_min": round(float(np.min(chain_all)), 4)}
     if not args.chain_only:
         parts["walk_estimate_ms"] = round(float(np.mean([e[1].elapsed_time(e[2]) for e in evs])), 4)
         parts["cholqr2_ms"] = round(float(np.mean([e[2].elapsed_time(e[3]) for e in evs])), 4)
