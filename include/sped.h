@@ -355,7 +355,8 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  *          game's own unit vectors, players in order)
  *  vdt     storage of the iterate: F32, or BF16 (float32 sums, float64 Gram,
  *          Cholesky and Rayleigh-Ritz) until the bound reaches coarse_tol or
- *          stops improving (8 checks without a 2% drop: bf16's rounding floor),
+ *          the largest residual stops improving (8 checks without a 2% drop:
+ *          bf16's rounding floor),
  *          followed by a float32 refinement sweep down to tol
  *  evals   HOST double [k]: Ritz values of L, ascending (for mu-EigenGame those
  *          of L on the span of its vectors)

@@ -313,9 +313,9 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   int t = 0;
   // One phase of iterations with the iterate stored as dt in (Q, W); returns
   // with the Ritz vectors in Q after the last check.
-  // With stall_checks > 0 the phase also ends when the bound has not dropped
-  // below 0.98 x its best value for that many consecutive checks (the
-  // storage's rounding floor has been reached).
+  // With stall_checks > 0 the phase also ends when the largest residual has
+  // not dropped below 0.98 x its best value for that many consecutive checks
+  // (the storage's rounding floor has been reached).
   auto phase = [&](int dt, void *&Q, void *&W, double tol, int iter_cap, int stall_checks,
                    bool *done) -> sped_status {
     *done = false;
@@ -388,8 +388,11 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
           *done = true;
           return SPED_OK;
         }
-        if (stats.bound < 0.98 * best) {
-          best = stats.bound;
+        // progress is judged on the largest residual, which is finite from the
+        // first check (the bound is infinite while the gap estimate is not
+        // positive, which would otherwise read as a stall)
+        if (rmax < 0.98 * best) {
+          best = rmax;
           since_best = 0;
         } else if (stall_checks > 0 && ++since_best >= stall_checks) {
           return SPED_OK;
