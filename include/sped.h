@@ -382,6 +382,9 @@ typedef struct {
                                  (sped_apply_limit_lazy; needs the limit polynomial, solver 0 or 2) */
   int32_t stochastic_exact_terms; /* sampler 0: the first m terms of the polynomial exact, the
                                      tail sampled (sped_apply_poly_hybrid); 0..degree */
+  int32_t use_graphs;      /* nonzero: each exact iteration's launches are captured once into a
+                              HIP graph (per buffer pair, storage and check) and replayed
+                              (bit-identical results; fewer launch overheads on small graphs) */
 } sped_solve_opts;
 
 typedef struct {

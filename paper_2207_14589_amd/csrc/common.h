@@ -354,9 +354,9 @@ sped_status launch_resid(int64_t n, int k, int kn, const float *Z, const void *Q
 int dense_max_k();
 sped_status launch_chol_inv(int k, const double *G, double *T, double *R_out, int *flags, hipStream_t s);
 // Sweeps stop once the off-diagonal Frobenius norm is at most rel times the
-// whole matrix's.
+// whole matrix's; with rel_dev, rel is read from that device scalar instead.
 sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s,
-                          double rel = 1e-12);
+                          double rel = 1e-12, const double *rel_dev = nullptr);
 
 // walk.hip
 sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int64_t k, const void *X,

@@ -96,7 +96,12 @@ constexpr int kVItems = (kMaxDense * kMaxPairs + kBlock - 1) / kBlock;     // V 
 // ranked ascending in parallel (ties by index).
 __global__ __launch_bounds__(kBlock) void jacobi_kernel(int k, const double *__restrict__ H,
                                                         double *__restrict__ theta, double *__restrict__ S,
-                                                        int *__restrict__ flags, double rel2) {
+                                                        int *__restrict__ flags, double rel,
+                                                        const double *__restrict__ rel_dev) {
+  // stopping point: from device memory when given (set by a kernel launched
+  // before this one, so a captured graph can reuse this launch)
+  const double rel_used = rel_dev ? *rel_dev : rel;
+  const double rel2 = rel_used * rel_used;
   // LDS rows are padded to ld = m + 1 doubles so that walking down a column
   // touches different banks.
   extern __shared__ double sm[];
@@ -245,12 +250,12 @@ sped_status launch_chol_inv(int k, const double *G, double *T, double *R_out, in
 }
 
 sped_status launch_jacobi(int k, const double *H, double *theta, double *S, int *flags, hipStream_t s,
-                          double rel) {
+                          double rel, const double *rel_dev) {
   if (k < 1 || k > kMaxDense) return fail(SPED_E_UNSUPPORTED, "dense width outside [1, 96]");
   const int m = k + (k & 1);
   size_t shm = size_t(2) * m * (m + 1) * sizeof(double);
   SPED_TRY(set_max_lds(jacobi_kernel, shm));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBlock), shm, s, k, H, theta, S, flags, rel * rel);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBlock), shm, s, k, H, theta, S, flags, rel, rel_dev);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }

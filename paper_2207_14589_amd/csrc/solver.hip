@@ -31,6 +31,10 @@ __global__ __launch_bounds__(kBlock) void copy_block_kernel(int64_t n, int k, co
   }
 }
 
+__global__ void set_double_kernel(double *p, double v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
 __global__ void zero_int_kernel(int *p, int count) {
   if (int(threadIdx.x) < count) p[threadIdx.x] = 0;
 }
@@ -117,7 +121,7 @@ struct RRWs {
   void *Qtmp;
   double *H, *S, *theta, *resid, *partials, *G, *norm2;
   int *flags;
-  double jacobi_rel = 1e-12;  // stopping point of the k x k eigensolver
+  const double *jacobi_rel = nullptr;  // device scalar: where the k x k eigensolver stops (NULL: 1e-12)
 };
 
 // Rayleigh-Ritz of L on span(Q) (Q of storage type dt, Z = L Q in float32);
@@ -132,7 +136,7 @@ sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, int kn, const voi
   a.a = 1.f; a.b = 0.f; a.g = 0.f;
   SPED_TRY(launch_spmm_step(L, k, a, s));
   SPED_TRY(launch_gram(n, k, k, Q, ld, dt, w.Z, ld, SPED_F32, w.H, w.partials, s));
-  SPED_TRY(launch_jacobi(k, w.H, w.theta, w.S, w.flags, s, w.jacobi_rel));
+  SPED_TRY(launch_jacobi(k, w.H, w.theta, w.S, w.flags, s, 1e-12, w.jacobi_rel));
   SPED_TRY(launch_tsmm(n, k, k, Q, ld, dt, w.S, w.Qtmp, ld, dt, s));
   SPED_TRY(launch_tsmm(n, k, k, w.Z, ld, SPED_F32, w.S, w.ZS, ld, SPED_F32, s));
   SPED_TRY(launch_resid(n, k, kn, w.ZS, w.Qtmp, ld, dt, w.theta, w.G, w.resid, w.norm2, w.partials, s));
@@ -232,6 +236,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->stochastic_iters < 0) return fail(SPED_E_INVALID, "stochastic_iters");
   if (o->stochastic_sampler != 0 && o->stochastic_sampler != 1) return fail(SPED_E_INVALID, "stochastic_sampler");
   const bool lazy = o->stochastic_iters > 0 && o->stochastic_sampler == 1;
+  if (o->use_graphs != 0 && o->use_graphs != 1) return fail(SPED_E_INVALID, "use_graphs must be 0 or 1");
   if (o->stochastic_exact_terms < 0 || (lazy && o->stochastic_exact_terms != 0))
     return fail(SPED_E_INVALID, "stochastic_exact_terms (edge walks only, >= 0)");
   if (o->stochastic_iters > 0 && !lazy && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
@@ -287,6 +292,8 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   rw.partials = ow.partials;
   int *flags = c.take<int>(4);
   ow.flags = rw.flags = flags;
+  double *jrel = c.take<double>(1);
+  rw.jacobi_rel = jrel;
   // mu-EigenGame: its Grams and update matrix, and a buffer for the Ritz
   // vectors of the checks (the game's iterate itself is kept)
   const bool mueg = o->solver == 2;
@@ -316,6 +323,106 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   // With stall_checks > 0 the phase also ends when the largest residual has
   // not dropped below 0.98 x its best value for that many consecutive checks
   // (the storage's rounding floor has been reached).
+  // The device work of one iteration: the operator (exact, or a random
+  // estimate for the first stochastic_iters iterations), the orthonormalisation
+  // or mu-EigenGame update, and with `check` the Rayleigh-Ritz step.
+  auto enqueue = [&](int dt, void *Q, void *W, bool check, bool stoch, hipStream_t q) -> sped_status {
+    if (stoch && lazy) {
+      SPED_TRY(lazy_walk_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
+                              lz_max, q));
+    } else if (stoch) {
+      SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb, dt,
+                                    0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, q, &stats.spmm_count));
+    } else {
+      SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, q, &stats.spmm_count));
+    }
+    if (mueg) {
+      // V <- normalise(V + eta grad), grad the projected mu-EG gradients
+      SPED_TRY(launch_gram(n, int(kb), int(kb), Q, kb, dt, W, kb, dt, G1, ow.partials, q));
+      hipLaunchKernelGGL(mueg_coeffs_kernel, dim3(1), dim3(128), 0, q, int(kb), G1, G3, o->eta, Amu);
+      SPED_CHECK_HIP(hipGetLastError());
+      SPED_TRY(launch_tsmm(n, int(kb), int(kb), Q, kb, dt, Amu, W, kb, dt, q, W, kb, float(o->eta)));
+      SPED_TRY(launch_gram(n, int(kb), int(kb), W, kb, dt, W, kb, dt, G3, ow.partials, q));
+      SPED_TRY(scale_cols(n, int(kb), static_cast<const float *>(W), kb, G3, static_cast<float *>(Q), kb, q));
+    } else {
+      SPED_TRY(cholqr(n, int(kb), W, Q, kb, dt, o->orth_passes, nullptr, ow, q));
+    }
+    if (check) {
+      rw.Z = bufA;
+      rw.ZS = bufB;
+      if (mueg) {  // Ritz pairs of L on span(V), from an orthonormalised copy
+        SPED_TRY(cholqr(n, int(kb), Q, W, kb, dt, o->orth_passes, nullptr, ow, q));
+        rw.Qtmp = Rtmp;
+        SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), W, kb, dt, rw, q));
+      } else {
+        rw.Qtmp = W;  // Ritz vectors land in W
+        SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), Q, kb, dt, rw, q));
+      }
+      stats.spmm_count += 1;
+    }
+    return SPED_OK;
+  };
+  // With use_graphs the exact iterations are captured once per (buffers,
+  // storage, check) into a HIP graph and replayed; the graph holds the same
+  // launches in the same order, so results are bit-identical.  Capture runs on
+  // a stream of its own (the caller's may be the legacy default stream, which
+  // cannot capture); replays run on the caller's stream.
+  struct Captured {
+    const void *Q, *W;
+    int dt;
+    bool check;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int64_t spmm;
+  };
+  std::vector<Captured> graphs;
+  hipStream_t cap = nullptr;
+  struct Cleanup {
+    std::vector<Captured> &g;
+    hipStream_t &c;
+    ~Cleanup() {
+      for (auto &x : g) {
+        (void)hipGraphExecDestroy(x.exec);
+        (void)hipGraphDestroy(x.graph);
+      }
+      if (c) (void)hipStreamDestroy(c);
+    }
+  } cleanup{graphs, cap};
+  auto run_graph = [&](int dt, void *Q, void *W, bool check) -> sped_status {
+    Captured *hit = nullptr;
+    for (auto &x : graphs)
+      if (x.Q == Q && x.W == W && x.dt == dt && x.check == check) hit = &x;
+    if (!hit) {
+      if (!cap) SPED_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      Captured c{Q, W, dt, check, nullptr, nullptr, 0};
+      const int64_t before = stats.spmm_count;
+      SPED_CHECK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+      const sped_status st = enqueue(dt, Q, W, check, false, cap);
+      const hipError_t ec = hipStreamEndCapture(cap, &c.graph);
+      if (st != SPED_OK) {
+        if (ec == hipSuccess && c.graph) (void)hipGraphDestroy(c.graph);
+        return st;
+      }
+      SPED_CHECK_HIP(ec);
+      const hipError_t ei = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        (void)hipGraphDestroy(c.graph);
+        SPED_CHECK_HIP(ei);
+      }
+      c.spmm = stats.spmm_count - before;  // counted again at every replay
+      stats.spmm_count = before;
+      graphs.push_back(c);
+      hit = &graphs.back();
+    }
+    SPED_CHECK_HIP(hipGraphLaunch(hit->exec, s));
+    stats.spmm_count += hit->spmm;
+    return SPED_OK;
+  };
+  // One phase of iterations with the iterate stored as dt in (Q, W); returns
+  // with the Ritz vectors in Q after the last check.
+  // With stall_checks > 0 the phase also ends when the largest residual has
+  // not dropped below 0.98 x its best value for that many consecutive checks
+  // (the storage's rounding floor has been reached).
   auto phase = [&](int dt, void *&Q, void *&W, double tol, int iter_cap, int stall_checks,
                    bool *done) -> sped_status {
     *done = false;
@@ -323,45 +430,21 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     double best = INFINITY;
     int since_best = 0;
     for (t = first; t <= iter_cap; ++t) {
-      if (t <= o->stochastic_iters && lazy) {
-        SPED_TRY(lazy_walk_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
-                                lz_max, s));
-      } else if (t <= o->stochastic_iters) {
-        SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb,
-                                      dt, 0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, s,
-                                      &stats.spmm_count));
-      } else {
-        SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, s, &stats.spmm_count));
-      }
-      if (mueg) {
-        // V <- normalise(V + eta grad), grad the projected mu-EG gradients
-        SPED_TRY(launch_gram(n, int(kb), int(kb), Q, kb, dt, W, kb, dt, G1, ow.partials, s));
-        hipLaunchKernelGGL(mueg_coeffs_kernel, dim3(1), dim3(128), 0, s, int(kb), G1, G3, o->eta, Amu);
-        SPED_CHECK_HIP(hipGetLastError());
-        SPED_TRY(launch_tsmm(n, int(kb), int(kb), Q, kb, dt, Amu, W, kb, dt, s, W, kb, float(o->eta)));
-        SPED_TRY(launch_gram(n, int(kb), int(kb), W, kb, dt, W, kb, dt, G3, ow.partials, s));
-        SPED_TRY(scale_cols(n, int(kb), static_cast<const float *>(W), kb, G3, static_cast<float *>(Q), kb, s));
-      } else {
-        SPED_TRY(cholqr(n, int(kb), W, Q, kb, dt, o->orth_passes, nullptr, ow, s));
-      }
-      if ((t - first + 1) % o->check_every == 0 || t == iter_cap) {
-        rw.Z = bufA;
-        rw.ZS = bufB;
+      const bool check = (t - first + 1) % o->check_every == 0 || t == iter_cap;
+      const bool stoch = t <= o->stochastic_iters;
+      if (check) {
         // Far from convergence the Ritz pairs need not be exact: an early stop
         // leaves S orthogonal (the same subspace) and can only raise the
         // residuals, so the stopping bound stays valid.  The k x k eigensolver
         // stops at 1e-3 x the last bound, within [1e-12, 1e-6] of ||H||.
-        rw.jacobi_rel = std::min(1e-6, std::max(1e-12, 1e-3 * stats.bound));
-        if (mueg) {  // Ritz pairs of L on span(V), from an orthonormalised copy
-          SPED_TRY(cholqr(n, int(kb), Q, W, kb, dt, o->orth_passes, nullptr, ow, s));
-          rw.Qtmp = Rtmp;
-          SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), W, kb, dt, rw, s));
-        } else {
-          rw.Qtmp = W;
-          SPED_TRY(rayleigh_ritz(L, n, int(kb), int(k), Q, kb, dt, rw, s));
-          std::swap(Q, W);  // Ritz vectors now in Q
-        }
-        stats.spmm_count += 1;
+        const double rel = std::min(1e-6, std::max(1e-12, 1e-3 * stats.bound));
+        hipLaunchKernelGGL(set_double_kernel, dim3(1), dim3(64), 0, s, jrel, rel);
+        SPED_CHECK_HIP(hipGetLastError());
+      }
+      if (o->use_graphs && !stoch) SPED_TRY(run_graph(dt, Q, W, check));
+      else SPED_TRY(enqueue(dt, Q, W, check, stoch, s));
+      if (check) {
+        if (!mueg) std::swap(Q, W);  // Ritz vectors now in Q
         SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipMemcpyAsync(&h_norm2, rw.norm2, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -43,7 +43,8 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("solver", _c_i32), ("eta", _c_f64), ("tol", _c_f64), ("max_iters", _c_i32),
                 ("check_every", _c_i32), ("guard", _c_i32), ("orth_passes", _c_i32),
                 ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64),
-                ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32), ("stochastic_exact_terms", _c_i32)]
+                ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32), ("stochastic_exact_terms", _c_i32),
+                ("use_graphs", _c_i32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -350,7 +351,8 @@ class SolveResult:
 
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
-            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=0):
+            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=0,
+            graphs=False):
     dev = L.device
     kb = k + guard
     if V0 is None:
@@ -363,7 +365,7 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
                   check_every=check_every, guard=guard, orth_passes=orth_passes,
                   stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
                   coarse_tol=coarse_tol, stochastic_sampler={"importance": 0, "lazy": 1}[sampler],
-                  stochastic_exact_terms=int(exact_terms))
+                  stochastic_exact_terms=int(exact_terms), use_graphs=int(bool(graphs)))
     st = SolveStats()
     ps = poly.struct() if poly is not None else None
     status, _ = _call_ws(lib().sped_bottomk_solve, "sped_bottomk_solve",

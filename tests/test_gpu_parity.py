@@ -910,3 +910,34 @@ def test_powerlaw_bf16_solve_and_cluster(sped):
     lab, _, _, _ = sped.cluster_embed(r.V, 24, row_normalize=True, seed=1)
     planted = comm[ref.old_of_new]
     assert okm.adjusted_rand_index(lab.cpu().numpy(), planted) > 0.85
+
+
+@pytest.mark.parametrize("case", ["limit", "plain", "limit_check3", "mu_eg", "bf16", "stochastic_first"])
+def test_solver_graph_replay_matches_eager(sped, case):
+    """Iterations captured once into HIP graphs and replayed give the eager
+    solve's result bit for bit (every replay feeds the next, so one wrong
+    replay changes the end result): same iteration count, Ritz values and
+    vectors."""
+    _say(f"graph replay vs eager: {case}")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    kw = dict(V0=V0, guard=4, tol=1e-6, max_iters=3000)
+    p = sped.transform("limit", 8)
+    if case == "plain":
+        p = None
+    elif case == "limit_check3":
+        kw["check_every"] = 3
+    elif case == "mu_eg":
+        kw.update(solver="mu_eg", eta=0.5, tol=0.0, max_iters=120)
+    elif case == "bf16":
+        kw["storage"] = "bf16"
+    elif case == "stochastic_first":
+        kw.update(stochastic_iters=5, walks_per_row=4, exact_terms=2)
+    eager = sped.bottomk(L, 10, p, **kw)
+    graph = sped.bottomk(L, 10, p, graphs=True, **kw)
+    assert graph.stats["iters"] == eager.stats["iters"]
+    assert graph.stats["spmm_count"] == eager.stats["spmm_count"]
+    assert graph.converged == eager.converged
+    np.testing.assert_array_equal(graph.evals, eager.evals)
+    assert torch.equal(graph.V, eager.V)
