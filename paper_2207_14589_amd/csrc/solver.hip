@@ -380,14 +380,16 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   struct Cleanup {
     std::vector<Captured> &g;
     hipStream_t &c;
+    hipStream_t s;
     ~Cleanup() {
+      if (!g.empty()) (void)hipStreamSynchronize(s);  // no replay may still be running
       for (auto &x : g) {
         (void)hipGraphExecDestroy(x.exec);
         (void)hipGraphDestroy(x.graph);
       }
       if (c) (void)hipStreamDestroy(c);
     }
-  } cleanup{graphs, cap};
+  } cleanup{graphs, cap, s};
   auto run_graph = [&](int dt, void *Q, void *W, bool check) -> sped_status {
     Captured *hit = nullptr;
     for (auto &x : graphs)
