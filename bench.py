@@ -248,6 +248,45 @@ def time_to_tolerance(sped, synth, torch, np):
     return out
 
 
+def polyapply_sbm500k(sped, synth, torch, np):
+    """The learnable-coefficient workload: 500k-node SBM (50 blocks, mean
+    degree 24, 5% cross), k = 50, degree 12, float32.  Times PolyApply's
+    forward (Horner: 12 fused steps that also re-read X) and backward (dX by
+    the same Horner chain on dY; dtheta by 12 recomputed powers with the fused
+    float64 inner product), each with its algorithmic bytes."""
+    from paper_2207_14589_amd.autograd import poly_apply
+
+    n, s, d, _ = synth.sbm_from_degrees(500_000, 50, 22.8, 1.2, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym", walk_records=False)
+    k, ell = 50, 12
+    g = torch.Generator(device="cpu").manual_seed(5)
+    theta = (torch.randn(ell + 1, generator=g, dtype=torch.float64) * 0.3).requires_grad_(True)
+    X = synth.gaussian_block_device(L.n, k, seed=6).requires_grad_(True)
+    dY = synth.gaussian_block_device(L.n, k, seed=7)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    Y = poly_apply(theta, X, L, 1.0, 1.0)
+    fwd_ms = timed(lambda: poly_apply(theta, X, L, 1.0, 1.0))
+    bwd_ms = timed(lambda: torch.autograd.grad(Y, (theta, X), dY, retain_graph=True))
+    idx = 8 * (L.n + 1) + L.nnz * 8 + 4 * L.n
+    horner = ell * (idx + L.n * k * 12)                          # U in, O out, X re-read
+    fwd_bytes = horner
+    bwd_bytes = horner + ell * (idx + L.n * k * 12) + L.n * k * 8  # dX chain; powers with dY dot; first dot
+    return {"workload": "SBM n=5e5, 50 blocks, mean degree 24, 5% cross; k=50, degree 12, float32",
+            "forward_ms": round(fwd_ms, 4), "forward_GBps": round(fwd_bytes / (fwd_ms * 1e-3) / 1e9, 1),
+            "backward_ms": round(bwd_ms, 4), "backward_GBps": round(bwd_bytes / (bwd_ms * 1e-3) / 1e9, 1)}
+
+
 def time_to_tolerance_combinatorial(sped, synth, torch, np):
     """The combinatorial Laplacian, whose spectrum reaches 2 d_max: plain
     iteration on lambda_bound I - L contracts the unwanted directions by only
@@ -759,6 +798,7 @@ def main():
         line["time_to_tolerance"] = time_to_tolerance(sped, synth, torch, np)
         line["time_to_tolerance_sbm500k"] = time_to_tolerance_sbm500k(sped, synth, torch, np)
         line["time_to_tolerance_combinatorial"] = time_to_tolerance_combinatorial(sped, synth, torch, np)
+        line["polyapply_sbm500k"] = polyapply_sbm500k(sped, synth, torch, np)
         line["mu_eg_streak"] = mu_eg_streak_sbm2000(sped, synth, torch, np)
         line["paper_experiments"] = paper_experiments(sped, synth, torch, np)
     if not args.no_cpu_baseline and not args.chain_only:
