@@ -220,12 +220,15 @@ def cpu_baseline_leg(n, s, d, X, ell, alg_bytes):
 
     ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
     Xd = X.astype(np.float64)
-    t0 = time.perf_counter()
-    opoly.apply_limit_product(ref.L, ell, Xd)
-    dt = time.perf_counter() - t0
-    return {"value": round(ell * alg_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 3),
-            "sample": f"one full degree-{ell} application (I - L/{ell})^{ell} V on the same {n}-node graph, "
+    reps, dt = 0, 0.0
+    while reps < 3 and (reps == 0 or dt < 10.0):  # about 10 s of CPU work
+        t0 = time.perf_counter()
+        opoly.apply_limit_product(ref.L, ell, Xd)
+        dt += time.perf_counter() - t0
+        reps += 1
+    return {"value": round(reps * ell * alg_bytes / dt / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 3), "applications": reps,
+            "sample": f"{reps} full degree-{ell} applications (I - L/{ell})^{ell} V on the same {n}-node graph, "
                       f"{X.shape[1]} columns, float64 scipy CSR products (single thread)"}
 
 
