@@ -251,6 +251,33 @@ def time_to_tolerance(sped, synth, torch, np):
     return out
 
 
+def gather_probe(sped, torch):
+    """The chip's rate for the sparse step's load pattern (sped_gather_probe):
+    128-byte rows, 8 lanes x 16 bytes per row, 8 rows per instruction, from
+    tables that fit L1, one XCD's L2, or neither; scattered rows against 1 KB
+    contiguous reads.  Rates in TB/s and in 128-byte lines per clock per CU
+    (256 CUs at 2.4 GHz)."""
+    blocks, iters = 2048, 4096
+    out_buf = torch.empty(blocks * 256, dtype=torch.int32, device="cuda")
+    res = []
+    for rows in (128, 16384, 262144):
+        table = torch.zeros(rows, 32, dtype=torch.float32, device="cuda")
+        for scattered in (True, False):
+            sped.gather_probe(table, iters, scattered, blocks, out_buf)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            sped.gather_probe(table, iters, scattered, blocks, out_buf)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+            nbytes = blocks * 256 * iters * 16
+            res.append({"table_kb": rows * 128 // 1024, "pattern": "scattered rows" if scattered else "contiguous 1 KB",
+                        "ms": round(ms, 3), "TBps": round(nbytes / (ms * 1e-3) / 1e12, 2),
+                        "lines_per_clk_per_cu": round(nbytes / 128 / (ms * 1e-3 * 2.4e9) / 256, 3)})
+        del table
+    return res
+
+
 def polyapply_sbm500k(sped, synth, torch, np):
     """The learnable-coefficient workload: 500k-node SBM (50 blocks, mean
     degree 24, 5% cross), k = 50, degree 12, float32.  Times PolyApply's
@@ -665,6 +692,8 @@ def main():
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
     ap.add_argument("--power-law-only", action="store_true",
                     help="run only the power-law bf16 workload (profiling the SpMM bins)")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="measure the chip's rate for the sparse step's row-load pattern")
     ap.add_argument("--rmat26", action="store_true",
                     help="run only the R-MAT scale-26 solver iterations (minutes; not part of the default run)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -707,6 +736,9 @@ def main():
                "mu_eg_streak": mu_eg_streak_sbm2000(sped, synth, torch, np),
                "paper_experiments": paper_experiments(sped, synth, torch, np)}
         print(json.dumps(out), flush=True)
+        return
+    if args.gather_probe:
+        print(json.dumps({"gather_probe": gather_probe(sped, torch)}), flush=True)
         return
     if args.rmat26:
         print(json.dumps({"rmat26_solver": rmat26_solver(sped, synth, torch, np)}), flush=True)

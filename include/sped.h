@@ -433,6 +433,19 @@ sped_status sped_cluster_embed(const void *V, int64_t n, int64_t k, int64_t ldv,
  */
 sped_status sped_stream_copy(const void *src, void *dst, size_t bytes, sped_stream_t stream);
 
+/*
+ * sped_gather_probe -- the chip's rate for the sparse step's load pattern:
+ * `blocks` x 256 threads, each 8-lane group loading `iters` 128-byte rows of
+ * `table` (16 bytes per lane, 8 rows per wavefront instruction, 8 loads in
+ * flight), rows pseudo-random per group (scattered != 0) or 8 consecutive rows
+ * per wavefront.  A measurement aid like sped_stream_copy.
+ *  table  DEVICE, 16-byte aligned, rows x 128 bytes; rows a power of two >= 8
+ *  iters  positive multiple of 8
+ *  out    DEVICE uint32 [blocks x 256] (overwritten; keeps the loads alive)
+ */
+sped_status sped_gather_probe(const void *table, int64_t rows, int32_t iters, int32_t scattered,
+                              int32_t blocks, uint32_t *out, sped_stream_t stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *sped_last_error(void);
 

@@ -79,6 +79,41 @@ __global__ void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ d
   size_t stride = size_t(gridDim.x) * blockDim.x;
   for (; i < n16; i += stride) dst[i] = src[i];
 }
+
+// Row-load rate probe: each wavefront loads 128-byte rows of `table` with 8
+// lanes x 16 bytes per row and 8 rows per load instruction (the layout of the
+// sparse step's neighbour-row gathers at 32 float32 columns), 8 loads in
+// flight, `iters` rows per lane.  scattered: each 8-lane group takes its own
+// pseudo-random row; otherwise the wavefront reads 8 consecutive rows (1 KB).
+// Row indices are masked into the table.
+__global__ __launch_bounds__(256) void gather_probe_kernel(const uint4 *__restrict__ table, uint32_t rows_mask,
+                                                           int iters, int scattered, uint32_t *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 3, l8 = lane & 7;
+  const uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u;
+  uint32_t acc = 0;
+  for (int it = 0; it < iters; it += 8) {
+    uint4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      uint32_t x = h + uint32_t(it + u) * 0x9E3779B9u;
+      if (scattered) x ^= uint32_t(g) * 0x85EBCA6Bu;
+      x ^= x >> 15;
+      x *= 0x2C1B3C6Du;
+      x ^= x >> 12;
+      uint32_t idx;
+      if (scattered) {
+        idx = (uint32_t(__shfl(int(x), lane & ~7, 64)) & rows_mask) * 8u + uint32_t(l8);
+      } else {
+        idx = (uint32_t(__shfl(int(x), 0, 64)) & (rows_mask & ~7u)) * 8u + uint32_t(lane);
+      }
+      v[u] = table[idx];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  out[blockIdx.x * 256u + threadIdx.x] = acc;
+}
 }  // namespace
 
 }  // namespace sped
@@ -100,6 +135,21 @@ extern "C" sped_status sped_stream_copy(const void *src, void *dst, size_t bytes
   if (blocks > 256 * 64) blocks = 256 * 64;
   hipLaunchKernelGGL(copy_kernel, dim3(unsigned(blocks)), dim3(256), 0, as_stream(stream),
                      static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n16);
+  SPED_CHECK_HIP(hipGetLastError());
+  return SPED_OK;
+}
+
+extern "C" sped_status sped_gather_probe(const void *table, int64_t rows, int32_t iters, int32_t scattered,
+                                         int32_t blocks, uint32_t *out, sped_stream_t stream) {
+  clear_error();
+  if (!table || !out) return fail(SPED_E_INVALID, "NULL pointer");
+  if (rows < 8 || rows > (int64_t(1) << 31) || (rows & (rows - 1)))
+    return fail(SPED_E_INVALID, "rows must be a power of two in [8, 2^31]");
+  if (iters < 8 || (iters & 7)) return fail(SPED_E_INVALID, "iters must be a positive multiple of 8");
+  if (blocks < 1) return fail(SPED_E_INVALID, "blocks < 1");
+  if (reinterpret_cast<uintptr_t>(table) & 15) return fail(SPED_E_INVALID, "table must be 16-byte aligned");
+  hipLaunchKernelGGL(gather_probe_kernel, dim3(unsigned(blocks)), dim3(256), 0, as_stream(stream),
+                     static_cast<const uint4 *>(table), uint32_t(rows - 1), int(iters), int(scattered != 0), out);
   SPED_CHECK_HIP(hipGetLastError());
   return SPED_OK;
 }

@@ -77,6 +77,7 @@ SIGNATURES = {
     "sped_cluster_embed": [_c_vp, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, _c_i32, _c_u64, _c_i32, _c_vp, _c_vp,
                            _c_vp, _P(_c_f64), _P(_c_i32), _c_vp, _P(_c_sz), _c_vp],
     "sped_stream_copy": [_c_vp, _c_vp, _c_sz, _c_vp],
+    "sped_gather_probe": [_c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp],
     "sped_last_error": [],
     "sped_version": [],
 }
@@ -388,6 +389,13 @@ def cluster_embed(V, n_clusters, row_normalize=True, seed=0, max_iters=300, init
              (_ptr(V), n, k, _ld(V), _dt(V), n_clusters, int(bool(row_normalize)), int(seed), max_iters,
               _ptr(init_t), _ptr(labels), _ptr(cent), ctypes.byref(inertia), ctypes.byref(iters)), V.device)
     return labels, cent, inertia.value, iters.value
+
+
+def gather_probe(table, iters, scattered, blocks, out):
+    """Launch the row-load rate probe over `table` (rows x 32 float32)."""
+    rows = table.shape[0]
+    _check(lib().sped_gather_probe(_ptr(table), rows, int(iters), int(bool(scattered)), int(blocks), _ptr(out),
+                                   _stream(table.device)), "sped_gather_probe")
 
 
 def stream_copy(src, dst):
