@@ -156,3 +156,12 @@ def test_hybrid_validation(lib):
     assert lib.sped_apply_poly_hybrid(ctypes.byref(c), coeffs, 4, 1, 8, 4096, 8, 0, 4096 + 64, 8, 0, 0, 4, 1,
                                       0, aligned, ctypes.byref(need), None) == sped.E_INVALID
     assert b"overlap" in lib.sped_last_error()
+
+
+def test_gather_probe_validation(lib):
+    need_out = 16
+    assert lib.sped_gather_probe(None, 128, 8, 1, 1, need_out, None) == sped.E_INVALID
+    assert lib.sped_gather_probe(256, 100, 8, 1, 1, need_out, None) == sped.E_INVALID   # not a power of two
+    assert lib.sped_gather_probe(256, 128, 12, 1, 1, need_out, None) == sped.E_INVALID  # iters not a multiple of 8
+    assert lib.sped_gather_probe(256, 128, 8, 1, 0, need_out, None) == sped.E_INVALID   # no blocks
+    assert lib.sped_gather_probe(260, 128, 8, 1, 1, need_out, None) == sped.E_INVALID   # misaligned table
