@@ -86,6 +86,82 @@ struct Step {
     }
   }
 
+  // The same sum with the (col, val) indices in chunks of 4G entries: each
+  // lane loads 4 consecutive entries of each array with one 16-byte load
+  // (dword-aligned; the last 3 entries of the arrays are read one by one), so a
+  // chunk of 4G entries costs two index loads instead of eight.  A load
+  // instruction occupies the texture path for about the same time whatever
+  // its width or lane mask, so fewer index loads leave more of it to the
+  // neighbour-row gathers.  Entry e of a chunk sits in lane e / 4, component
+  // e % 4 (a compile-time constant below, since batches start at multiples
+  // of 8).  With PREFETCH the next chunk's indices load during this chunk's
+  // gathers (long rows); without it the registers stay fewer (light rows,
+  // mostly a single chunk).
+  template <bool PREFETCH>
+  __device__ static void gather4(const int32_t *__restrict__ col, const float *__restrict__ val,
+                                 const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end, int64_t nnz,
+                                 int G, int lig, int first, int stride, int c0, bool col_ok, float (&acc)[VEC]) {
+    typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
+    typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+    const int C = 4 * G;
+    auto load4 = [&](int64_t q, i4u &c4, f4u &v4) {
+      const int64_t a = q + 4 * lig;
+      if (a + 3 < nnz) {
+        c4 = __builtin_nontemporal_load(reinterpret_cast<const i4u *>(col + a));
+        v4 = __builtin_nontemporal_load(reinterpret_cast<const f4u *>(val + a));
+      } else {
+        c4 = i4u{0, 0, 0, 0};
+        v4 = f4u{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (a + i < nnz) {
+            c4[i] = col[a + i];
+            v4[i] = val[a + i];
+          }
+      }
+    };
+    int64_t p = beg + int64_t(first) * C;
+    if (p >= end) return;
+    i4u c4, nc4 = {0, 0, 0, 0};
+    f4u v4, nv4 = {0.f, 0.f, 0.f, 0.f};
+    load4(p, c4, v4);
+    for (; p < end; p += int64_t(stride) * C) {
+      const int cnt = int(min<int64_t>(C, end - p));
+      const int64_t pn = p + int64_t(stride) * C;
+      if (PREFETCH && pn < end) load4(pn, nc4, nv4);
+      for (int t = 0; t < cnt; t += 8) {
+        int32_t j[8];
+        float sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int src = ((t + u) >> 2) & (G - 1);
+          j[u] = __shfl(c4[u & 3], src, G);
+          sv[u] = (t + u < cnt) ? __shfl(v4[u & 3], src, G) : 0.f;
+        }
+        if (col_ok) {
+          float x[8][VEC];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t + u < cnt) VecIO<TU, VEC>::load(U + int64_t(j[u]) * ldu + c0, x[u]);
+            else
+#pragma unroll
+              for (int v = 0; v < VEC; ++v) x[u][v] = 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(sv[u], x[u][v], acc[v]);
+        }
+      }
+      if (PREFETCH) {
+        c4 = nc4;
+        v4 = nv4;
+      } else if (pn < end) {
+        load4(pn, c4, v4);
+      }
+    }
+  }
+
   // The same sum with every load unconditional (no exec-mask branches):
   // (col, val) indices are clamped into the row, and the neighbour rows of a
   // partial batch of 8 re-read the batch's first row, their terms masked off
@@ -190,7 +266,7 @@ struct XcdRows {
 // share its L2) and the ranges carry equal work.
 template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_light(
-    XcdRows xr, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    XcdRows xr, int64_t nnz, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
     const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
     int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
@@ -212,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
       if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
-      else S::gather(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
+      else S::template gather4<false>(col, val, U, ldu, beg, end, nnz, G, lig, 0, 1, c0, col_ok, acc);
       if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
     }
   }
@@ -225,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
 
 template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_medium(
-    int64_t n_rows, const int32_t *__restrict__ rows, int k, int G, int lgG,
+    int64_t n_rows, const int32_t *__restrict__ rows, int64_t nnz, int k, int G, int lgG,
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col,
     const float *__restrict__ val, const float *__restrict__ diag, const TU *__restrict__ U,
     int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O, int64_t ldo, Coef cf,
@@ -246,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
     if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
-    else S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+    else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
     for (int off = G; off < 64; off <<= 1)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
@@ -261,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
 
 template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
 __global__ __launch_bounds__(kBlock) void spmm_heavy(
-    const int32_t *__restrict__ rows, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
+    const int32_t *__restrict__ rows, int64_t nnz, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
     const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
     const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
     int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
@@ -278,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void spmm_heavy(
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
   if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
-  else S::gather(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+  else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
   __syncthreads();
@@ -364,12 +440,12 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     const dim3 grid = dim3(unsigned(g.light_blocks), unsigned(g.ytiles));
     if constexpr (VEC == 4) {
       if (straight)
-        hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, true>), grid, dim3(kBlock), 0, s, g.xr, int(k),
+        hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, true>), grid, dim3(kBlock), 0, s, g.xr, L->nnz, int(k),
                            g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
                            cf, a.dotw, a.lddw, part);
     }
     if (!straight)
-      hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, false>), grid, dim3(kBlock), 0, s, g.xr, int(k),
+      hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, false>), grid, dim3(kBlock), 0, s, g.xr, L->nnz, int(k),
                          g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
                          cf, a.dotw, a.lddw, part);
     SPED_CHECK_HIP(hipGetLastError());
@@ -379,8 +455,8 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     const dim3 grid = dim3(unsigned(g.medium_blocks), unsigned(g.ytiles));
 #define SPED_MEDIUM(ST)                                                                                    \
   hipLaunchKernelGGL((spmm_medium<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s, L->n_medium,      \
-                     L->bins, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, \
-                     O, a.ldo, cf, a.dotw, a.lddw, part)
+                     L->bins, L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu,     \
+                     V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
     if constexpr (VEC == 4) {
       if (straight) SPED_MEDIUM(true);
     }
@@ -393,8 +469,8 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
 #define SPED_HEAVY(ST)                                                                                     \
   hipLaunchKernelGGL((spmm_heavy<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s,                    \
-                     L->bins + L->n_medium, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U,    \
-                     a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
+                     L->bins + L->n_medium, L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val,        \
+                     L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
     if constexpr (VEC == 4) {
       if (straight) SPED_HEAVY(true);
     }
