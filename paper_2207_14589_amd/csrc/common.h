@@ -202,11 +202,6 @@ struct VecNT<bf16_t, 4> {
   }
 };
 
-template <typename T>
-__device__ inline T ld_stream(const T *p) {
-  return __builtin_nontemporal_load(p);
-}
-
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
 // maps hardware block b to logical block (b % 8) * per + b / 8 so that each
 // XCD walks one contiguous stretch of logical blocks (rows), keeping the rows

@@ -12,9 +12,8 @@
 //   heavy   d >  SPED_MEDIUM_MAX: one 256-thread block per row, LDS reduction
 // Each lane owns VEC consecutive columns; G = next_pow2(k / VEC) lanes cover
 // a row of the block (columns beyond 64 VEC are tiled over blockIdx.y).  The
-// G lanes of a group load G consecutive (col, val) pairs with one coalesced
-// access (the next chunk's pairs are fetched while the current chunk's rows are
-// in flight), broadcast them by shuffle, and issue 8 neighbour-row gathers
+// G lanes of a group load 4G consecutive (col, val) pairs with two 16-byte
+// loads per lane, broadcast them by shuffle, and issue 8 neighbour-row gathers
 // before consuming any, so each lane keeps 8 row gathers in flight.
 #include <algorithm>
 #include <type_traits>
@@ -32,62 +31,31 @@ struct Coef {
 
 template <typename TU, typename TV, typename TO, int VEC, bool DOT>
 struct Step {
-  // Accumulate sum_p S_rp U[col_p, c0 .. c0+VEC) over entries [beg, end),
-  // handled in chunks of G by the lanes of one group (lane `lig`).  Chunks
-  // start at beg + first*G and advance by stride*G.
-  __device__ static void gather(const int32_t *__restrict__ col, const float *__restrict__ val,
-                                const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end,
-                                int G, int lig, int first, int stride, int c0, bool col_ok,
-                                float (&acc)[VEC]) {
-    int64_t p = beg + int64_t(first) * G;
-    if (p >= end) return;
-    // the (col, val) chunk for the next round is loaded while this round's
-    // neighbour rows are in flight
-    int32_t myc = 0;
-    float myv = 0.f;
-    if (p + lig < end) {
-      myc = ld_stream(col + p + lig);
-      myv = ld_stream(val + p + lig);
-    }
-    for (; p < end; p += int64_t(stride) * G) {
-      const int cnt = int(min<int64_t>(G, end - p));
-      const int64_t pn = p + int64_t(stride) * G;
-      int32_t nc = 0;
-      float nv = 0.f;
-      if (pn + lig < end) {
-        nc = ld_stream(col + pn + lig);
-        nv = ld_stream(val + pn + lig);
-      }
-      for (int t = 0; t < cnt; t += 8) {
-        int32_t j[8];
-        float sv[8];
+  // 4 consecutive entries of each index array from entry a on, as one 16-byte
+  // load each (dword alignment suffices); entries at or past nnz read as 0.
+  typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
+  typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+  __device__ static void load_idx4(const int32_t *__restrict__ col, const float *__restrict__ val, int64_t a,
+                                   int64_t nnz, i4u &c4, f4u &v4) {
+    if (a + 3 < nnz) {
+      c4 = __builtin_nontemporal_load(reinterpret_cast<const i4u *>(col + a));
+      v4 = __builtin_nontemporal_load(reinterpret_cast<const f4u *>(val + a));
+    } else {
+      c4 = i4u{0, 0, 0, 0};
+      v4 = f4u{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          j[u] = __shfl(myc, (t + u) & (G - 1), G);
-          sv[u] = (t + u < cnt) ? __shfl(myv, (t + u) & (G - 1), G) : 0.f;
+      for (int i = 0; i < 4; ++i)
+        if (a + i < nnz) {
+          c4[i] = col[a + i];
+          v4[i] = val[a + i];
         }
-        if (col_ok) {
-          float x[8][VEC];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            if (t + u < cnt) VecIO<TU, VEC>::load(U + int64_t(j[u]) * ldu + c0, x[u]);
-            else
-#pragma unroll
-              for (int v = 0; v < VEC; ++v) x[u][v] = 0.f;
-          }
-#pragma unroll
-          for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(sv[u], x[u][v], acc[v]);
-        }
-      }
-      myc = nc;
-      myv = nv;
     }
   }
 
-  // The same sum with the (col, val) indices in chunks of 4G entries: each
-  // lane loads 4 consecutive entries of each array with one 16-byte load
+  // Accumulate sum_p S_rp U[col_p, c0 .. c0+VEC) over entries [beg, end),
+  // handled by the G lanes of one group (lane `lig`) in chunks of C = 4G
+  // entries that start at beg + first*C and advance by stride*C.  Each lane
+  // loads 4 consecutive entries of each index array with one 16-byte load
   // (dword-aligned; the last 3 entries of the arrays are read one by one), so a
   // chunk of 4G entries costs two index loads instead of eight.  A load
   // instruction occupies the texture path for about the same time whatever
@@ -101,25 +69,8 @@ struct Step {
   __device__ static void gather4(const int32_t *__restrict__ col, const float *__restrict__ val,
                                  const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end, int64_t nnz,
                                  int G, int lig, int first, int stride, int c0, bool col_ok, float (&acc)[VEC]) {
-    typedef int32_t i4u __attribute__((ext_vector_type(4), aligned(4)));
-    typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
     const int C = 4 * G;
-    auto load4 = [&](int64_t q, i4u &c4, f4u &v4) {
-      const int64_t a = q + 4 * lig;
-      if (a + 3 < nnz) {
-        c4 = __builtin_nontemporal_load(reinterpret_cast<const i4u *>(col + a));
-        v4 = __builtin_nontemporal_load(reinterpret_cast<const f4u *>(val + a));
-      } else {
-        c4 = i4u{0, 0, 0, 0};
-        v4 = f4u{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (a + i < nnz) {
-            c4[i] = col[a + i];
-            v4[i] = val[a + i];
-          }
-      }
-    };
+    auto load4 = [&](int64_t q, i4u &c4, f4u &v4) { load_idx4(col, val, q + 4 * lig, nnz, c4, v4); };
     int64_t p = beg + int64_t(first) * C;
     if (p >= end) return;
     i4u c4, nc4 = {0, 0, 0, 0};
@@ -162,36 +113,38 @@ struct Step {
     }
   }
 
-  // The same sum with every load unconditional (no exec-mask branches):
-  // (col, val) indices are clamped into the row, and the neighbour rows of a
-  // partial batch of 8 re-read the batch's first row, their terms masked off
-  // bitwise.  Faster with 16 or more lanes per row (k >= 61 at 4 columns per
-  // lane: 12-17% on bf16 k = 64 blocks), slower with 8 (5-7% at k = 32).
+  // The same sum as gather4 with every neighbour-row load unconditional (no
+  // exec-mask branches): the entries of a partial batch of 8 re-read the
+  // batch's first row and their terms are masked off bitwise (index entries
+  // past the row's end are other rows' valid columns, or 0 past the arrays'
+  // end, so every load stays in bounds).  Faster with 16 or more lanes per row
+  // (k >= 61 at 4 columns per lane: 12-17% on bf16 k = 64 blocks), slower
+  // with 8 (5-7% at k = 32).
+  template <bool PREFETCH>
   __device__ static void gather_straight(const int32_t *__restrict__ col, const float *__restrict__ val,
                                          const TU *__restrict__ U, int64_t ldu, int64_t beg, int64_t end,
-                                         int G, int lig, int first, int stride, int c0, bool col_ok,
+                                         int64_t nnz, int G, int lig, int first, int stride, int c0, bool col_ok,
                                          float (&acc)[VEC]) {
-    int64_t p = beg + int64_t(first) * G;
+    const int C = 4 * G;
+    auto load4 = [&](int64_t q, i4u &c4, f4u &v4) { load_idx4(col, val, q + 4 * lig, nnz, c4, v4); };
+    int64_t p = beg + int64_t(first) * C;
     if (p >= end) return;
-    int32_t myc = ld_stream(col + min(p + lig, end - 1));
-    float myv = ld_stream(val + min(p + lig, end - 1));
-    for (; p < end; p += int64_t(stride) * G) {
-      const int cnt = int(min<int64_t>(G, end - p));
-      const int64_t pn = p + int64_t(stride) * G;
-      int32_t nc = 0;
-      float nv = 0.f;
-      if (pn < end) {  // uniform over the group
-        nc = ld_stream(col + min(pn + lig, end - 1));
-        nv = ld_stream(val + min(pn + lig, end - 1));
-      }
+    i4u c4, nc4 = {0, 0, 0, 0};
+    f4u v4, nv4 = {0.f, 0.f, 0.f, 0.f};
+    load4(p, c4, v4);
+    for (; p < end; p += int64_t(stride) * C) {
+      const int cnt = int(min<int64_t>(C, end - p));
+      const int64_t pn = p + int64_t(stride) * C;
+      if (PREFETCH && pn < end) load4(pn, nc4, nv4);
       for (int t = 0; t < cnt; t += 8) {
         int32_t j[8];
         float sv[8];
         uint32_t keep[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          j[u] = __shfl(myc, (t + u) & (G - 1), G);
-          sv[u] = __shfl(myv, (t + u) & (G - 1), G);
+          const int src = ((t + u) >> 2) & (G - 1);
+          j[u] = __shfl(c4[u & 3], src, G);
+          sv[u] = __shfl(v4[u & 3], src, G);
           keep[u] = (t + u < cnt) ? 0xffffffffu : 0u;
         }
         if (col_ok) {
@@ -209,8 +162,12 @@ struct Step {
                             __uint_as_float(__float_as_uint(x[u][v]) & keep[u]), acc[v]);
         }
       }
-      myc = nc;
-      myv = nv;
+      if (PREFETCH) {
+        c4 = nc4;
+        v4 = nv4;
+      } else if (pn < end) {
+        load4(pn, c4, v4);
+      }
     }
   }
 
@@ -287,7 +244,8 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
       float acc[VEC];
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-      if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, 0, 1, c0, col_ok, acc);
+      if (STRAIGHT)
+        S::template gather_straight<false>(col, val, U, ldu, beg, end, nnz, G, lig, 0, 1, c0, col_ok, acc);
       else S::template gather4<false>(col, val, U, ldu, beg, end, nnz, G, lig, 0, 1, c0, col_ok, acc);
       if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
     }
@@ -321,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
     float acc[VEC];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-    if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+    if (STRAIGHT)
+      S::template gather_straight<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
     else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
     for (int off = G; off < 64; off <<= 1)
 #pragma unroll
@@ -353,7 +312,8 @@ __global__ __launch_bounds__(kBlock) void spmm_heavy(
   float acc[VEC];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-  if (STRAIGHT) S::gather_straight(col, val, U, ldu, beg, end, G, lig, sub, nsub, c0, col_ok, acc);
+  if (STRAIGHT)
+    S::template gather_straight<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
   else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
