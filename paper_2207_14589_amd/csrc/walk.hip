@@ -168,6 +168,14 @@ __device__ inline void gather_weighted_rows(const TX *__restrict__ X, int64_t ld
 // of those walks at once, the X row of the node each walk just left (every
 // lane its VEC columns) and adds them into the row's sum in walk order.  All
 // walks of a row meet in the same registers: one store per row, no atomics.
+// LDS the importance-walk launch reserves (and leaves unused) so that at most
+// 3 of its 256-thread blocks share a CU (160 KB of LDS each): fewer walks in
+// flight keep more of the active neighbourhoods' entry records and rows in
+// cache.  On a clustered 1e6-node SBM this is 4% faster than the 4 blocks the
+// registers allow; on a power-law graph with scattered communities it makes
+// no difference.
+constexpr int kWalkLdsReserve = 48 * 1024;
+
 template <typename TX, typename TY, int VEC>
 __global__ __launch_bounds__(kBlock) void walk_importance_kernel(
     int64_t n, int64_t nb, int k, int G, int lgG, Graph g, int ell, const TX *__restrict__ X, int64_t ldx,
@@ -491,9 +499,10 @@ sped_status launch_is(const sped_csr *L, int64_t k, const void *X, int64_t ldx, 
   const int64_t rows_per_block = kBlock >> lgG;
   const int64_t nb = (L->n + rows_per_block - 1) / rows_per_block;
   const dim3 grid = dim3(unsigned(xcd_padded_grid(nb)), unsigned(ytiles));
-#define SPED_IS(V)                                                                                      \
-  hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), 0, s, L->n, nb, int(k), G, lgG, g, \
-                     ell, static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, k0, k1, ctr, cf)
+#define SPED_IS(V)                                                                                     \
+  hipLaunchKernelGGL((walk_importance_kernel<TX, TY, V>), grid, dim3(kBlock), kWalkLdsReserve, s, L->n, nb, \
+                     int(k), G, lgG, g, ell, static_cast<const TX *>(X), ldx, static_cast<TY *>(Y), ldy, walks, \
+                     k0, k1, ctr, cf)
   if (vec == 4) SPED_IS(4);
   else if (vec == 2) SPED_IS(2);
   else SPED_IS(1);
