@@ -26,8 +26,25 @@ __device__ inline double load_as_double<float>(const float *p) { return double(*
 template <>
 __device__ inline double load_as_double<bf16_t>(const bf16_t *p) { return double(bf16_to_f32(*p)); }
 
+// Elements c and c + 1 with one load (p aligned to two elements).
+template <typename T>
+__device__ inline void load2_as_double(const T *p, double &x0, double &x1);
+template <>
+__device__ inline void load2_as_double<float>(const float *p, double &x0, double &x1) {
+  const float2 v = *reinterpret_cast<const float2 *>(p);
+  x0 = double(v.x);
+  x1 = double(v.y);
+}
+template <>
+__device__ inline void load2_as_double<bf16_t>(const bf16_t *p, double &x0, double &x1) {
+  const uint32_t v = *reinterpret_cast<const uint32_t *>(p);
+  x0 = double(bf16_to_f32(bf16_t(v & 0xffffu)));
+  x1 = double(bf16_to_f32(bf16_t(v >> 16)));
+}
+
 // Operand loaders of the Gram kernels: element (row, c) of the left and right
-// factors, converted to float64.
+// factors, converted to float64; a2/b2 give elements c and c + 1 (c even,
+// rows aligned to two elements).
 template <typename T1, typename T2>
 struct PlainLoad {
   const T1 *A;
@@ -36,6 +53,8 @@ struct PlainLoad {
   int64_t ldb;
   __device__ double a(int64_t r, int c) const { return load_as_double(A + r * lda + c); }
   __device__ double b(int64_t r, int c) const { return load_as_double(B + r * ldb + c); }
+  __device__ void a2(int64_t r, int c, double &x0, double &x1) const { load2_as_double(A + r * lda + c, x0, x1); }
+  __device__ void b2(int64_t r, int c, double &x0, double &x1) const { load2_as_double(B + r * ldb + c, x0, x1); }
 };
 
 // Residual block R = Z - Q diag(theta) formed on the fly (both factors are R).
@@ -49,6 +68,14 @@ struct ResidLoad {
     return double(Z[r * ld + c]) - theta[c] * load_as_double(Q + r * ld + c);
   }
   __device__ double b(int64_t r, int c) const { return a(r, c); }
+  __device__ void a2(int64_t r, int c, double &x0, double &x1) const {
+    double z0, z1, q0, q1;
+    load2_as_double(Z + r * ld + c, z0, z1);
+    load2_as_double(Q + r * ld + c, q0, q1);
+    x0 = z0 - theta[c] * q0;
+    x1 = z1 - theta[c + 1] * q1;
+  }
+  __device__ void b2(int64_t r, int c, double &x0, double &x1) const { a2(r, c, x0, x1); }
 };
 
 // Wide Gram (a width above 32, both <= 128).  The block has NW wavefronts;
@@ -240,6 +267,108 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
     const int i = idx / kb, j = idx - i * kb;
     const int pi = i / 16, qj = j / 16;
     out[idx] = (SYM && pi > qj) ? red[j * W + i] : red[i * W + j];
+  }
+}
+
+// Narrow Gram with column pairs (both widths even and in (16, 32], rows
+// aligned to two elements): lane (li, lk) loads columns 2li and 2li + 1 of row
+// row + 4u + lk with one load, so 16 lanes read a whole row and a load
+// instruction covers 4 rows (half the instructions of the one-column form).
+// Component v of the pair feeds MFMA operand v: the tile of MFMA pair
+// (v1, v2) holds G[2i + v1][2j + v2] (i, j the tile's row and column), the
+// four tiles together the whole 32 x 32 block.  With SYM the tile (1, 0) is
+// the transpose of (0, 1) and is not formed.  Otherwise as the one-column
+// form: unconditional loads, two alternating fragment buffers, 16 wavefronts
+// adding their tiles into LDS in wavefront order, one partial per block.
+template <typename LD, bool SYM>
+__global__ __launch_bounds__(kNarrowBlock) void gram_pair_kernel(int64_t n, int ka, int kb, LD ld,
+                                                                 int64_t rows_per_block,
+                                                                 double *__restrict__ partials) {
+  constexpr int KU = 4;
+  constexpr int NW = kNarrowBlock / 64;
+  constexpr int W = 32;
+  __shared__ double red[W * W];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  double4_t acc[2][2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = double4_t{0.0, 0.0, 0.0, 0.0};
+  const int64_t r_begin = int64_t(blockIdx.x) * rows_per_block;
+  const int64_t r_end = min(n, r_begin + rows_per_block);
+  // pairs past the width re-read the last pair (they feed only output entries
+  // that are never written)
+  const int ca = 2 * min(li, ka / 2 - 1), cb = 2 * min(li, kb / 2 - 1);
+  struct Frag {
+    double a[KU][2], b[KU][2];
+  };
+  auto load = [&](int64_t r, Frag &f) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int64_t row = r + 4 * u + lk;
+      const bool rok = row < r_end;
+      const int64_t rc = rok ? row : r_begin;
+      const double rm = rok ? 1.0 : 0.0;
+      ld.a2(rc, ca, f.a[u][0], f.a[u][1]);
+      f.a[u][0] *= rm;
+      f.a[u][1] *= rm;
+      if (!SYM) {
+        ld.b2(rc, cb, f.b[u][0], f.b[u][1]);
+        f.b[u][0] *= rm;
+        f.b[u][1] *= rm;
+      }
+    }
+  };
+  auto mma = [&](const Frag &f) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (!SYM || p <= q)
+            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[u][p], SYM ? f.a[u][q] : f.b[u][q], acc[p][q], 0,
+                                                             0, 0);
+  };
+  constexpr int64_t STRIDE = 4 * KU * NW;
+  const int64_t first = r_begin + 4 * KU * wave;
+  if (first < r_end) {
+    Frag f0, f1;
+    load(first, f0);
+    for (int64_t r = first; r < r_end; r += 2 * STRIDE) {
+      load(r + STRIDE, f1);  // rows past the end load as zeros
+      mma(f0);
+      load(r + 2 * STRIDE, f0);
+      mma(f1);
+    }
+  }
+  // accumulator slot -> (row, column) of the tile, read off the matrix core
+  const double4_t zero4 = double4_t{0.0, 0.0, 0.0, 0.0};
+  const double4_t rowid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? double(li) : 0.0, lk == 0 ? 1.0 : 0.0,
+                                                               zero4, 0, 0, 0);
+  const double4_t colid = __builtin_amdgcn_mfma_f64_16x16x4f64(lk == 0 ? 1.0 : 0.0, lk == 0 ? double(li) : 0.0,
+                                                               zero4, 0, 0, 0);
+  for (int w = 0; w < NW; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (!SYM || p <= q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = 2 * int(rowid[r]) + p, j = 2 * int(colid[r]) + q;
+              red[i * W + j] = (w == 0 ? 0.0 : red[i * W + j]) + acc[p][q][r];
+            }
+    }
+    __syncthreads();
+  }
+  double *out = partials + int64_t(blockIdx.x) * ka * kb;
+  for (int idx = threadIdx.x; idx < ka * kb; idx += kNarrowBlock) {
+    const int i = idx / kb, j = idx - i * kb;
+    out[idx] = (SYM && (i & 1) && !(j & 1)) ? red[j * W + i] : red[i * W + j];
   }
 }
 
@@ -516,8 +645,15 @@ sped_status launch_gram_narrow_t(int64_t n, int ka, int kb, const LD &ld, double
 
 template <typename LD, bool SYM>
 sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
-                             hipStream_t s) {
+                             hipStream_t s, bool pairs) {
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
+  // column pairs fill the four 16 x 16 tiles only when both widths exceed 16
+  if (p.narrow && pairs && ka % 2 == 0 && kb % 2 == 0 && ka > 16 && kb > 16) {
+    hipLaunchKernelGGL((gram_pair_kernel<LD, SYM>), dim3(p.nblocks), dim3(kNarrowBlock), 0, s, n, ka, kb, ld,
+                       p.rows_per_block, partials);
+    SPED_CHECK_HIP(hipGetLastError());
+    return SPED_OK;
+  }
   if (p.narrow) {
     if (TA == 1 && TB == 1) return launch_gram_narrow_t<LD, 1, 1, SYM>(n, ka, kb, ld, partials, p, s);
     if (TA == 1 && TB == 2) return launch_gram_narrow_t<LD, 1, 2, SYM>(n, ka, kb, ld, partials, p, s);
@@ -535,7 +671,10 @@ template <typename T1, typename T2, bool SYM>
 sped_status launch_gram_plain(int64_t n, int ka, int kb, const void *A, int64_t lda, const void *B, int64_t ldb,
                               double *partials, const GramPlan &p, hipStream_t s) {
   PlainLoad<T1, T2> ld{static_cast<const T1 *>(A), lda, static_cast<const T2 *>(B), ldb};
-  return launch_gram_maxt<PlainLoad<T1, T2>, SYM>(n, ka, kb, ld, partials, p, s);
+  // column pairs need every row to start on a two-element boundary
+  const bool pairs = lda % 2 == 0 && ldb % 2 == 0 && reinterpret_cast<uintptr_t>(A) % (2 * sizeof(T1)) == 0 &&
+                     reinterpret_cast<uintptr_t>(B) % (2 * sizeof(T2)) == 0;
+  return launch_gram_maxt<PlainLoad<T1, T2>, SYM>(n, ka, kb, ld, partials, p, s, pairs);
 }
 
 // From G = R^T R (k x k): resid[i] = sqrt(G_ii) for i < k, and
@@ -624,13 +763,16 @@ sped_status launch_resid(int64_t n, int k, int kn, const float *Z, const void *Q
                          hipStream_t s) {
   if (k < 1 || k > kMaxK || kn < 1 || kn > k) return fail(SPED_E_UNSUPPORTED, "resid width outside [1, 128]");
   const GramPlan plan = gram_plan(n, k, k, true);
+  const size_t qsize = tq == SPED_F32 ? sizeof(float) : sizeof(bf16_t);
+  const bool pairs = ld % 2 == 0 && reinterpret_cast<uintptr_t>(Z) % (2 * sizeof(float)) == 0 &&
+                     reinterpret_cast<uintptr_t>(Q) % (2 * qsize) == 0;
   sped_status st;
   if (tq == SPED_F32) {
     ResidLoad<float> ld_{Z, static_cast<const float *>(Q), ld, theta};
-    st = launch_gram_maxt<ResidLoad<float>, true>(n, k, k, ld_, partials, plan, s);
+    st = launch_gram_maxt<ResidLoad<float>, true>(n, k, k, ld_, partials, plan, s, pairs);
   } else {
     ResidLoad<bf16_t> ld_{Z, static_cast<const bf16_t *>(Q), ld, theta};
-    st = launch_gram_maxt<ResidLoad<bf16_t>, true>(n, k, k, ld_, partials, plan, s);
+    st = launch_gram_maxt<ResidLoad<bf16_t>, true>(n, k, k, ld_, partials, plan, s, pairs);
   }
   if (st != SPED_OK) return st;
   SPED_TRY(launch_sum_partials(partials, plan.nparts, int64_t(k) * k, G, false, s));

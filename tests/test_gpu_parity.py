@@ -415,11 +415,13 @@ def test_stochastic_unbiased(sped):
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
-@pytest.mark.parametrize("ka,kb", [(20, 36), (56, 56), (61, 128), (100, 7), (128, 128)])
+@pytest.mark.parametrize("ka,kb", [(20, 36), (56, 56), (61, 128), (100, 7), (128, 128), (32, 32), (18, 30),
+                                   (31, 32), (14, 24)])
 def test_gram_parity(sped, dt, ka, kb):
     """G = A^T B against float64 numpy on the same (rounded) operands: narrow
-    (both widths <= 32), wide with 4 or 8 wavefronts per block, odd widths and
-    a ragged row count; the symmetric form is exactly symmetric and the
+    (both widths <= 32; column pairs when both are even and above 16, else one
+    column per lane), wide with 4 or 8 wavefronts per block, odd widths and a
+    ragged row count; the symmetric form is exactly symmetric and the
     reduction order is fixed."""
     _say(f"gram {dt} {ka}x{kb}")
     g = np.random.default_rng(ka * 1000 + kb)
@@ -439,6 +441,27 @@ def test_gram_parity(sped, dt, ka, kb):
         np.testing.assert_array_equal(S, S.T)
     G2 = sped.gram(Ad, Bd).cpu().numpy()
     np.testing.assert_array_equal(G, G2)   # fixed reduction order
+
+
+@pytest.mark.parametrize("ld,k,off", [(40, 30, 2), (40, 30, 1), (33, 30, 2)])
+def test_gram_strided_operands(sped, ld, k, off):
+    """Operands that are column slices of wider blocks: an even leading
+    dimension with pair-aligned starts keeps the column-pair Gram; an odd
+    start or an odd leading dimension (rows not aligned to two elements)
+    takes the one-column form; all match float64 numpy."""
+    _say(f"gram strided ld={ld} k={k} off={off}")
+    g = np.random.default_rng(ld * 100 + k + off)
+    n = 50_001
+    W = torch.from_numpy(g.standard_normal((n, ld)).astype(np.float32)).cuda()
+    A, B = W[:, :k], W[:, off:k + off]
+    An = A.cpu().numpy().astype(np.float64)
+    Bn = B.cpu().numpy().astype(np.float64)
+    G = sped.gram(A, B).cpu().numpy()
+    Gr = An.T @ Bn
+    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+    S = sped.gram(A).cpu().numpy()
+    np.testing.assert_allclose(S, An.T @ An, rtol=1e-12, atol=1e-12 * n)
+    np.testing.assert_array_equal(S, S.T)
 
 
 @pytest.mark.parametrize("k", [14, 56, 57, 96])
