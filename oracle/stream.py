@@ -1,0 +1,57 @@
+"""Edge-minibatch products with the Laplacian (oracle; test infrastructure only).
+
+The Laplacian is a sum of rank-one terms, one per edge vector (Sec. 2:
+L = X^T X = sum_e x_e x_e^T, weighted X^T W X; Sec. 4.1 normalised form with
+x_e scaled by s_i = d_i^{-1/2} at each endpoint).  When the edge list does not
+fit in memory, a solver sees batches of edge vectors (the eigengap discussion
+of Sec. 3 and the conclusion): a batch B gives sum_{e in B} x_e x_e^T V, and
+a uniformly drawn batch of b of the m edges, scaled by m / b, has expectation
+L V.
+
+Per edge e = (i, j) with weight w (i != j; a self-loop has x_e = 0):
+    x_e = sqrt(w) (s_i e_i - s_j e_j),
+    x_e x_e^T V adds  w s_i (s_i V_i - s_j V_j)  to row i
+               and   -w s_j (s_i V_i - s_j V_j)  to row j.
+The sign of x_e (which endpoint gets +1) does not change x_e x_e^T.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+COMBINATORIAL = "combinatorial"
+SYM_NORMALIZED = "sym"
+
+
+def node_scales(n, src, dst, w=None, kind=SYM_NORMALIZED):
+    """(degree, scale): d_i = sum of the weights of the non-loop edges at i
+    (repeats add), s_i = d_i^{-1/2} (0 when d_i = 0) for the normalised
+    Laplacian, 1 for the combinatorial one."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    wt = np.ones(len(src)) if w is None else np.asarray(w, dtype=np.float64)
+    keep = src != dst
+    d = np.zeros(n)
+    np.add.at(d, src[keep], wt[keep])
+    np.add.at(d, dst[keep], wt[keep])
+    if kind == COMBINATORIAL:
+        return d, np.ones(n)
+    s = np.zeros(n)
+    pos = d > 0
+    s[pos] = 1.0 / np.sqrt(d[pos])
+    return d, s
+
+
+def edge_batch_apply(n, src, dst, w, scale, V):
+    """sum over the batch's edges of x_e x_e^T V (float64), rows as above."""
+    V = np.asarray(V, dtype=np.float64)
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    wt = np.ones(len(src)) if w is None else np.asarray(w, dtype=np.float64)
+    s = np.asarray(scale, dtype=np.float64)
+    keep = src != dst
+    i, j, wt = src[keep], dst[keep], wt[keep]
+    diff = s[i, None] * V[i] - s[j, None] * V[j]
+    Y = np.zeros((n, V.shape[1]))
+    np.add.at(Y, i, (wt * s[i])[:, None] * diff)
+    np.add.at(Y, j, -(wt * s[j])[:, None] * diff)
+    return Y

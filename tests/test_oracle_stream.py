@@ -1,0 +1,92 @@
+"""Pins for the edge-minibatch oracle (oracle/stream.py) -- no GPU.
+
+The sum over all edges of x_e x_e^T V must be L V with L built from the
+incidence matrix by its definition (Sec. 2: L = X^T X, weighted X^T W X;
+Sec. 4.1: columns scaled by s_i = d_i^{-1/2}); degrees are checked on a
+graph small enough to add up by hand."""
+import numpy as np
+import pytest
+
+from oracle import laplacian as olap
+from oracle import stream as ost
+
+
+def incidence_laplacian(n, src, dst, w, scale):
+    """X^T X with one row per edge: +sqrt(w) s_i at min(i, j), -sqrt(w) s_j at
+    max(i, j); a self-loop's row is zero."""
+    rows = []
+    for i, j, wt in zip(src, dst, w):
+        x = np.zeros(n)
+        if i != j:
+            a, b = min(i, j), max(i, j)
+            x[a] = np.sqrt(wt) * scale[a]
+            x[b] = -np.sqrt(wt) * scale[b]
+        rows.append(x)
+    X = np.array(rows)
+    return X.T @ X
+
+
+def small_graph():
+    # repeats (0, 1) twice and (2, 3) in both directions, a self-loop at 4,
+    # node 5 isolated
+    src = np.array([0, 1, 0, 2, 3, 4, 1, 3])
+    dst = np.array([1, 0, 2, 3, 2, 4, 3, 0])
+    w = np.array([1.0, 2.0, 0.5, 3.0, 1.5, 7.0, 0.25, 4.0])
+    return 6, src, dst, w
+
+
+def test_degrees_by_hand():
+    n, src, dst, w = small_graph()
+    d, s = ost.node_scales(n, src, dst, w, kind=ost.SYM_NORMALIZED)
+    # node 0: 1 + 2 + 0.5 + 4; node 1: 1 + 2 + 0.25; node 2: 0.5 + 3 + 1.5;
+    # node 3: 3 + 1.5 + 0.25 + 4; node 4: only its self-loop; node 5: none
+    np.testing.assert_array_equal(d, [7.5, 3.25, 5.0, 8.75, 0.0, 0.0])
+    np.testing.assert_allclose(s[:4], 1.0 / np.sqrt([7.5, 3.25, 5.0, 8.75]), rtol=1e-15)
+    assert s[4] == 0.0 and s[5] == 0.0
+    d2, s2 = ost.node_scales(n, src, dst, w, kind=ost.COMBINATORIAL)
+    np.testing.assert_array_equal(d2, d)
+    np.testing.assert_array_equal(s2, np.ones(n))
+
+
+@pytest.mark.parametrize("kind", [ost.COMBINATORIAL, ost.SYM_NORMALIZED])
+def test_full_pass_is_incidence_laplacian(kind):
+    n, src, dst, w = small_graph()
+    _, s = ost.node_scales(n, src, dst, w, kind=kind)
+    V = np.random.default_rng(1).standard_normal((n, 3))
+    Y = ost.edge_batch_apply(n, src, dst, w, s, V)
+    L = incidence_laplacian(n, src, dst, w, s)
+    np.testing.assert_allclose(Y, L @ V, rtol=1e-13, atol=1e-13)
+    # L 1 = 0 for the combinatorial form; L D^{1/2} 1 = 0 for the normalised one
+    d, _ = ost.node_scales(n, src, dst, w, kind=kind)
+    null = np.ones((n, 1)) if kind == ost.COMBINATORIAL else np.sqrt(d)[:, None]
+    np.testing.assert_allclose(ost.edge_batch_apply(n, src, dst, w, s, null), 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_full_pass_matches_csr_oracle(kind):
+    g = np.random.default_rng(7)
+    n, m = 300, 2500
+    src = g.integers(0, n, m)
+    dst = g.integers(0, n, m)
+    w = g.uniform(0.05, 1.0, m)
+    ref = olap.laplacian(n, src, dst, w=w, kind=kind)
+    _, s = ost.node_scales(n, src, dst, w, kind=kind)
+    np.testing.assert_allclose(s, ref.scale, rtol=1e-14)
+    V = g.standard_normal((n, 5))
+    np.testing.assert_allclose(ost.edge_batch_apply(n, src, dst, w, s, V), ref.L @ V, rtol=1e-12, atol=1e-12)
+    # the endpoint order of an edge does not matter
+    np.testing.assert_allclose(ost.edge_batch_apply(n, dst, src, w, s, V), ref.L @ V, rtol=1e-12, atol=1e-12)
+
+
+def test_batches_add_up_and_single_edge_mean_is_unbiased():
+    n, src, dst, w = small_graph()
+    _, s = ost.node_scales(n, src, dst, w)
+    V = np.random.default_rng(3).standard_normal((n, 2))
+    full = ost.edge_batch_apply(n, src, dst, w, s, V)
+    parts = sum(ost.edge_batch_apply(n, src[a:a + 3], dst[a:a + 3], w[a:a + 3], s, V) for a in range(0, 8, 3))
+    np.testing.assert_allclose(parts, full, rtol=1e-14, atol=1e-14)
+    # a batch of one uniformly drawn edge, scaled by m: its mean over the m
+    # equally likely draws is the full product
+    m = len(src)
+    mean = sum(m * ost.edge_batch_apply(n, src[e:e + 1], dst[e:e + 1], w[e:e + 1], s, V) for e in range(m)) / m
+    np.testing.assert_allclose(mean, full, rtol=1e-13, atol=1e-13)
