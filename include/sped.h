@@ -427,6 +427,55 @@ sped_status sped_cluster_embed(const void *V, int64_t n, int64_t k, int64_t ldv,
                                size_t *ws_bytes, sped_stream_t stream);
 
 /*
+ * Edge-batch products, for graphs whose edge list is not resident on the
+ * device (Sec. 3: when the data cannot be held in memory, a solver sees
+ * batches of edge vectors x_e; the conclusion's stochastic model).  L is the
+ * sum of x_e x_e^T over the edges (Sec. 2, weighted X^T W X), x_e =
+ * sqrt(w) (s_i e_i - s_j e_j) with s the node scales (Sec. 4.1; all ones for
+ * the combinatorial Laplacian), so a batch B adds, per edge e = (i, j, w),
+ *   w s_i (s_i X_i - s_j X_j) to row i and -w s_j (s_i X_i - s_j X_j) to row j.
+ * Self-loops add nothing; repeated edges add their weights.  A uniformly drawn
+ * batch of b of the m edges, scaled by alpha = m / b, estimates L X without
+ * bias; all m edges with alpha = 1 give L X.  Rows are summed with float32
+ * atomics, so the order of the additions (and the last bits) varies from run
+ * to run.  Y is float32; X is F32 or BF16, n x k with leading dimension ldx;
+ * Y must not be X.
+ */
+
+/* sped_edge_apply -- Y += alpha sum_{e in batch} x_e x_e^T X for a batch of m
+ * DEVICE edges (src, dst int32 [m]; w float [m] or NULL for ones; scale
+ * DEVICE float [n] or NULL for ones).  An edge with an endpoint outside
+ * [0, n) or a weight that is not finite and > 0 is skipped and counted in
+ * *invalid (DEVICE uint64, added to; may be NULL).  Asynchronous. */
+sped_status sped_edge_apply(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const float *w,
+                            const float *scale, int64_t k, const void *X, int64_t ldx, int32_t xdt, float *Y,
+                            int64_t ldy, float alpha, unsigned long long *invalid, sped_stream_t stream);
+
+/* sped_stream_node_scales -- the weighted degrees d (DEVICE double [n]) and
+ * node scales s (DEVICE float [n]: d^{-1/2}, 0 for d = 0, under
+ * SPED_LAP_SYM_NORMALIZED; 1 under SPED_LAP_COMBINATORIAL) of the graph whose
+ * m edges are HOST arrays src_h, dst_h (int32) and w_h (float, or NULL for
+ * ones), read in batches of `batch` edges (pinned host memory lets the copies
+ * overlap the kernels).  Workspace: two staging batches.  Synchronises
+ * `stream`; the host arrays may be released on return.  Invalid edges (as
+ * above) are skipped and make the call return SPED_E_INVALID. */
+sped_status sped_stream_node_scales(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h,
+                                    const float *w_h, int32_t kind, int64_t batch, double *degree, float *scale,
+                                    void *ws, size_t *ws_bytes, sped_stream_t stream);
+
+/* sped_stream_laplacian_apply -- Y = alpha sum_e x_e x_e^T X (accumulate = 0)
+ * or Y += that (accumulate != 0) over the m HOST edges src_h, dst_h, w_h,
+ * streamed in batches of `batch` edges: the copy of each batch overlaps the
+ * previous batch's kernel.  scale: DEVICE float [n] (from
+ * sped_stream_node_scales) or NULL for the combinatorial Laplacian.
+ * Workspace: two staging batches.  Synchronises `stream`.  Invalid edges are
+ * skipped and make the call return SPED_E_INVALID. */
+sped_status sped_stream_laplacian_apply(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h,
+                                        const float *w_h, const float *scale, int64_t k, const void *X, int64_t ldx,
+                                        int32_t xdt, float *Y, int64_t ldy, float alpha, int32_t accumulate,
+                                        int64_t batch, void *ws, size_t *ws_bytes, sped_stream_t stream);
+
+/*
  * sped_stream_copy -- dst <- src, `bytes` bytes (multiple of 16, 16-byte
  * aligned DEVICE pointers): a plain streaming copy used to calibrate the
  * chip's achievable HBM bandwidth and its memory counters.

@@ -76,6 +76,12 @@ SIGNATURES = {
                            _P(_c_f64), _P(SolveOpts), _P(SolveStats), _c_vp, _P(_c_sz), _c_vp],
     "sped_cluster_embed": [_c_vp, _c_i64, _c_i64, _c_i64, _c_i32, _c_i32, _c_i32, _c_u64, _c_i32, _c_vp, _c_vp,
                            _c_vp, _P(_c_f64), _P(_c_i32), _c_vp, _P(_c_sz), _c_vp],
+    "sped_edge_apply": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
+                        ctypes.c_float, _c_vp, _c_vp],
+    "sped_stream_node_scales": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_i32, _c_i64, _c_vp, _c_vp, _c_vp,
+                                _P(_c_sz), _c_vp],
+    "sped_stream_laplacian_apply": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32,
+                                    _c_vp, _c_i64, ctypes.c_float, _c_i32, _c_i64, _c_vp, _P(_c_sz), _c_vp],
     "sped_stream_copy": [_c_vp, _c_vp, _c_sz, _c_vp],
     "sped_gather_probe": [_c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp],
     "sped_last_error": [],
@@ -389,6 +395,66 @@ def cluster_embed(V, n_clusters, row_normalize=True, seed=0, max_iters=300, init
              (_ptr(V), n, k, _ld(V), _dt(V), n_clusters, int(bool(row_normalize)), int(seed), max_iters,
               _ptr(init_t), _ptr(labels), _ptr(cent), ctypes.byref(inertia), ctypes.byref(iters)), V.device)
     return labels, cent, inertia.value, iters.value
+
+
+# ------------------------------------------------------- edge-batch products
+def _host_edges(src_h, dst_h, w_h):
+    """Host edge arrays as contiguous CPU tensors (int32, int32, float32 or
+    None); pinned memory lets the library overlap copies with kernels."""
+    def chk(t, dt, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cpu" or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CPU tensor of {dt}")
+        return t
+    src_h = chk(src_h, torch.int32, "src")
+    dst_h = chk(dst_h, torch.int32, "dst")
+    if dst_h.numel() != src_h.numel() or (w_h is not None and w_h.numel() != src_h.numel()):
+        raise ValueError("src, dst and w must have the same length")
+    return src_h, dst_h, (None if w_h is None else chk(w_h, torch.float32, "w"))
+
+
+def edge_apply(n, src, dst, X, w=None, scale=None, alpha=1.0, out=None, invalid=None):
+    """out += alpha sum_e x_e x_e^T X over a batch of DEVICE edges (int32 src,
+    dst; float32 w or None; node scales or None for the combinatorial L).
+    out is float32 n x k (a new zero block when None); invalid is an optional
+    DEVICE int64 counter of skipped edges."""
+    k = X.shape[1]
+    if out is None:
+        out = torch.zeros(n, k, dtype=torch.float32, device=X.device)
+    _check(lib().sped_edge_apply(int(n), src.numel(), _ptr(src), _ptr(dst), _ptr(w), _ptr(scale), k, _ptr(X), _ld(X),
+                                 _dt(X), _ptr(out), _ld(out), float(alpha), _ptr(invalid), _stream(X.device)),
+           "sped_edge_apply")
+    return out
+
+
+def stream_node_scales(n, src_h, dst_h, w_h=None, kind="sym", batch=1 << 22, device="cuda"):
+    """(degree float64, scale float32) DEVICE tensors from a HOST edge list
+    read in batches."""
+    src_h, dst_h, w_h = _host_edges(src_h, dst_h, w_h)
+    kind_i = {"sym": SYM_NORMALIZED, "combinatorial": COMBINATORIAL}[kind] if isinstance(kind, str) else kind
+    dev = torch.device(device)
+    degree = torch.empty(max(int(n), 1), dtype=torch.float64, device=dev)
+    scale = torch.empty(max(int(n), 1), dtype=torch.float32, device=dev)
+    _call_ws(lib().sped_stream_node_scales, "sped_stream_node_scales",
+             (int(n), src_h.numel(), _c_vp(src_h.data_ptr()), _c_vp(dst_h.data_ptr()),
+              _c_vp(w_h.data_ptr() if w_h is not None else None), kind_i, int(batch), _ptr(degree), _ptr(scale)), dev)
+    return degree[: int(n)], scale[: int(n)]
+
+
+def stream_laplacian_apply(n, src_h, dst_h, X, w_h=None, scale=None, alpha=1.0, out=None, accumulate=False,
+                           batch=1 << 22):
+    """alpha sum_e x_e x_e^T X over a HOST edge list streamed in batches
+    (accumulate: added to out).  scale: node scales (DEVICE) or None for the
+    combinatorial Laplacian.  Returns the float32 n x k result."""
+    src_h, dst_h, w_h = _host_edges(src_h, dst_h, w_h)
+    k = X.shape[1]
+    if out is None:
+        out = torch.empty(int(n), k, dtype=torch.float32, device=X.device)
+        accumulate = False
+    _call_ws(lib().sped_stream_laplacian_apply, "sped_stream_laplacian_apply",
+             (int(n), src_h.numel(), _c_vp(src_h.data_ptr()), _c_vp(dst_h.data_ptr()),
+              _c_vp(w_h.data_ptr() if w_h is not None else None), _ptr(scale), k, _ptr(X), _ld(X), _dt(X),
+              _ptr(out), _ld(out), float(alpha), int(bool(accumulate)), int(batch)), X.device)
+    return out
 
 
 def gather_probe(table, iters, scattered, blocks, out):

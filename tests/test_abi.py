@@ -165,3 +165,29 @@ def test_gather_probe_validation(lib):
     assert lib.sped_gather_probe(256, 128, 12, 1, 1, need_out, None) == sped.E_INVALID  # iters not a multiple of 8
     assert lib.sped_gather_probe(256, 128, 8, 1, 0, need_out, None) == sped.E_INVALID   # no blocks
     assert lib.sped_gather_probe(260, 128, 8, 1, 1, need_out, None) == sped.E_INVALID   # misaligned table
+
+
+def test_edge_batch_validation(lib):
+    """Argument checks of the edge-batch entry points run on the host, before
+    any device work; the streamed calls answer a workspace size query."""
+    X, Y, s, d = 4096, 8192, 1024, 2048   # fake, never dereferenced
+    f = lib.sped_edge_apply
+    assert f(10, 5, s, d, None, None, 0, X, 4, sped.F32, Y, 4, 1.0, None, None) == sped.E_INVALID        # k < 1
+    assert f(10, 5, s, d, None, None, 4, X, 3, sped.F32, Y, 4, 1.0, None, None) == sped.E_INVALID        # ldx < k
+    assert f(10, 5, s, d, None, None, 4, X, 4, sped.F64, Y, 4, 1.0, None, None) == sped.E_UNSUPPORTED    # dtype
+    assert f(10, 5, None, d, None, None, 4, X, 4, sped.F32, Y, 4, 1.0, None, None) == sped.E_INVALID     # src NULL
+    assert f(10, 5, s, d, None, None, 4, X, 4, sped.F32, X, 4, 1.0, None, None) == sped.E_INVALID        # Y = X
+    assert f(10, 5, s, d, None, None, 4, X, 4, sped.F32, Y, 4, float("nan"), None, None) == sped.E_INVALID
+    assert f(10, -1, s, d, None, None, 4, X, 4, sped.F32, Y, 4, 1.0, None, None) == sped.E_INVALID       # m < 0
+    need = ctypes.c_size_t(0)
+    g = lib.sped_stream_laplacian_apply
+    assert g(10, 100, s, d, None, None, 4, X, 4, sped.F32, Y, 4, 1.0, 0, 0, None, ctypes.byref(need),
+             None) == sped.E_INVALID                                                                    # batch < 1
+    assert g(10, 100, s, d, None, None, 4, X, 4, sped.F32, Y, 4, 1.0, 0, 64, None, ctypes.byref(need),
+             None) == sped.OK
+    assert need.value >= 2 * 64 * 12   # two staging batches of (src, dst, w)
+    h = lib.sped_stream_node_scales
+    assert h(10, 100, s, d, None, 7, 64, Y, X, None, ctypes.byref(need), None) == sped.E_INVALID         # kind
+    assert h(10, 100, s, d, None, sped.SYM_NORMALIZED, 64, None, X, None, ctypes.byref(need),
+             None) == sped.E_INVALID                                                                    # degree NULL
+    assert h(10, 100, s, d, None, sped.SYM_NORMALIZED, 64, Y, X, None, ctypes.byref(need), None) == sped.OK

@@ -964,3 +964,142 @@ def test_solver_graph_replay_matches_eager(sped, case):
     assert graph.converged == eager.converged
     np.testing.assert_array_equal(graph.evals, eager.evals)
     assert torch.equal(graph.V, eager.V)
+
+
+# ------------------------------------------------------- edge-batch products
+def _pinned(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).pin_memory()
+
+
+@pytest.mark.parametrize("kind", ["sym", "combinatorial"])
+@pytest.mark.parametrize("k,dt,batch", [(32, "f32", 4096), (7, "f32", 1000), (64, "bf16", 7919),
+                                        (300, "f32", 10 ** 6)])
+def test_stream_laplacian_apply_parity(sped, kind, k, dt, batch):
+    """Streamed sum_e x_e x_e^T X over a pinned host edge list (weights,
+    repeats, self-loops, a degree-9000 hub) against the float64 oracle on the
+    same node scales and the same (rounded) X: batches that leave a ragged
+    tail, one batch for everything, 1, 2 and 4 columns per lane, two column
+    tiles; the streamed degrees and scales against the oracle's."""
+    from oracle import stream as ost
+    _say(f"stream apply {kind} k={k} {dt} batch={batch}")
+    n, src, dst, w = mixed_degree_graph()
+    sh, dh, wh = _pinned(src, torch.int32), _pinned(dst, torch.int32), _pinned(w, torch.float32)
+    deg, scale = sped.stream_node_scales(n, sh, dh, wh, kind=kind, batch=batch)
+    okind = ost.SYM_NORMALIZED if kind == "sym" else ost.COMBINATORIAL
+    d_r, s_r = ost.node_scales(n, src, dst, w, kind=okind)
+    np.testing.assert_allclose(deg.cpu().numpy(), d_r, rtol=1e-12)
+    np.testing.assert_allclose(scale.cpu().numpy(), s_r, rtol=2 * U32)
+    tdt = torch.float32 if dt == "f32" else torch.bfloat16
+    X = torch.from_numpy(synth.gaussian_block(n, k, 2).astype(np.float32)).to(tdt).cuda()
+    sc = scale if kind == "sym" else None
+    Y = sped.stream_laplacian_apply(n, sh, dh, X, wh, scale=sc, batch=batch)
+    Xn = X.float().cpu().numpy().astype(np.float64)
+    s64 = scale.cpu().numpy().astype(np.float64) if kind == "sym" else np.ones(n)
+    Yr = ost.edge_batch_apply(n, src, dst, w, s64, Xn)
+    err = np.abs(Y.cpu().numpy() - Yr).max() / np.abs(Yr).max()
+    assert err < 1e-5, err
+
+
+def test_stream_apply_matches_resident_laplacian(sped):
+    """The streamed L X equals the resident CSR path's L X (the sparse step
+    with the monomial p(L) = L) on the same graph."""
+    n, src, dst, w = mixed_degree_graph()
+    sh, dh, wh = _pinned(src, torch.int32), _pinned(dst, torch.int32), _pinned(w, torch.float32)
+    _, scale = sped.stream_node_scales(n, sh, dh, wh, kind="sym", batch=5000)
+    L = sped.Laplacian(n, src, dst, w=w, kind="sym")
+    X = torch.from_numpy(synth.gaussian_block(n, 32, 2).astype(np.float32)).cuda()
+    Yc = sped.apply_poly(L, sped.monomial([0.0, 1.0]), X).cpu().numpy()
+    Ys = sped.stream_laplacian_apply(n, sh, dh, X, wh, scale=scale, batch=5000).cpu().numpy()
+    assert np.abs(Ys - Yc).max() <= 1e-5 * np.abs(Yc).max()
+
+
+def test_stream_minibatch_accumulate_and_edge_cases(sped):
+    """A drawn minibatch scaled by m / b against the oracle on that batch;
+    accumulate adds to the block; m = 0 gives zeros (or leaves the block);
+    an endpoint outside [0, n) or a zero weight is skipped and reported."""
+    from oracle import stream as ost
+    n, src, dst, w = mixed_degree_graph()
+    m = len(src)
+    sh, dh, wh = _pinned(src, torch.int32), _pinned(dst, torch.int32), _pinned(w, torch.float32)
+    _, scale = sped.stream_node_scales(n, sh, dh, wh, kind="sym", batch=1 << 20)
+    s64 = scale.cpu().numpy().astype(np.float64)
+    X = torch.from_numpy(synth.gaussian_block(n, 16, 4).astype(np.float32)).cuda()
+    Xn = X.cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(9).choice(m, m // 7, replace=False))
+    alpha = m / len(idx)
+    Y0 = torch.from_numpy(synth.gaussian_block(n, 16, 5).astype(np.float32)).cuda()
+    Y = sped.stream_laplacian_apply(n, _pinned(src[idx], torch.int32), _pinned(dst[idx], torch.int32), X,
+                                    _pinned(w[idx], torch.float32), scale=scale, alpha=alpha, out=Y0.clone(),
+                                    accumulate=True, batch=999)
+    Yr = Y0.cpu().numpy() + alpha * ost.edge_batch_apply(n, src[idx], dst[idx], w[idx], s64, Xn)
+    assert np.abs(Y.cpu().numpy() - Yr).max() <= 1e-5 * np.abs(Yr).max()
+    empty = torch.empty(0, dtype=torch.int32)
+    Z = sped.stream_laplacian_apply(n, empty, empty, X, scale=scale)
+    assert not Z.any()
+    Z2 = sped.stream_laplacian_apply(n, empty, empty, X, scale=scale, out=Y0.clone(), accumulate=True)
+    assert torch.equal(Z2, Y0)
+    for bad_src, bad_w in ((n, 1.0), (-1, 1.0), (3, 0.0)):
+        s2, d2, w2 = src.copy(), dst.copy(), w.copy()
+        s2[100], w2[101] = bad_src, bad_w
+        with pytest.raises(sped.SpedError) as ei:
+            sped.stream_laplacian_apply(n, _pinned(s2, torch.int32), _pinned(d2, torch.int32), X,
+                                        _pinned(w2, torch.float32), scale=scale, batch=4096)
+        assert ei.value.status == sped.E_INVALID
+    # the device-batch entry point counts the skipped edges
+    s2 = src.copy()
+    s2[[10, 20, 30]] = n + 5
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    Yd = sped.edge_apply(n, torch.from_numpy(s2.astype(np.int32)).cuda(), torch.from_numpy(dst.astype(np.int32)).cuda(),
+                         X, w=torch.from_numpy(w.astype(np.float32)).cuda(), scale=scale, invalid=cnt)
+    assert int(cnt.item()) == 3
+    keep = np.ones(m, bool)
+    keep[[10, 20, 30]] = False
+    Ydr = ost.edge_batch_apply(n, src[keep], dst[keep], w[keep], s64, Xn)
+    assert np.abs(Yd.cpu().numpy() - Ydr).max() <= 1e-5 * np.abs(Ydr).max()
+
+
+def test_minibatch_oja_limit_polynomial_lowers_noise_floor(sped):
+    """The edge-minibatch regime end to end on the 2,000-node SBM: Oja steps
+    V <- orth(V + eta M V) where M V is estimated from streamed batches of
+    2,000 of the 10,834 edges (scaled by m / b).  Plain M = 2I - L stalls at
+    its noise floor; the limit polynomial (I - L/8)^8, one independent batch
+    per factor (so the product stays unbiased), dilates the gap and settles
+    several times lower.  The oracle runs the same batches in float64."""
+    from oracle import solver as osol
+    from oracle import stream as ost
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    m, b, eta, T = len(s), 2000, 0.5, 100
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    _, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    sh, dh = _pinned(s, torch.int32), _pinned(d, torch.int32)
+    _, scale = sped.stream_node_scales(n, sh, dh, kind="sym")
+    s64 = scale.cpu().numpy().astype(np.float64)
+    V0 = np.linalg.qr(np.random.default_rng(3).standard_normal((n, 10)))[0]
+
+    def run(ell, gpu):
+        g = np.random.default_rng(11)
+        V = torch.from_numpy(V0.astype(np.float32)).cuda() if gpu else V0.copy()
+        for _ in range(T):
+            W = 2.0 * V if ell == 1 else V
+            for _f in range(ell):
+                idx = g.choice(m, b, replace=False)
+                a = -(m / b) / (1.0 if ell == 1 else ell)
+                if gpu:
+                    W = sped.stream_laplacian_apply(n, _pinned(s[idx], torch.int32), _pinned(d[idx], torch.int32),
+                                                    V if ell == 1 else W, scale=scale, alpha=a,
+                                                    out=W.clone(), accumulate=True)
+                else:
+                    W = W + a * ost.edge_batch_apply(n, s[idx], d[idx], None, s64, V if ell == 1 else W)
+            if gpu:
+                V = sped.orthonormalize((V + eta * W).contiguous())
+            else:
+                V = np.linalg.qr(V + eta * W)[0]
+        Vn = V.cpu().numpy().astype(np.float64) if gpu else V
+        return osol.max_principal_angle(U, Vn)
+
+    plain_gpu, limit_gpu = run(1, True), run(8, True)
+    plain_ref, limit_ref = run(1, False), run(8, False)
+    _say(f"minibatch Oja angles: plain {plain_gpu:.3f} (oracle {plain_ref:.3f}), "
+         f"limit8 {limit_gpu:.3f} (oracle {limit_ref:.3f})")
+    assert limit_ref < 0.06 and limit_gpu < 0.06
+    assert plain_ref > 2 * limit_ref and plain_gpu > 2 * limit_gpu
