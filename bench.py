@@ -661,6 +661,42 @@ def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
     return out
 
 
+def stream_apply_leg(sped, torch, np, L, n, s, d, Q):
+    """L Q from the bench graph's edge list held in pinned host memory and
+    streamed in batches (the edge-minibatch path: the graph not resident),
+    against the resident sparse step's L Q.  Host->device bytes are 8 per edge
+    (two int32 endpoints, no weights), so the rate includes the PCIe copies."""
+    sh = torch.from_numpy(np.ascontiguousarray(s)).to(torch.int32).pin_memory()
+    dh = torch.from_numpy(np.ascontiguousarray(d)).to(torch.int32).pin_memory()
+    m = sh.numel()
+    batch = 1 << 22
+    t0 = time.perf_counter()
+    _, scale = sped.stream_node_scales(n, sh, dh, kind="sym", batch=batch)
+    torch.cuda.synchronize()
+    scales_ms = (time.perf_counter() - t0) * 1e3
+    Y = torch.empty(n, Q.shape[1], dtype=torch.float32, device=Q.device)
+    sped.stream_laplacian_apply(n, sh, dh, Q, scale=scale, out=Y, batch=batch)
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sped.stream_laplacian_apply(n, sh, dh, Q, scale=scale, out=Y, batch=batch)
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    Yc = sped.apply_poly(L, sped.monomial([0.0, 1.0]), Q)
+    torch.cuda.synchronize()
+    rel = float((Y - Yc).abs().max() / Yc.abs().max())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        sped.apply_poly(L, sped.monomial([0.0, 1.0]), Q, out=Yc)
+    e1.record()
+    torch.cuda.synchronize()
+    resident_ms = e0.elapsed_time(e1) / reps
+    return {"workload": "same SBM edge list (int32 pairs, pinned host memory), L Q with k=32, batches of 2^22 edges",
+            "edges": m, "node_scales_ms": round(scales_ms, 3), "apply_ms": round(ms, 3),
+            "edges_per_s": round(m / (ms * 1e-3), 1), "host_to_device_GBps": round(8 * m / (ms * 1e-3) / 1e9, 2),
+            "resident_sparse_step_ms": round(resident_ms, 4), "max_rel_diff_vs_resident": rel}
+
+
 def power_law_bf16(sped, synth, torch, np):
     """The power-law workload at its full shape: a 4e6-node Chung-Lu graph
     (exponent 2.1, mean degree 16, 256 planted communities, 95% of draws
@@ -717,6 +753,8 @@ def main():
     ap.add_argument("--chain-only", action="store_true", help="time only the exact p(L)V chain (profiling)")
     ap.add_argument("--power-law-only", action="store_true",
                     help="run only the power-law bf16 workload (profiling the SpMM bins)")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="run only the streamed edge-batch L Q on the bench graph (profiling that path)")
     ap.add_argument("--gather-probe", action="store_true",
                     help="measure the chip's rate for the sparse step's row-load pattern")
     ap.add_argument("--rmat26", action="store_true",
@@ -770,6 +808,12 @@ def main():
         return
     if args.power_law_only:
         print(json.dumps({"power_law_bf16_k64": power_law_bf16(sped, synth, torch, np)}), flush=True)
+        return
+    if args.stream_only:
+        n, s, d, _ = synth.sbm_from_degrees(1_000_000, 100, 19.0, 1.0, seed=1)
+        L = sped.Laplacian(n, s, d, kind="sym", walk_records=False)
+        Q = torch.from_numpy(synth.gaussian_block(n, 32, 2).astype(np.float32)).cuda()
+        print(json.dumps({"stream_apply": stream_apply_leg(sped, torch, np, L, n, s, d, Q)}), flush=True)
         return
     k, ell, walks = 32, 16, 8
     t0 = time.perf_counter()
@@ -850,6 +894,7 @@ def main():
     }
     if not args.chain_only:
         line["estimators"] = estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream)
+        line["stream_apply"] = stream_apply_leg(sped, torch, np, L, n, s, d, Q)
     if not args.chain_only and not args.no_solve:
         del L, Q, W, S
         torch.cuda.empty_cache()
