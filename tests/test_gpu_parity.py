@@ -972,8 +972,8 @@ def _pinned(a, dt):
 
 
 @pytest.mark.parametrize("kind", ["sym", "combinatorial"])
-@pytest.mark.parametrize("k,dt,batch", [(32, "f32", 4096), (7, "f32", 1000), (64, "bf16", 7919),
-                                        (300, "f32", 10 ** 6)])
+@pytest.mark.parametrize("k,dt,batch", [(32, "f32", 4096), (7, "f32", 1000), (50, "f32", 3001),
+                                        (64, "bf16", 7919), (300, "f32", 10 ** 6)])
 def test_stream_laplacian_apply_parity(sped, kind, k, dt, batch):
     """Streamed sum_e x_e x_e^T X over a pinned host edge list (weights,
     repeats, self-loops, a degree-9000 hub) against the float64 oracle on the
