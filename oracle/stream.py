@@ -55,3 +55,41 @@ def edge_batch_apply(n, src, dst, w, scale, V):
     np.add.at(Y, i, (wt * s[i])[:, None] * diff)
     np.add.at(Y, j, -(wt * s[j])[:, None] * diff)
     return Y
+
+
+def _cholqr2(V):
+    for _ in range(2):
+        R = np.linalg.cholesky(V.T @ V).T
+        V = np.linalg.solve(R.T, V.T).T
+    return V
+
+
+def cyclic_batch(m, start, j, batch):
+    """Indices of batch j: edges (start + j batch + r) mod m, r < batch."""
+    return (start + j * batch + np.arange(batch)) % m
+
+
+def minibatch_oja(n, src, dst, w, scale, degree, lambda_bound, V0, batch, eta, iters, start=0):
+    """Oja steps V <- orth(V + eta M_hat V) (Sec. 5's update; orth by two
+    Cholesky QR passes) with M_hat from consecutive batches of the edge list
+    taken cyclically, each scaled by m / batch (Sec. 3: edge vectors fed in
+    minibatches).  degree 0: M_hat V = lambda_bound V - L_B V; degree l:
+    (I - L_{B_l} / l) ... (I - L_{B_1} / l) V with a fresh batch per factor,
+    so the product is an unbiased estimate of (I - L/l)^l V."""
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    wt = None if w is None else np.asarray(w, dtype=np.float64)
+    m = len(src)
+    V = np.asarray(V0, dtype=np.float64).copy()
+    F = 1 if degree == 0 else degree
+    j = 0
+    for _ in range(iters):
+        W = V
+        for _f in range(F):
+            idx = cyclic_batch(m, start, j, batch)
+            j += 1
+            LB = edge_batch_apply(n, src[idx], dst[idx], None if wt is None else wt[idx], scale,
+                                  V if degree == 0 else W) * (m / batch)
+            W = lambda_bound * V - LB if degree == 0 else W - LB / degree
+        V = _cholqr2(V + eta * W)
+    return V

@@ -90,3 +90,53 @@ def test_batches_add_up_and_single_edge_mean_is_unbiased():
     m = len(src)
     mean = sum(m * ost.edge_batch_apply(n, src[e:e + 1], dst[e:e + 1], w[e:e + 1], s, V) for e in range(m)) / m
     np.testing.assert_allclose(mean, full, rtol=1e-13, atol=1e-13)
+
+
+def test_minibatch_oja_full_batch_limit_step_is_the_limit_product():
+    """With one batch holding every edge the limit-polynomial step is
+    orth(V + eta (I - L/l)^l V) exactly; (I - L/l)^l V from the product
+    oracle, orthonormalised by a textbook QR."""
+    from oracle import poly as opoly
+    from oracle import solver as osol
+    g = np.random.default_rng(2)
+    n, m = 80, 400
+    src, dst = g.integers(0, n, m), g.integers(0, n, m)
+    w = g.uniform(0.1, 1.0, m)
+    ref = olap.laplacian(n, src, dst, w=w, kind=olap.SYM_NORMALIZED)
+    _, s = ost.node_scales(n, src, dst, w)
+    V0 = np.linalg.qr(g.standard_normal((n, 4)))[0]
+    V = ost.minibatch_oja(n, src, dst, w, s, 6, 2.0, V0, batch=m, eta=0.7, iters=1)
+    Vr = np.linalg.qr(V0 + 0.7 * opoly.apply_limit_product(ref.L, 6, V0))[0]
+    assert osol.max_principal_angle(V, Vr) < 1e-10
+    np.testing.assert_allclose(V.T @ V, np.eye(4), atol=1e-12)
+
+
+def test_minibatch_oja_fixed_point_and_cyclic_batches():
+    """The bottom eigenvectors are a fixed point of the full-batch plain step
+    (lambda I - L keeps them, orth keeps their span); a batch that wraps past
+    the end of the list takes the last edges then the first ones."""
+    from oracle import solver as osol
+    n, src, dst, w = small_graph()
+    _, s = ost.node_scales(n, src, dst, w)
+    L = incidence_laplacian(n, src, dst, w, s)
+    _, U = np.linalg.eigh(L)
+    U = U[:, :3]
+    V = ost.minibatch_oja(n, src, dst, w, s, 0, 2.0, U, batch=len(src), eta=0.5, iters=5)
+    assert osol.max_principal_angle(U, V) < 1e-10
+    m = len(src)
+    np.testing.assert_array_equal(ost.cyclic_batch(m, m - 3, 0, 5), [m - 3, m - 2, m - 1, 0, 1])
+    np.testing.assert_array_equal(ost.cyclic_batch(m, m - 3, 1, 5), [2, 3, 4, 5, 6])
+    # two limit-polynomial steps (degree 2) whose batches wrap, against the
+    # same factors applied step by step with a textbook QR
+    V0 = np.linalg.qr(np.random.default_rng(4).standard_normal((n, 2)))[0]
+    Va = ost.minibatch_oja(n, src, dst, w, s, 2, 2.0, V0, batch=5, eta=0.3, iters=2, start=m - 3)
+    Vh = V0.copy()
+    j = 0
+    for _ in range(2):
+        W = Vh
+        for _f in range(2):
+            idx = ost.cyclic_batch(m, m - 3, j, 5)
+            j += 1
+            W = W - ost.edge_batch_apply(n, src[idx], dst[idx], w[idx], s, W) * (m / 5) / 2
+        Vh = np.linalg.qr(Vh + 0.3 * W)[0]
+    assert osol.max_principal_angle(Va, Vh) < 1e-10
