@@ -475,6 +475,27 @@ sped_status sped_stream_laplacian_apply(int64_t n, int64_t m, const int32_t *src
                                         int32_t xdt, float *Y, int64_t ldy, float alpha, int32_t accumulate,
                                         int64_t batch, void *ws, size_t *ws_bytes, sped_stream_t stream);
 
+/* sped_minibatch_oja -- `iters` Oja steps V <- orth(V + eta M_hat V) on a
+ * host-resident edge list (Sec. 3: edge vectors fed to the solver in
+ * minibatches; Sec. 5: Oja's update; orth = Cholesky QR, two passes).  The
+ * batches are consecutive runs of `batch` edges of the host arrays, taken
+ * cyclically from edge `start` (shuffle the list once for uniformly drawn
+ * batches); each is scaled by m / batch.
+ *  degree 0:   M_hat V = lambda_bound V - (m / b) L_B V (the plain reversed
+ *              operator, one batch per step);
+ *  degree l:   M_hat V = (I - (m / b) L_{B_l} / l) ... (I - (m / b) L_{B_1} / l) V,
+ *              the limit polynomial (I - L/l)^l with a fresh batch per factor
+ *              (independent batches keep the product unbiased; l batches per
+ *              step).
+ * scale as in sped_stream_laplacian_apply; V DEVICE float n x k (ldv), k <= 96,
+ * updated in place.  1 <= batch <= m.  Workspace: two staging batches, two
+ * n x k float blocks and the orthonormalisation's.  Synchronises `stream`;
+ * invalid edges are skipped and make the call return SPED_E_INVALID. */
+sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h, const float *w_h,
+                               const float *scale, int32_t degree, double lambda_bound, int64_t k, float *V,
+                               int64_t ldv, int64_t batch, double eta, int32_t iters, int64_t start, void *ws,
+                               size_t *ws_bytes, sped_stream_t stream);
+
 /*
  * sped_stream_copy -- dst <- src, `bytes` bytes (multiple of 16, 16-byte
  * aligned DEVICE pointers): a plain streaming copy used to calibrate the

@@ -96,6 +96,24 @@ __global__ void fill_f64_kernel(int64_t n, double *__restrict__ p) {
 
 __global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
 
+// out = a in (n x k blocks)
+__global__ void scale_copy_kernel(int64_t n, int k, const float *__restrict__ in, int64_t ldi, float *__restrict__ out,
+                                  int64_t ldo, float a) {
+  GRID_STRIDE(t, n * k) {
+    const int64_t r = t / k, c = t - r * k;
+    out[r * ldo + c] = a * in[r * ldi + c];
+  }
+}
+
+// V += eta W (n x k blocks)
+__global__ void axpy_block_kernel(int64_t n, int k, float *__restrict__ V, int64_t ldv, const float *__restrict__ W,
+                                  int64_t ldw, float eta) {
+  GRID_STRIDE(t, n * k) {
+    const int64_t r = t / k, c = t - r * k;
+    V[r * ldv + c] += eta * W[r * ldw + c];
+  }
+}
+
 unsigned grid_blocks(int64_t work) {
   int64_t b = (work + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
@@ -157,12 +175,18 @@ sped_status check_block_args(int64_t n, int64_t k, const void *X, int64_t ldx, i
 }
 
 // Host edge list -> device batches on a private copy stream, two staging
-// buffers alternating; `body(b, src, dst, w, count)` enqueues the batch's
-// kernel on `s`.  Synchronises `s` before returning.
-template <typename Body>
-sped_status stream_batches(int64_t m, const int32_t *src_h, const int32_t *dst_h, const float *w_h, int64_t batch,
-                           int32_t *stage_src[2], int32_t *stage_dst[2], float *stage_w[2], hipStream_t s,
-                           Body body) {
+// buffers alternating.  Batch j is seg(j) = up to two ranges of the host
+// arrays (a batch may wrap around the end of the list), copied back to back
+// into one staging buffer; `body(j, src, dst, w, count)` enqueues the batch's
+// kernels on `s`.  Synchronises `s` before returning.
+struct Segs {
+  int64_t off[2], cnt[2];
+};
+
+template <typename SegFn, typename Body>
+sped_status stream_segments(int64_t nbatches, const int32_t *src_h, const int32_t *dst_h, const float *w_h,
+                            int32_t *stage_src[2], int32_t *stage_dst[2], float *stage_w[2], hipStream_t s,
+                            SegFn seg, Body body) {
   hipStream_t cs = nullptr;
   hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
   sped_status st = SPED_OK;
@@ -176,26 +200,30 @@ sped_status stream_batches(int64_t m, const int32_t *src_h, const int32_t *dst_h
       hip_ok(hipEventCreateWithFlags(&used[0], hipEventDisableTiming), "hipEventCreate") &&
       hip_ok(hipEventCreateWithFlags(&used[1], hipEventDisableTiming), "hipEventCreate")) {
     // the copies must not start before work already queued on s that may
-    // still read the staging buffers (an earlier call's batches)
+    // still read the staging buffers
     hip_ok(hipEventRecord(used[0], s), "hipEventRecord");
     hip_ok(hipEventRecord(used[1], s), "hipEventRecord");
-    int64_t b = 0;
-    for (int64_t off = 0; off < m && st == SPED_OK; off += batch, ++b) {
-      const int buf = int(b & 1);
-      const int64_t cnt = std::min(batch, m - off);
+    for (int64_t j = 0; j < nbatches && st == SPED_OK; ++j) {
+      const int buf = int(j & 1);
+      const Segs g = seg(j);
       if (!hip_ok(hipStreamWaitEvent(cs, used[buf], 0), "hipStreamWaitEvent")) break;
-      if (!hip_ok(hipMemcpyAsync(stage_src[buf], src_h + off, cnt * sizeof(int32_t), hipMemcpyHostToDevice, cs),
-                  "hipMemcpyAsync") ||
-          !hip_ok(hipMemcpyAsync(stage_dst[buf], dst_h + off, cnt * sizeof(int32_t), hipMemcpyHostToDevice, cs),
-                  "hipMemcpyAsync"))
-        break;
-      if (w_h && !hip_ok(hipMemcpyAsync(stage_w[buf], w_h + off, cnt * sizeof(float), hipMemcpyHostToDevice, cs),
-                         "hipMemcpyAsync"))
-        break;
+      int64_t at = 0;
+      for (int q = 0; q < 2 && st == SPED_OK; ++q) {
+        if (g.cnt[q] == 0) continue;
+        hip_ok(hipMemcpyAsync(stage_src[buf] + at, src_h + g.off[q], g.cnt[q] * sizeof(int32_t),
+                              hipMemcpyHostToDevice, cs), "hipMemcpyAsync");
+        hip_ok(hipMemcpyAsync(stage_dst[buf] + at, dst_h + g.off[q], g.cnt[q] * sizeof(int32_t),
+                              hipMemcpyHostToDevice, cs), "hipMemcpyAsync");
+        if (w_h)
+          hip_ok(hipMemcpyAsync(stage_w[buf] + at, w_h + g.off[q], g.cnt[q] * sizeof(float), hipMemcpyHostToDevice,
+                                cs), "hipMemcpyAsync");
+        at += g.cnt[q];
+      }
+      if (st != SPED_OK) break;
       if (!hip_ok(hipEventRecord(copied[buf], cs), "hipEventRecord") ||
           !hip_ok(hipStreamWaitEvent(s, copied[buf], 0), "hipStreamWaitEvent"))
         break;
-      const sped_status kst = body(b, stage_src[buf], stage_dst[buf], w_h ? stage_w[buf] : nullptr, cnt);
+      const sped_status kst = body(j, stage_src[buf], stage_dst[buf], w_h ? stage_w[buf] : nullptr, at);
       if (kst != SPED_OK) {
         st = kst;
         break;
@@ -213,6 +241,21 @@ sped_status stream_batches(int64_t m, const int32_t *src_h, const int32_t *dst_h
     if (ev) hipEventDestroy(ev);
   if (cs) hipStreamDestroy(cs);
   return st;
+}
+
+// The list [0, m) in consecutive batches of `batch` edges.
+template <typename Body>
+sped_status stream_batches(int64_t m, const int32_t *src_h, const int32_t *dst_h, const float *w_h, int64_t batch,
+                           int32_t *stage_src[2], int32_t *stage_dst[2], float *stage_w[2], hipStream_t s,
+                           Body body) {
+  const int64_t nb = (m + batch - 1) / batch;
+  return stream_segments(
+      nb, src_h, dst_h, w_h, stage_src, stage_dst, stage_w, s,
+      [&](int64_t j) {
+        Segs g{{j * batch, 0}, {std::min(batch, m - j * batch), 0}};
+        return g;
+      },
+      body);
 }
 
 struct StreamWs {
@@ -328,5 +371,81 @@ extern "C" sped_status sped_stream_laplacian_apply(int64_t n, int64_t m, const i
                             return launch_edge_apply(g, cnt, bs, bd, bw, scale, n, k, X, ldx, xdt, Y, ldy, alpha,
                                                      w.invalid, s);
                           }));
+  return read_invalid(w.invalid, s);
+}
+
+extern "C" sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h,
+                                          const float *w_h, const float *scale, int32_t degree, double lambda_bound,
+                                          int64_t k, float *V, int64_t ldv, int64_t batch, double eta, int32_t iters,
+                                          int64_t start, void *ws, size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  if (n < 1 || n >= (int64_t(1) << 31)) return fail(SPED_E_INVALID, "n out of range");
+  if (k < 1 || k > 96) return fail(SPED_E_UNSUPPORTED, "k outside [1, 96]");
+  if (ldv < k) return fail(SPED_E_INVALID, "ldv < k");
+  if (!V) return fail(SPED_E_INVALID, "V NULL");
+  if (m < 1 || !src_h || !dst_h) return fail(SPED_E_INVALID, "empty or NULL edge list");
+  if (batch < 1 || batch > m) return fail(SPED_E_INVALID, "batch outside [1, m]");
+  if (degree < 0 || degree > 1024) return fail(SPED_E_INVALID, "degree outside [0, 1024]");
+  if (degree == 0 && !(std::isfinite(lambda_bound) && lambda_bound > 0.0)) return fail(SPED_E_INVALID, "lambda_bound");
+  if (!(std::isfinite(eta) && eta > 0.0)) return fail(SPED_E_INVALID, "eta");
+  if (iters < 0) return fail(SPED_E_INVALID, "iters < 0");
+  if (start < 0) return fail(SPED_E_INVALID, "start < 0");
+  StreamWs w;
+  Carver c(ws);
+  const size_t stage = carve_stream_ws(ws, batch, &w);
+  c.off = stage;
+  float *W0 = c.take<float>(size_t(n) * k);
+  float *W1 = c.take<float>(size_t(n) * k);
+  size_t orth_need = 0;
+  SPED_TRY(sped_orthonormalize(n, k, V, ldv, SPED_F32, 2, nullptr, nullptr, &orth_need, stream));
+  void *orth_ws = c.take<char>(orth_need);
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+  clear_error();
+  hipStream_t s = as_stream(stream);
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, w.invalid);
+  SPED_CHECK_HIP(hipGetLastError());
+  const int F = degree == 0 ? 1 : int(degree);
+  const EdgeGeom g = edge_geom(k, V, ldv, SPED_F32, W0, k);
+  const unsigned blocks = grid_blocks(n * k);
+  const float a = degree == 0 ? float(-double(m) / double(batch)) : float(-double(m) / double(batch) / F);
+  float *cur = W0, *nxt = W1;
+  int64_t next_off = start % m;  // batch j: edges (start + j batch + r) mod m, r < batch
+  const sped_status st = stream_segments(
+      int64_t(iters) * F, src_h, dst_h, w_h, w.src, w.dst, w.w, s,
+      [&](int64_t) {  // called once per batch, in order
+        const int64_t o = next_off;
+        const int64_t first = std::min(batch, m - o);
+        next_off = (o + batch) % m;
+        Segs sg{{o, 0}, {first, batch - first}};
+        return sg;
+      },
+      [&](int64_t j, const int32_t *bs, const int32_t *bd, const float *bw, int64_t cnt) -> sped_status {
+        const int f = int(j % F);
+        if (degree == 0) {  // W = lambda V - (m / b) L_B V
+          hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks), dim3(kBlock), 0, s, n, int(k), V, ldv, cur, k,
+                             float(lambda_bound));
+          SPED_CHECK_HIP(hipGetLastError());
+          SPED_TRY(launch_edge_apply(g, cnt, bs, bd, bw, scale, n, k, V, ldv, SPED_F32, cur, k, a, w.invalid, s));
+        } else {  // W <- (I - (m / b) L_B / l) W, W = V before the first factor
+          const float *in = f == 0 ? V : cur;
+          const int64_t ldi = f == 0 ? ldv : k;
+          hipLaunchKernelGGL(scale_copy_kernel, dim3(blocks), dim3(kBlock), 0, s, n, int(k), in, ldi, nxt, k, 1.f);
+          SPED_CHECK_HIP(hipGetLastError());
+          SPED_TRY(launch_edge_apply(g, cnt, bs, bd, bw, scale, n, k, in, ldi, SPED_F32, nxt, k, a, w.invalid, s));
+          std::swap(cur, nxt);
+        }
+        if (f == F - 1) {  // V <- orth(V + eta W)
+          hipLaunchKernelGGL(axpy_block_kernel, dim3(blocks), dim3(kBlock), 0, s, n, int(k), V, ldv, cur, k,
+                             float(eta));
+          SPED_CHECK_HIP(hipGetLastError());
+          size_t need = orth_need;
+          SPED_TRY(sped_orthonormalize(n, k, V, ldv, SPED_F32, 2, nullptr, orth_need ? orth_ws : nullptr,
+                                       orth_need ? &need : nullptr, stream));
+        }
+        return SPED_OK;
+      });
+  if (st != SPED_OK) return st;
   return read_invalid(w.invalid, s);
 }

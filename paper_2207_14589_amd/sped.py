@@ -82,6 +82,8 @@ SIGNATURES = {
                                 _P(_c_sz), _c_vp],
     "sped_stream_laplacian_apply": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32,
                                     _c_vp, _c_i64, ctypes.c_float, _c_i32, _c_i64, _c_vp, _P(_c_sz), _c_vp],
+    "sped_minibatch_oja": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_f64, _c_i64, _c_vp, _c_i64,
+                           _c_i64, _c_f64, _c_i32, _c_i64, _c_vp, _P(_c_sz), _c_vp],
     "sped_stream_copy": [_c_vp, _c_vp, _c_sz, _c_vp],
     "sped_gather_probe": [_c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp],
     "sped_last_error": [],
@@ -455,6 +457,22 @@ def stream_laplacian_apply(n, src_h, dst_h, X, w_h=None, scale=None, alpha=1.0, 
               _c_vp(w_h.data_ptr() if w_h is not None else None), _ptr(scale), k, _ptr(X), _ld(X), _dt(X),
               _ptr(out), _ld(out), float(alpha), int(bool(accumulate)), int(batch)), X.device)
     return out
+
+
+def minibatch_oja(n, src_h, dst_h, V, w_h=None, scale=None, degree=0, lambda_bound=2.0, batch=1 << 16, eta=0.5,
+                  iters=100, start=0):
+    """In place: `iters` Oja steps V <- orth(V + eta M_hat V) with M_hat from
+    consecutive batches of a HOST edge list (degree 0: lambda_bound I - L;
+    degree l: the limit polynomial (I - L/l)^l, one batch per factor).
+    V: DEVICE float32 n x k."""
+    src_h, dst_h, w_h = _host_edges(src_h, dst_h, w_h)
+    if V.dtype != torch.float32:
+        raise TypeError("V must be float32")
+    _call_ws(lib().sped_minibatch_oja, "sped_minibatch_oja",
+             (int(n), src_h.numel(), _c_vp(src_h.data_ptr()), _c_vp(dst_h.data_ptr()),
+              _c_vp(w_h.data_ptr() if w_h is not None else None), _ptr(scale), int(degree), float(lambda_bound),
+              V.shape[1], _ptr(V), _ld(V), int(batch), float(eta), int(iters), int(start)), V.device)
+    return V
 
 
 def gather_probe(table, iters, scattered, blocks, out):

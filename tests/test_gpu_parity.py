@@ -1103,3 +1103,57 @@ def test_minibatch_oja_limit_polynomial_lowers_noise_floor(sped):
          f"limit8 {limit_gpu:.3f} (oracle {limit_ref:.3f})")
     assert limit_ref < 0.06 and limit_gpu < 0.06
     assert plain_ref > 2 * limit_ref and plain_gpu > 2 * limit_gpu
+
+
+@pytest.mark.parametrize("degree", [0, 8])
+def test_minibatch_oja_solver_parity(sped, degree):
+    """sped_minibatch_oja against the oracle's trajectory on the same cyclic
+    batches (2,000 of the 10,834 edges of the shuffled 2,000-node SBM list,
+    eta = 0.5, 100 steps, starting 7 edges before the end of the list): the
+    float32 iterate stays within 1e-4 of the float64 one, and the limit
+    polynomial ends several times closer to the bottom-10 subspace than the
+    plain operator."""
+    from oracle import solver as osol
+    from oracle import stream as ost
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    perm = np.random.default_rng(5).permutation(len(s))
+    s, d = s[perm], d[perm]
+    m = len(s)
+    sh, dh = _pinned(s, torch.int32), _pinned(d, torch.int32)
+    _, scale = sped.stream_node_scales(n, sh, dh, kind="sym")
+    s64 = scale.cpu().numpy().astype(np.float64)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    _, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = np.linalg.qr(np.random.default_rng(3).standard_normal((n, 10)))[0]
+    V = torch.from_numpy(V0.astype(np.float32)).cuda()
+    sped.minibatch_oja(n, sh, dh, V, scale=scale, degree=degree, lambda_bound=2.0, batch=2000, eta=0.5,
+                       iters=100, start=m - 7)
+    Vr = ost.minibatch_oja(n, s, d, None, s64, degree, 2.0, V0, batch=2000, eta=0.5, iters=100, start=m - 7)
+    Vg = V.cpu().numpy().astype(np.float64)
+    drift = osol.max_principal_angle(Vg, Vr)
+    ang = osol.max_principal_angle(U, Vg)
+    _say(f"minibatch_oja degree {degree}: angle to bottom-10 {ang:.4f}, to the oracle trajectory {drift:.2e}")
+    assert drift < 1e-4
+    np.testing.assert_allclose(Vg.T @ Vg, np.eye(10), atol=1e-5)
+    assert ang < (0.03 if degree == 8 else 0.12)
+    if degree == 0:
+        assert ang > 0.04   # the plain operator's noise floor sits above the limit polynomial's
+
+
+def test_minibatch_oja_edge_cases(sped):
+    """No steps leave V unchanged; a batch larger than the list and an
+    endpoint outside [0, n) are rejected."""
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    sh, dh = _pinned(s, torch.int32), _pinned(d, torch.int32)
+    V0 = torch.from_numpy(np.linalg.qr(np.random.default_rng(3).standard_normal((n, 6)))[0].astype(np.float32)).cuda()
+    V = V0.clone()
+    sped.minibatch_oja(n, sh, dh, V, degree=4, batch=100, iters=0)
+    assert torch.equal(V, V0)
+    with pytest.raises(sped.SpedError) as ei:
+        sped.minibatch_oja(n, sh, dh, V, degree=4, batch=len(s) + 1, iters=1)
+    assert ei.value.status == sped.E_INVALID
+    bad = s.copy()
+    bad[5] = n
+    with pytest.raises(sped.SpedError) as ei:
+        sped.minibatch_oja(n, _pinned(bad, torch.int32), dh, V.clone(), degree=0, batch=1000, iters=2)
+    assert ei.value.status == sped.E_INVALID
