@@ -691,8 +691,19 @@ def stream_apply_leg(sped, torch, np, L, n, s, d, Q):
     e1.record()
     torch.cuda.synchronize()
     resident_ms = e0.elapsed_time(e1) / reps
+    # minibatch Oja steps with the degree-8 limit polynomial, one batch of 2^21
+    # edges per factor (8 batches per step), on a copy of Q
+    V = Q.clone()
+    sped.minibatch_oja(n, sh, dh, V, scale=scale, degree=8, batch=1 << 21, eta=0.5, iters=1)
+    torch.cuda.synchronize()
+    steps = 3
+    t0 = time.perf_counter()
+    sped.minibatch_oja(n, sh, dh, V, scale=scale, degree=8, batch=1 << 21, eta=0.5, iters=steps)
+    oja_ms = (time.perf_counter() - t0) * 1e3 / steps
     return {"workload": "same SBM edge list (int32 pairs, pinned host memory), L Q with k=32, batches of 2^22 edges",
             "edges": m, "node_scales_ms": round(scales_ms, 3), "apply_ms": round(ms, 3),
+            "minibatch_oja_limit8_ms_per_step": round(oja_ms, 3),
+            "minibatch_oja_edge_samples_per_s": round(8 * (1 << 21) / (oja_ms * 1e-3), 1),
             "edges_per_s": round(m / (ms * 1e-3), 1), "host_to_device_GBps": round(8 * m / (ms * 1e-3) / 1e9, 2),
             "resident_sparse_step_ms": round(resident_ms, 4), "max_rel_diff_vs_resident": rel}
 
