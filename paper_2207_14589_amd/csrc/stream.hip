@@ -11,7 +11,10 @@
 //
 // The streamed entry points copy a host edge list in batches into two device
 // staging buffers (alternating, on a private copy stream ordered by events),
-// so the copy of batch b + 1 overlaps the kernel of batch b.
+// so the copy of batch b + 1 overlaps the kernel of batch b.  The minibatch
+// solver runs Oja steps (Sec. 5) on such batches: the reversed operator
+// lambda I - L from one batch, or the limit polynomial (I - L/l)^l from l
+// batches, one per factor, then Cholesky QR.
 #include <algorithm>
 #include <cmath>
 
