@@ -191,3 +191,21 @@ def test_edge_batch_validation(lib):
     assert h(10, 100, s, d, None, sped.SYM_NORMALIZED, 64, None, X, None, ctypes.byref(need),
              None) == sped.E_INVALID                                                                    # degree NULL
     assert h(10, 100, s, d, None, sped.SYM_NORMALIZED, 64, Y, X, None, ctypes.byref(need), None) == sped.OK
+
+
+def test_minibatch_oja_validation(lib):
+    """Host checks of the minibatch solver, and its workspace size query (two
+    staging batches, two n x k float blocks and the orthonormalisation's)."""
+    s, d, V = 1024, 2048, 4096   # fake, never dereferenced
+    f = lib.sped_minibatch_oja
+    need = ctypes.c_size_t(0)
+    q = ctypes.byref(need)
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 51, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # batch > m
+    assert f(100, 50, s, d, None, None, 8, 2.0, 97, V, 97, 10, 0.5, 3, 0, None, q, None) == sped.E_UNSUPPORTED
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 9, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID   # ldv < k
+    assert f(100, 50, s, d, None, None, 0, 0.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # lambda
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.0, 3, 0, None, q, None) == sped.E_INVALID  # eta
+    assert f(100, 50, s, d, None, None, -1, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # degree
+    assert f(100, 0, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID   # m = 0
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.OK
+    assert need.value >= 2 * 100 * 10 * 4 + 2 * 10 * 12
