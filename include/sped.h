@@ -169,7 +169,9 @@ typedef struct {
  *                     lambda* = f(lambda_bound): c_0 = f(lambda_bound),
  *                     c_i = (-1)^i / i; shift = 1 - eps, scale = 1
  * (Sec. 4.1 requires f increasing where the wanted eigenvalues lie; Table 2
- * takes l odd.)  coeffs HOST [degree+1]; shift, scale HOST.
+ * takes l odd.  The Taylor log with an even degree is not increasing on
+ * [0, 2] and returns SPED_E_UNSUPPORTED.)  coeffs HOST [degree+1]; shift,
+ * scale HOST.
  */
 typedef enum { SPED_T_PLAIN = 0, SPED_T_LIMIT = 1, SPED_T_TAYLOR_EXP = 2, SPED_T_TAYLOR_LOG = 3 } sped_transform;
 sped_status sped_transform_coeffs(int32_t transform, int32_t degree, double lambda_bound, double eps,
@@ -179,6 +181,14 @@ sped_status sped_transform_coeffs(int32_t transform, int32_t degree, double lamb
  * (binomial expansion of the shift and scale, or of the limit product);
  * out HOST [degree+1]. */
 sped_status sped_poly_monomial(const sped_poly *p, double *out);
+
+/* sped_poly_rebase -- the coefficients of p in the variable
+ * Lt = (L - shift I) / scale (scale != 0), so that p = sum_i out[i] Lt^i:
+ * the learnable coefficients of Sec. 6 start from a Table 2 row written in
+ * the variable where the tuning runs.  The limit polynomial is expanded
+ * directly, (a + b Lt)^l with a = 1 - shift/l, b = -scale/l; a monomial
+ * polynomial through its coefficients in L.  out HOST [degree+1]. */
+sped_status sped_poly_rebase(const sped_poly *p, double shift, double scale, double *out);
 
 /*
  * sped_apply_poly -- Y = M X for the polynomial p (Sec. 4.2): `degree` fused
@@ -477,24 +487,33 @@ sped_status sped_stream_laplacian_apply(int64_t n, int64_t m, const int32_t *src
 
 /* sped_minibatch_oja -- `iters` Oja steps V <- orth(V + eta M_hat V) on a
  * host-resident edge list (Sec. 3: edge vectors fed to the solver in
- * minibatches; Sec. 5: Oja's update; orth = Cholesky QR, two passes).  The
- * batches are consecutive runs of `batch` edges of the host arrays, taken
- * cyclically from edge `start` (shuffle the list once for uniformly drawn
- * batches); each is scaled by m / batch.
+ * minibatches; Sec. 5: Oja's update; orth = Cholesky QR, two passes).  Batch
+ * j of the call is the run of `batch` edges of the host arrays that starts at
+ * a uniform random offset o_J and wraps past the end: edges (o_J + r) mod m,
+ * r < batch, with J = batch0 + j and o_J = Lemire's bounded draw in [0, m)
+ * from Philox4x32-10 keyed by seed, counter (J mod 2^32, J >> 32, 0, 0), the
+ * words of j' = 0, 1, ... in order (as sped_apply_poly_stochastic's draws).
+ * Every edge is in a batch with probability b / m, and different batches are
+ * independent; each batch is scaled by m / b.  (Shuffle the list once if its
+ * order is not random: the edges of one batch are then a uniform sample.)
  *  degree 0:   M_hat V = lambda_bound V - (m / b) L_B V (the plain reversed
  *              operator, one batch per step);
  *  degree l:   M_hat V = (I - (m / b) L_{B_l} / l) ... (I - (m / b) L_{B_1} / l) V,
- *              the limit polynomial (I - L/l)^l with a fresh batch per factor
- *              (independent batches keep the product unbiased; l batches per
+ *              the limit polynomial (I - L/l)^l with its own batch per factor;
+ *              independent factors make E[M_hat] = (I - L/l)^l (l batches per
  *              step).
+ * A solve split over several calls continues the same batch stream when each
+ * call passes batch0 = the number of batches drawn before it (iters x max(1,
+ * degree) per call).
  * scale as in sped_stream_laplacian_apply; V DEVICE float n x k (ldv), k <= 96,
- * updated in place.  1 <= batch <= m.  Workspace: two staging batches, two
- * n x k float blocks and the orthonormalisation's.  Synchronises `stream`;
- * invalid edges are skipped and make the call return SPED_E_INVALID. */
+ * updated in place.  1 <= batch <= m < 2^32.  Workspace: two staging
+ * batches, two n x k float blocks and the orthonormalisation's.  Synchronises
+ * `stream`; invalid edges are skipped and make the call return
+ * SPED_E_INVALID. */
 sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h, const float *w_h,
                                const float *scale, int32_t degree, double lambda_bound, int64_t k, float *V,
-                               int64_t ldv, int64_t batch, double eta, int32_t iters, int64_t start, void *ws,
-                               size_t *ws_bytes, sped_stream_t stream);
+                               int64_t ldv, int64_t batch, double eta, int32_t iters, uint64_t seed,
+                               int64_t batch0, void *ws, size_t *ws_bytes, sped_stream_t stream);
 
 /*
  * sped_stream_copy -- dst <- src, `bytes` bytes (multiple of 16, 16-byte

@@ -135,6 +135,90 @@ def estimate_lazy(lap: Laplacian, ell: int, V, walks_per_row: int, seed: int, co
     return est.reshape(rows.shape[0], walks_per_row, -1).mean(axis=1)
 
 
+def walk_path(lap: Laplacian, ell: int, r: int, w: int, seed: int, counter: int = 0, flip: int | None = None):
+    """One walk, step by step (the same draws as `estimate_lazy`), for
+    checking single rows.  Returns (end node, decisions): every decision the
+    walk took, in order, as (kind, margin), the margin being how far the
+    compared quantities were from the other outcome, relative to their size:
+      'gap'    |q - nearest integer| / max(1, |q|), q = log(1 - u) / log1p(-p_move)
+               (the floor of q is the number of stays);
+      'accept' |u - ratio| / ratio for a proposal tested against a uniform u
+               (a ratio that the equality rule accepts is not a decision: the
+               other rounding of it would be accepted by the test with
+               probability 1 - 2^-20);
+      'cdf'    distance of the target to the nearest running-sum boundary,
+               relative to the row sum.
+    flip = i takes decision i the other way (the floor of q on the other side
+    of the nearest integer; the other accept outcome; the entry across the
+    nearest boundary): what the walk does when the compared values round the
+    other way."""
+    rowptr, col, x, xmax, _ = _device_weights(lap)
+    deg = np.diff(rowptr)
+    norm = lap.kind == SYM_NORMALIZED
+    d32 = lap.degree.astype(np.float32).astype(np.float64)
+    decisions = []
+
+    def flipped():
+        return flip is not None and len(decisions) == flip
+
+    def u53(step):
+        return float(rng.uniform53(seed, r, w, counter, step)[()])
+
+    z, t, m = int(r), 0, 0
+    while deg[z] > 0:
+        pm = 1.0 / ell if norm else d32[z] / ell
+        with np.errstate(divide="ignore"):
+            q = float(np.log(1.0 - u53(m)) / np.log1p(-pm))
+        near = float(np.rint(q))
+        g = np.floor(q)
+        if flipped():
+            g = near - 1.0 if q >= near else near
+        decisions.append(("gap", abs(q - near) / max(1.0, abs(q)) if np.isfinite(q) else np.inf))
+        m += 1
+        if not g < ell - t:
+            break
+        t += int(g) + 1
+        a0 = int(rowptr[z])
+        chosen = -1
+        for a in range(_ATTEMPTS):
+            cand = int(rng.bounded(seed, r, w, counter, 256 + 1024 * t + a, int(deg[z]))[0])
+            ratio = x[a0 + cand] / xmax[z]
+            if ratio >= _EQUAL:
+                ok = True
+            else:
+                u2 = u53((1 << 20) + 1024 * t + a)
+                ok = u2 < ratio
+                if flipped():
+                    ok = not ok
+                decisions.append(("accept", abs(u2 - ratio) / ratio))
+            if ok:
+                chosen = a0 + cand
+                break
+        if chosen < 0:
+            run = np.cumsum(x[a0:a0 + deg[z]])
+            target = u53((1 << 21) + t) * run[-1]
+            hit = np.nonzero(run > target)[0]
+            i = int(hit[0]) if hit.size else int(deg[z]) - 1
+            lo = run[i - 1] if i > 0 else -np.inf
+            above = abs(run[i] - target) <= abs(target - lo)
+            if flipped():
+                i = min(i + 1, int(deg[z]) - 1) if above else max(i - 1, 0)
+            decisions.append(("cdf", min(abs(run[i] - target), abs(target - lo)) / run[-1]))
+            chosen = a0 + i
+        z = int(col[chosen])
+    return z, decisions
+
+
+def row_from_ends(lap: Laplacian, r: int, ends, V):
+    """Row r of the estimate from its walks' end nodes (weights s_Z / s_r in
+    the stored float32 scales; 1 for the combinatorial Laplacian)."""
+    _, _, _, _, s32 = _device_weights(lap)
+    V = np.asarray(V, dtype=np.float64)
+    ends = np.asarray(ends, dtype=np.int64)
+    wgt = s32[ends].astype(np.float64) / float(s32[r]) if s32[r] > 0 else np.ones(len(ends))
+    return (wgt[:, None] * V[ends]).mean(axis=0)
+
+
 def lazy_walk_matrix(lap: Laplacian, ell: int):
     """The dense lazy-walk transition matrix P of the module header (for
     checking the similarity to I - L/l)."""

@@ -18,6 +18,7 @@ Readings where the paper is silent:
 from __future__ import annotations
 
 from dataclasses import dataclass
+from fractions import Fraction
 from math import comb, factorial
 
 import numpy as np
@@ -56,8 +57,10 @@ def limit_exp(ell: int) -> Poly:
 
 
 def taylor_exp(ell: int) -> Poly:
-    """Table 2 row 4: f(L) = -sum_{i<=l} (-L)^i / i!;  M = -f(L)."""
-    c = np.array([(-1.0) ** i / factorial(i) for i in range(ell + 1)])
+    """Table 2 row 4: f(L) = -sum_{i<=l} (-L)^i / i!;  M = -f(L).  1/i! is
+    rounded once from the exact rational (it falls below the double range for
+    large i, e.g. the degree 251 of the experiments, and then rounds to 0)."""
+    c = np.array([(-1.0) ** i * float(Fraction(1, factorial(i))) for i in range(ell + 1)])
     return Poly(c, name=f"texp{ell}")
 
 

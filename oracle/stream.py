@@ -18,6 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import rng
+
 COMBINATORIAL = "combinatorial"
 SYM_NORMALIZED = "sym"
 
@@ -57,39 +59,50 @@ def edge_batch_apply(n, src, dst, w, scale, V):
     return Y
 
 
-def _cholqr2(V):
-    for _ in range(2):
-        R = np.linalg.cholesky(V.T @ V).T
-        V = np.linalg.solve(R.T, V.T).T
-    return V
+def _orth(V):
+    """Orthonormal basis of span(V) by Householder QR, signs fixed so that R
+    has a positive diagonal (the factor a Cholesky QR would give)."""
+    Q, R = np.linalg.qr(V)
+    return Q * np.where(np.diag(R) < 0, -1.0, 1.0)
 
 
-def cyclic_batch(m, start, j, batch):
-    """Indices of batch j: edges (start + j batch + r) mod m, r < batch."""
-    return (start + j * batch + np.arange(batch)) % m
+def batch_offsets(seed, m, first, count):
+    """Start offsets o_J in [0, m) of batches J = first .. first + count - 1:
+    Lemire's bounded draw from Philox4x32-10 keyed by seed, counter
+    (J mod 2^32, J >> 32, 0, 0)."""
+    J = np.arange(first, first + count, dtype=np.uint64)
+    return rng.bounded(seed, J & np.uint64(0xFFFFFFFF), J >> np.uint64(32), 0, 0, m)
 
 
-def minibatch_oja(n, src, dst, w, scale, degree, lambda_bound, V0, batch, eta, iters, start=0):
-    """Oja steps V <- orth(V + eta M_hat V) (Sec. 5's update; orth by two
-    Cholesky QR passes) with M_hat from consecutive batches of the edge list
-    taken cyclically, each scaled by m / batch (Sec. 3: edge vectors fed in
-    minibatches).  degree 0: M_hat V = lambda_bound V - L_B V; degree l:
-    (I - L_{B_l} / l) ... (I - L_{B_1} / l) V with a fresh batch per factor,
-    so the product is an unbiased estimate of (I - L/l)^l V."""
+def drawn_batch(m, offset, batch):
+    """Indices of the batch that starts at `offset`: (offset + r) mod m, r < batch."""
+    return (int(offset) + np.arange(batch)) % m
+
+
+def minibatch_oja(n, src, dst, w, scale, degree, lambda_bound, V0, batch, eta, iters, seed=0, batch0=0):
+    """Oja steps V <- orth(V + eta M_hat V) (Sec. 5's update) with M_hat from
+    edge batches, each scaled by m / batch (Sec. 3: edge vectors fed in
+    minibatches).  Batch J (J = batch0, batch0 + 1, ... in order) is the run
+    of `batch` edges from a uniform random offset (batch_offsets), so every
+    edge is in it with probability batch / m and different batches are
+    independent.  degree 0: M_hat V = lambda_bound V - L_B V; degree l:
+    (I - L_{B_l} / l) ... (I - L_{B_1} / l) V with its own batch per factor,
+    whose independence makes E[M_hat] = (I - L/l)^l."""
     src = np.asarray(src, dtype=np.int64)
     dst = np.asarray(dst, dtype=np.int64)
     wt = None if w is None else np.asarray(w, dtype=np.float64)
     m = len(src)
     V = np.asarray(V0, dtype=np.float64).copy()
     F = 1 if degree == 0 else degree
+    offs = batch_offsets(seed, m, batch0, iters * F)
     j = 0
     for _ in range(iters):
         W = V
         for _f in range(F):
-            idx = cyclic_batch(m, start, j, batch)
+            idx = drawn_batch(m, offs[j], batch)
             j += 1
             LB = edge_batch_apply(n, src[idx], dst[idx], None if wt is None else wt[idx], scale,
                                   V if degree == 0 else W) * (m / batch)
             W = lambda_bound * V - LB if degree == 0 else W - LB / degree
-        V = _cholqr2(V + eta * W)
+        V = _orth(V + eta * W)
     return V

@@ -185,6 +185,9 @@ extern "C" sped_status sped_transform_coeffs(int32_t transform, int32_t degree, 
     }
     case SPED_T_TAYLOR_LOG: {
       if (degree < 1 || degree > 1024) return fail(SPED_E_INVALID, "degree");
+      // Table 2 takes l odd: an even-degree truncation of the log series turns
+      // down at the top of [0, 2], so M would not reverse the spectrum.
+      if (degree % 2 == 0) return fail(SPED_E_UNSUPPORTED, "Taylor log needs an odd degree");
       if (!(eps > 0.0 && eps < 1.0)) return fail(SPED_E_INVALID, "eps outside (0, 1)");
       const double y = lambda_bound - (1.0 - eps);
       double ftop = 0.0, yp = 1.0;
@@ -200,6 +203,34 @@ extern "C" sped_status sped_transform_coeffs(int32_t transform, int32_t degree, 
     default:
       return fail(SPED_E_INVALID, "transform");
   }
+}
+
+extern "C" sped_status sped_poly_rebase(const sped_poly *p, double shift, double scale, double *out) {
+  clear_error();
+  SPED_TRY(validate_poly(p));
+  if (!out) return fail(SPED_E_INVALID, "out NULL");
+  if (!(std::isfinite(shift) && std::isfinite(scale) && scale != 0.0))
+    return fail(SPED_E_INVALID, "shift and scale must be finite, scale nonzero");
+  const int l = p->degree;
+  if (p->kind == SPED_POLY_LIMIT) {
+    // 1 - L/l = a + b Lt with a = 1 - shift/l, b = -scale/l: binomial expansion
+    const double a = 1.0 - shift / l, b = -scale / l;
+    double c = 1.0;  // C(l, i)
+    for (int i = 0; i <= l; ++i) {
+      out[i] = c * std::pow(a, l - i) * std::pow(b, i);
+      c = c * double(l - i) / double(i + 1);
+    }
+    return SPED_OK;
+  }
+  // monomial in L first, then L = scale Lt + shift: Horner in the new variable
+  std::vector<double> m = monomial_in_L(*p);
+  std::vector<double> acc(size_t(l) + 1, 0.0);
+  for (int j = l; j >= 0; --j) {  // acc <- acc * (scale Lt + shift) + m_j
+    for (int i = l; i >= 1; --i) acc[i] = acc[i] * shift + acc[i - 1] * scale;
+    acc[0] = acc[0] * shift + m[j];
+  }
+  for (int i = 0; i <= l; ++i) out[i] = acc[i];
+  return SPED_OK;
 }
 
 extern "C" sped_status sped_poly_monomial(const sped_poly *p, double *out) {

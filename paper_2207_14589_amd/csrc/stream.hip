@@ -206,10 +206,13 @@ sped_status stream_segments(int64_t nbatches, const int32_t *src_h, const int32_
     // still read the staging buffers
     hip_ok(hipEventRecord(used[0], s), "hipEventRecord");
     hip_ok(hipEventRecord(used[1], s), "hipEventRecord");
-    for (int64_t j = 0; j < nbatches && st == SPED_OK; ++j) {
+    int64_t count[2] = {0, 0};
+    // Enqueue batch j's copy into buffer j & 1 on the copy stream, after the
+    // kernels that last read that buffer (batch j - 2's).
+    auto issue_copy = [&](int64_t j) {
       const int buf = int(j & 1);
       const Segs g = seg(j);
-      if (!hip_ok(hipStreamWaitEvent(cs, used[buf], 0), "hipStreamWaitEvent")) break;
+      if (!hip_ok(hipStreamWaitEvent(cs, used[buf], 0), "hipStreamWaitEvent")) return;
       int64_t at = 0;
       for (int q = 0; q < 2 && st == SPED_OK; ++q) {
         if (g.cnt[q] == 0) continue;
@@ -222,11 +225,18 @@ sped_status stream_segments(int64_t nbatches, const int32_t *src_h, const int32_
                                 cs), "hipMemcpyAsync");
         at += g.cnt[q];
       }
+      count[buf] = at;
+      hip_ok(hipEventRecord(copied[buf], cs), "hipEventRecord");
+    };
+    if (nbatches > 0) issue_copy(0);
+    for (int64_t j = 0; j < nbatches && st == SPED_OK; ++j) {
+      const int buf = int(j & 1);
+      if (!hip_ok(hipStreamWaitEvent(s, copied[buf], 0), "hipStreamWaitEvent")) break;
+      // One batch ahead: batch j + 1's copy is queued before batch j's
+      // kernels, so it overlaps them even when the body synchronises.
+      if (j + 1 < nbatches) issue_copy(j + 1);
       if (st != SPED_OK) break;
-      if (!hip_ok(hipEventRecord(copied[buf], cs), "hipEventRecord") ||
-          !hip_ok(hipStreamWaitEvent(s, copied[buf], 0), "hipStreamWaitEvent"))
-        break;
-      const sped_status kst = body(j, stage_src[buf], stage_dst[buf], w_h ? stage_w[buf] : nullptr, at);
+      const sped_status kst = body(j, stage_src[buf], stage_dst[buf], w_h ? stage_w[buf] : nullptr, count[buf]);
       if (kst != SPED_OK) {
         st = kst;
         break;
@@ -380,7 +390,8 @@ extern "C" sped_status sped_stream_laplacian_apply(int64_t n, int64_t m, const i
 extern "C" sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *src_h, const int32_t *dst_h,
                                           const float *w_h, const float *scale, int32_t degree, double lambda_bound,
                                           int64_t k, float *V, int64_t ldv, int64_t batch, double eta, int32_t iters,
-                                          int64_t start, void *ws, size_t *ws_bytes, sped_stream_t stream) {
+                                          uint64_t seed, int64_t batch0, void *ws, size_t *ws_bytes,
+                                          sped_stream_t stream) {
   clear_error();
   if (n < 1 || n >= (int64_t(1) << 31)) return fail(SPED_E_INVALID, "n out of range");
   if (k < 1 || k > 96) return fail(SPED_E_UNSUPPORTED, "k outside [1, 96]");
@@ -392,7 +403,8 @@ extern "C" sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *s
   if (degree == 0 && !(std::isfinite(lambda_bound) && lambda_bound > 0.0)) return fail(SPED_E_INVALID, "lambda_bound");
   if (!(std::isfinite(eta) && eta > 0.0)) return fail(SPED_E_INVALID, "eta");
   if (iters < 0) return fail(SPED_E_INVALID, "iters < 0");
-  if (start < 0) return fail(SPED_E_INVALID, "start < 0");
+  if (m >= (int64_t(1) << 32)) return fail(SPED_E_UNSUPPORTED, "m >= 2^32 edges");
+  if (batch0 < 0) return fail(SPED_E_INVALID, "batch0 < 0");
   StreamWs w;
   Carver c(ws);
   const size_t stage = carve_stream_ws(ws, batch, &w);
@@ -414,13 +426,19 @@ extern "C" sped_status sped_minibatch_oja(int64_t n, int64_t m, const int32_t *s
   const unsigned blocks = grid_blocks(n * k);
   const float a = degree == 0 ? float(-double(m) / double(batch)) : float(-double(m) / double(batch) / F);
   float *cur = W0, *nxt = W1;
-  int64_t next_off = start % m;  // batch j: edges (start + j batch + r) mod m, r < batch
+  // Batch j of the call (global index J = batch0 + j) holds the edges
+  // (o_J + r) mod m, r < batch, from a uniform offset o_J in [0, m) drawn by
+  // Philox (key = seed, counter (J mod 2^32, J >> 32, 0, 0)) with Lemire's
+  // bound: each edge is in a batch with probability batch / m, and the
+  // batches of different factors are independent, so the product of the
+  // factors' estimates has the product of their expectations as its mean.
+  const uint32_t k0 = uint32_t(seed), k1 = uint32_t(seed >> 32);
   const sped_status st = stream_segments(
       int64_t(iters) * F, src_h, dst_h, w_h, w.src, w.dst, w.w, s,
-      [&](int64_t) {  // called once per batch, in order
-        const int64_t o = next_off;
+      [&](int64_t j) {
+        const uint64_t J = uint64_t(batch0 + j);
+        const int64_t o = int64_t(lemire_draw(k0, k1, uint32_t(J), uint32_t(J >> 32), 0u, 0u, uint32_t(m)));
         const int64_t first = std::min(batch, m - o);
-        next_off = (o + batch) % m;
         Segs sg{{o, 0}, {first, batch - first}};
         return sg;
       },

@@ -59,6 +59,7 @@ SIGNATURES = {
                            _P(_c_sz), _c_vp],
     "sped_transform_coeffs": [_c_i32, _c_i32, _c_f64, _c_f64, _P(_c_f64), _P(_c_f64), _P(_c_f64)],
     "sped_poly_monomial": [_P(Poly), _P(_c_f64)],
+    "sped_poly_rebase": [_P(Poly), _c_f64, _c_f64, _P(_c_f64)],
     "sped_apply_poly": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp,
                         _P(_c_sz), _c_vp],
     "sped_apply_poly_stochastic": [_P(CSR), _P(_c_f64), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
@@ -83,7 +84,7 @@ SIGNATURES = {
     "sped_stream_laplacian_apply": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32,
                                     _c_vp, _c_i64, ctypes.c_float, _c_i32, _c_i64, _c_vp, _P(_c_sz), _c_vp],
     "sped_minibatch_oja": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_vp, _c_i32, _c_f64, _c_i64, _c_vp, _c_i64,
-                           _c_i64, _c_f64, _c_i32, _c_i64, _c_vp, _P(_c_sz), _c_vp],
+                           _c_i64, _c_f64, _c_i32, _c_u64, _c_i64, _c_vp, _P(_c_sz), _c_vp],
     "sped_stream_copy": [_c_vp, _c_vp, _c_sz, _c_vp],
     "sped_gather_probe": [_c_vp, _c_i64, _c_i32, _c_i32, _c_i32, _c_vp, _c_vp],
     "sped_last_error": [],
@@ -245,6 +246,14 @@ class PolySpec:
         p = self.struct()
         _check(lib().sped_poly_monomial(ctypes.byref(p), out.ctypes.data_as(ctypes.POINTER(_c_f64))),
                "sped_poly_monomial")
+        return out
+
+    def rebase(self, shift, scale):
+        """Coefficients of the same polynomial in Lt = (L - shift I) / scale."""
+        out = np.zeros(self.degree + 1)
+        p = self.struct()
+        _check(lib().sped_poly_rebase(ctypes.byref(p), float(shift), float(scale),
+                                      out.ctypes.data_as(ctypes.POINTER(_c_f64))), "sped_poly_rebase")
         return out
 
 
@@ -414,15 +423,55 @@ def _host_edges(src_h, dst_h, w_h):
     return src_h, dst_h, (None if w_h is None else chk(w_h, torch.float32, "w"))
 
 
+def _device_block(X, name, dtype=None):
+    """X must be a 2-D CUDA tensor with unit column stride (rows may be
+    padded: the leading dimension is passed), of dtype float32/bfloat16 or the
+    one given."""
+    if not isinstance(X, torch.Tensor) or X.device.type != "cuda" or X.dim() != 2 or \
+            (X.shape[0] > 0 and X.stride(1) != 1):
+        raise TypeError(f"{name} must be a 2-D CUDA tensor with contiguous rows")
+    ok = (X.dtype == dtype) if dtype is not None else X.dtype in (torch.float32, torch.bfloat16)
+    if not ok:
+        raise TypeError(f"{name} has dtype {X.dtype}")
+
+
+def _device_vector(t, name, dtype, min_len, device):
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if t.numel() < min_len:
+        raise ValueError(f"{name} has {t.numel()} elements, needs at least {min_len}")
+
+
 def edge_apply(n, src, dst, X, w=None, scale=None, alpha=1.0, out=None, invalid=None):
     """out += alpha sum_e x_e x_e^T X over a batch of DEVICE edges (int32 src,
     dst; float32 w or None; node scales or None for the combinatorial L).
     out is float32 n x k (a new zero block when None); invalid is an optional
-    DEVICE int64 counter of skipped edges."""
+    DEVICE int64 counter of skipped edges.  Every tensor must sit on X's
+    device with the dtype and length named; violations raise before the
+    library is called."""
+    _device_block(X, "X")
     k = X.shape[1]
+    if X.shape[0] < int(n):
+        raise ValueError("X has fewer than n rows")
+    m = src.numel() if isinstance(src, torch.Tensor) else -1
+    _device_vector(src, "src", torch.int32, 0, X.device)
+    _device_vector(dst, "dst", torch.int32, m, X.device)
+    if dst.numel() != m:
+        raise ValueError("src and dst differ in length")
+    if w is not None:
+        _device_vector(w, "w", torch.float32, m, X.device)
+        if w.numel() != m:
+            raise ValueError("w and src differ in length")
+    if scale is not None:
+        _device_vector(scale, "scale", torch.float32, int(n), X.device)
+    if invalid is not None:
+        _device_vector(invalid, "invalid", torch.int64, 1, X.device)
     if out is None:
         out = torch.zeros(n, k, dtype=torch.float32, device=X.device)
-    _check(lib().sped_edge_apply(int(n), src.numel(), _ptr(src), _ptr(dst), _ptr(w), _ptr(scale), k, _ptr(X), _ld(X),
+    _device_block(out, "out", torch.float32)
+    if out.device != X.device or out.shape[0] < int(n) or out.shape[1] != k:
+        raise ValueError("out must be a float32 block of n x k on X's device")
+    _check(lib().sped_edge_apply(int(n), m, _ptr(src), _ptr(dst), _ptr(w), _ptr(scale), k, _ptr(X), _ld(X),
                                  _dt(X), _ptr(out), _ld(out), float(alpha), _ptr(invalid), _stream(X.device)),
            "sped_edge_apply")
     return out
@@ -448,10 +497,18 @@ def stream_laplacian_apply(n, src_h, dst_h, X, w_h=None, scale=None, alpha=1.0, 
     (accumulate: added to out).  scale: node scales (DEVICE) or None for the
     combinatorial Laplacian.  Returns the float32 n x k result."""
     src_h, dst_h, w_h = _host_edges(src_h, dst_h, w_h)
+    _device_block(X, "X")
     k = X.shape[1]
+    if X.shape[0] < int(n):
+        raise ValueError("X has fewer than n rows")
+    if scale is not None:
+        _device_vector(scale, "scale", torch.float32, int(n), X.device)
     if out is None:
         out = torch.empty(int(n), k, dtype=torch.float32, device=X.device)
         accumulate = False
+    _device_block(out, "out", torch.float32)
+    if out.device != X.device or out.shape[0] < int(n) or out.shape[1] != k:
+        raise ValueError("out must be a float32 block of n x k on X's device")
     _call_ws(lib().sped_stream_laplacian_apply, "sped_stream_laplacian_apply",
              (int(n), src_h.numel(), _c_vp(src_h.data_ptr()), _c_vp(dst_h.data_ptr()),
               _c_vp(w_h.data_ptr() if w_h is not None else None), _ptr(scale), k, _ptr(X), _ld(X), _dt(X),
@@ -460,18 +517,20 @@ def stream_laplacian_apply(n, src_h, dst_h, X, w_h=None, scale=None, alpha=1.0, 
 
 
 def minibatch_oja(n, src_h, dst_h, V, w_h=None, scale=None, degree=0, lambda_bound=2.0, batch=1 << 16, eta=0.5,
-                  iters=100, start=0):
+                  iters=100, seed=0, batch0=0):
     """In place: `iters` Oja steps V <- orth(V + eta M_hat V) with M_hat from
-    consecutive batches of a HOST edge list (degree 0: lambda_bound I - L;
-    degree l: the limit polynomial (I - L/l)^l, one batch per factor).
-    V: DEVICE float32 n x k."""
+    batches of a HOST edge list, each the run of `batch` edges from a random
+    offset (Philox keyed by seed; batch0 = batches drawn by earlier calls of
+    the same solve).  degree 0: lambda_bound I - L; degree l: the limit
+    polynomial (I - L/l)^l, one batch per factor.  V: DEVICE float32 n x k."""
     src_h, dst_h, w_h = _host_edges(src_h, dst_h, w_h)
-    if V.dtype != torch.float32:
-        raise TypeError("V must be float32")
+    _device_block(V, "V", torch.float32)
+    if scale is not None:
+        _device_vector(scale, "scale", torch.float32, int(n), V.device)
     _call_ws(lib().sped_minibatch_oja, "sped_minibatch_oja",
              (int(n), src_h.numel(), _c_vp(src_h.data_ptr()), _c_vp(dst_h.data_ptr()),
               _c_vp(w_h.data_ptr() if w_h is not None else None), _ptr(scale), int(degree), float(lambda_bound),
-              V.shape[1], _ptr(V), _ld(V), int(batch), float(eta), int(iters), int(start)), V.device)
+              V.shape[1], _ptr(V), _ld(V), int(batch), float(eta), int(iters), int(seed), int(batch0)), V.device)
     return V
 
 

@@ -21,12 +21,9 @@ from .autograd import poly_apply
 
 
 def limit_in_shifted(ell: int, shift: float = 1.0, scale: float = 1.0) -> np.ndarray:
-    """Coefficients of (I - L/ell)^ell in the variable Lt = (L - shift I)/scale."""
-    from math import comb
-
-    # 1 - L/ell = (1 - shift/ell) - (scale/ell) Lt
-    a, b = 1.0 - shift / ell, -scale / ell
-    return np.array([comb(ell, i) * a ** (ell - i) * b ** i for i in range(ell + 1)])
+    """Coefficients of (I - L/ell)^ell in the variable Lt = (L - shift I)/scale
+    (computed by the library)."""
+    return sped.transform("limit", ell).rebase(shift, scale)
 
 
 def rayleigh_loss(theta, L, V0, k, unroll, shift, scale):

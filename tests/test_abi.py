@@ -43,16 +43,42 @@ def test_version_and_error_string(lib):
 
 def test_transform_coeffs_match_table2(lib):
     lam = 2.0
-    for ell in (3, 8, 16):
+    for ell in (3, 8, 16, 251):
         np.testing.assert_allclose(sped.transform("limit", ell, lam, product_form=False).coeffs,
                                    opoly.limit_exp(ell).coeffs, rtol=1e-14, atol=1e-300)
         np.testing.assert_allclose(sped.transform("taylor_exp", ell, lam).coeffs, opoly.taylor_exp(ell).coeffs,
-                                   rtol=1e-14)
+                                   rtol=1e-14, atol=1e-320)
+    for ell in (3, 9, 15):
         t = sped.transform("taylor_log", ell, lam, eps=1e-3)
         o = opoly.taylor_log(ell, lam, 1e-3)
         np.testing.assert_allclose(t.coeffs, o.coeffs, rtol=1e-13)
         assert t.shift == pytest.approx(o.shift)
     np.testing.assert_allclose(sped.transform("plain", 1, 3.5).coeffs, [3.5, -1.0])
+
+
+@pytest.mark.parametrize("ell", [2, 8, 16])
+def test_even_taylor_log_rejected(lib, ell):
+    """Table 2 takes l odd: the even-degree log series is not increasing on
+    [0, 2] (the oracle's test_even_log_not_monotone), so it is refused."""
+    out = np.zeros(ell + 1)
+    sh, sc = ctypes.c_double(), ctypes.c_double()
+    assert lib.sped_transform_coeffs(sped.T_TAYLOR_LOG, ell, 2.0, 1e-3,
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.byref(sh), ctypes.byref(sc)) == sped.E_UNSUPPORTED
+    assert b"odd" in lib.sped_last_error()
+
+
+@pytest.mark.parametrize("shift,scale", [(1.0, 1.0), (0.5, 2.0), (0.0, 1.0)])
+def test_poly_rebase(lib, shift, scale):
+    """Rebased coefficients evaluate to the same polynomial: sum_i out_i
+    ((lam - shift)/scale)^i against the oracle's Table 2 rows on [0, 2]."""
+    lam = np.linspace(0.0, 2.0, 41)
+    y = (lam - shift) / scale
+    for spec, ref in ((sped.transform("limit", 12), opoly.limit_exp(12)),
+                      (sped.transform("taylor_log", 7, 2.0), opoly.taylor_log(7, 2.0)),
+                      (sped.transform("taylor_exp", 9), opoly.taylor_exp(9))):
+        c = spec.rebase(shift, scale)
+        np.testing.assert_allclose(np.polynomial.polynomial.polyval(y, c), ref(lam), rtol=1e-11, atol=1e-12)
 
 
 def test_monomial_expansion(lib):
@@ -200,12 +226,37 @@ def test_minibatch_oja_validation(lib):
     f = lib.sped_minibatch_oja
     need = ctypes.c_size_t(0)
     q = ctypes.byref(need)
-    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 51, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # batch > m
-    assert f(100, 50, s, d, None, None, 8, 2.0, 97, V, 97, 10, 0.5, 3, 0, None, q, None) == sped.E_UNSUPPORTED
-    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 9, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID   # ldv < k
-    assert f(100, 50, s, d, None, None, 0, 0.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # lambda
-    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.0, 3, 0, None, q, None) == sped.E_INVALID  # eta
-    assert f(100, 50, s, d, None, None, -1, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID  # degree
-    assert f(100, 0, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.E_INVALID   # m = 0
-    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, None, q, None) == sped.OK
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 51, 0.5, 3, 0, 0, None, q, None) == sped.E_INVALID  # batch > m
+    assert f(100, 50, s, d, None, None, 8, 2.0, 97, V, 97, 10, 0.5, 3, 0, 0, None, q, None) == sped.E_UNSUPPORTED
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 9, 10, 0.5, 3, 0, 0, None, q, None) == sped.E_INVALID   # ldv < k
+    assert f(100, 50, s, d, None, None, 0, 0.0, 10, V, 10, 10, 0.5, 3, 0, 0, None, q, None) == sped.E_INVALID  # lambda
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.0, 3, 0, 0, None, q, None) == sped.E_INVALID  # eta
+    assert f(100, 50, s, d, None, None, -1, 2.0, 10, V, 10, 10, 0.5, 3, 0, 0, None, q, None) == sped.E_INVALID  # degree
+    assert f(100, 0, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, 0, None, q, None) == sped.E_INVALID   # m = 0
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, -1, None, q, None) == sped.E_INVALID  # batch0
+    assert f(100, 50, s, d, None, None, 8, 2.0, 10, V, 10, 10, 0.5, 3, 0, 0, None, q, None) == sped.OK
     assert need.value >= 2 * 100 * 10 * 4 + 2 * 10 * 12
+
+
+def test_edge_apply_binding_rejects_bad_tensors(lib):
+    """The binding checks device, dtype and length of every tensor before it
+    hands raw pointers to the library (a host tensor or a short array would
+    otherwise be dereferenced by a kernel)."""
+    import torch
+    X = torch.zeros(10, 4)
+    with pytest.raises(TypeError):
+        sped.edge_apply(10, torch.zeros(3, dtype=torch.int32), torch.zeros(3, dtype=torch.int32), X)
+    with pytest.raises(TypeError):
+        sped.stream_laplacian_apply(10, torch.zeros(3, dtype=torch.int32), torch.zeros(3, dtype=torch.int32), X)
+    with pytest.raises(TypeError):
+        sped.minibatch_oja(10, torch.zeros(3, dtype=torch.int32), torch.zeros(3, dtype=torch.int32), X)
+    cpu = torch.device("cpu")
+    with pytest.raises(TypeError):
+        sped._device_vector(torch.zeros(3, dtype=torch.int64), "src", torch.int32, 0, cpu)
+    with pytest.raises(ValueError):
+        sped._device_vector(torch.zeros(3, dtype=torch.float32), "scale", torch.float32, 10, cpu)
+    with pytest.raises(TypeError):
+        sped._device_vector(torch.zeros(6, dtype=torch.int32)[::2], "dst", torch.int32, 3, cpu)
+    sped._device_vector(torch.zeros(10, dtype=torch.float32), "scale", torch.float32, 10, cpu)
+    with pytest.raises(TypeError):
+        sped._device_block(torch.zeros(4, 3, dtype=torch.float64), "X")

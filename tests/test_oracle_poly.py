@@ -113,3 +113,93 @@ def test_reversal_maps_bottom_k_to_top_k():
         mu, W = np.linalg.eigh(0.5 * (M + M.T))
         top = W[:, -k:]
         assert np.linalg.norm(top - U[:, :k] @ (U[:, :k].T @ top), 2) < 1e-8
+
+
+# ----------------------------------------------------------- exact transforms (Table 2 rows 1 and 3)
+def _closed_form_pairs(kind, n=40):
+    """Closed-form eigenpairs of the path and cycle graphs (orthonormal columns)."""
+    out = []
+    x = np.arange(n)
+    _, s, d = synth.path_graph(n)
+    lap = olap.laplacian(n, s, d, kind=kind)
+    V, lam = [], []
+    for j in range(0, n, 5):
+        if kind == olap.COMBINATORIAL:
+            V.append(np.cos(np.pi * j * (x + 0.5) / n))
+            lam.append(2 - 2 * np.cos(np.pi * j / n))
+        else:
+            V.append(np.sqrt(lap.degree) * np.cos(np.pi * j * x / (n - 1)))
+            lam.append(1 - np.cos(np.pi * j / (n - 1)))
+    out.append((lap, np.stack(V, 1), np.array(lam)))
+    _, s, d = synth.cycle_graph(n)
+    lap = olap.laplacian(n, s, d, kind=kind)
+    V, lam = [], []
+    for j in range(0, n // 2 + 1, 3):  # cos(2 pi j x / n), eigenvalue 2 - 2 cos(2 pi j / n) (halved if normalised)
+        V.append(np.cos(2 * np.pi * j * x / n))
+        mu = 2 - 2 * np.cos(2 * np.pi * j / n)
+        lam.append(mu if kind == olap.COMBINATORIAL else mu / 2)
+    out.append((lap, np.stack(V, 1), np.array(lam)))
+    return out
+
+
+@pytest.mark.parametrize("kind", [olap.COMBINATORIAL, olap.SYM_NORMALIZED])
+def test_exact_transforms_on_closed_form_spectra(kind):
+    """Table 2 rows 1 and 3 applied through the eigendecomposition act on the
+    closed-form eigenvectors of the path and cycle graphs as f(lambda):
+    log(L + eps) v = log(lambda + eps) v and -exp(-L) v = -exp(-lambda) v.
+    The cycle's eigenvalues are double, so this also checks that a repeated
+    eigenvalue's whole eigenspace gets the same factor."""
+    eps = 1e-3
+    for lap, V, lam in _closed_form_pairs(kind):
+        Ld = lap.dense()
+        np.testing.assert_allclose(Ld @ V, V * lam, atol=1e-12 * max(1.0, np.abs(V).max()))
+        Y = opoly.apply_spectral(Ld, opoly.exact_log(eps), V)
+        np.testing.assert_allclose(Y, V * np.log(lam + eps), atol=1e-11 * np.abs(V).max())
+        Y = opoly.apply_spectral(Ld, opoly.exact_negexp(), V)
+        np.testing.assert_allclose(Y, -V * np.exp(-lam), atol=1e-12 * np.abs(V).max())
+
+
+def test_exact_transforms_match_matrix_functions():
+    """The same transforms against scipy's matrix exponential (scaling and
+    squaring with Pade approximants) and matrix logarithm (inverse scaling and
+    squaring), which never form an eigendecomposition: -exp(-L) = -expm(-L),
+    log(L + eps I) = logm(L + eps I)."""
+    from scipy.linalg import expm, logm
+
+    n, s, d, _ = synth.sbm_bernoulli([12, 15, 9], 0.5, 0.05, seed=21)
+    for kind in (olap.SYM_NORMALIZED, olap.COMBINATORIAL):
+        Ld = olap.laplacian(n, s, d, kind=kind).dense()
+        V = synth.gaussian_block(n, 4, seed=5)
+        np.testing.assert_allclose(opoly.apply_spectral(Ld, opoly.exact_negexp(), V), -expm(-Ld) @ V,
+                                   atol=1e-12 * np.abs(V).max())
+        eps = 1e-3
+        Lg = np.real(logm(Ld + eps * np.eye(n)))
+        np.testing.assert_allclose(opoly.apply_spectral(Ld, opoly.exact_log(eps), V), Lg @ V,
+                                   atol=1e-9 * np.abs(Lg @ V).max())
+
+
+def test_series_forms_converge_to_exact_negexp():
+    """Table 2's series rows approximate row 3: the degree-30 Taylor series of
+    exp(-lam) is within its Lagrange remainder of the exact transform on [0, 2],
+    and the limit form (1 - lam/l)^l approaches exp(-lam) from below with
+    0 <= exp(-lam) - (1 - lam/l)^l <= lam^2 exp(-lam) / (2 (l - lam)) for lam < l."""
+    f = opoly.exact_negexp()
+    assert np.abs(opoly.taylor_exp(30)(LAM) + f(LAM)).max() <= 2.0 ** 31 / factorial(31) + 1e-15
+    for ell in (16, 64, 251):
+        gap = -f(LAM) - opoly.limit_exp(ell)(LAM)
+        assert gap.min() >= -1e-15
+        assert np.all(gap <= LAM ** 2 * np.exp(-LAM) / (2 * (ell - LAM)) + 1e-15)
+
+
+def test_exact_transforms_reverse_the_spectrum():
+    """Sec. 4.1: both exact transforms are increasing, so the reversed
+    operators lambda* - f(L) (lambda* = f(lambda_bound) for the log, 0 for
+    -exp(-L)) are decreasing, nonnegative on [0, lambda_bound], and keep the
+    bottom-k eigenvectors on top."""
+    lam = np.linspace(0.0, 2.0, 2001)
+    for f, lam_star in ((opoly.exact_log(1e-3), opoly.exact_log(1e-3)(2.0)), (opoly.exact_negexp(), 0.0)):
+        M = lam_star - f(lam)
+        assert np.all(np.diff(M) < 0) and M.min() >= -1e-15
+    # the log dilates the bottom of the spectrum: ratio of M's gaps near 0 vs near 2
+    g = opoly.exact_log(1e-3)
+    assert (g(0.02) - g(0.01)) / (g(1.99) - g(1.98)) > 50

@@ -263,6 +263,59 @@ def test_lazy_walk_skewed_weights_use_the_exact_fallback():
     np.testing.assert_allclose(est[0], exact[0], atol=0.02 * np.abs(exact).max())
 
 
+def _skewed_hub(kind=olap.SYM_NORMALIZED):
+    n = 9
+    src = np.zeros(8, dtype=np.int64)
+    dst = np.arange(1, 9)
+    w = np.array([1.0] + [1e-6] * 7)
+    return olap.laplacian(n, src, dst, w, kind=kind)
+
+
+@pytest.mark.parametrize("case", ["sym", "combinatorial", "skewed_hub"])
+def test_lazy_walk_single_path_matches_estimate(case):
+    """The step-by-step walk (walk_path, used to re-check single rows) takes
+    the same draws and decisions as the vectorised estimator: the rows built
+    from its end nodes equal estimate_lazy's rows, on a weighted graph of each
+    Laplacian and on a hub whose weights force the inverse-CDF fallback."""
+    if case == "skewed_hub":
+        lap, ell = _skewed_hub(), 3
+    else:
+        kind = olap.SYM_NORMALIZED if case == "sym" else olap.COMBINATORIAL
+        lap = _weighted_small(kind, seed=2)
+        ell = 7 if kind == olap.SYM_NORMALIZED else int(np.ceil(lap.degree.max()))
+    V = np.random.default_rng(8).standard_normal((lap.n, 3))
+    walks = 16
+    est = olazy.estimate_lazy(lap, ell, V, walks, seed=4, counter=2)
+    kinds = set()
+    for r in range(lap.n):
+        ends = []
+        for w in range(walks):
+            z, dec = olazy.walk_path(lap, ell, r, w, seed=4, counter=2)
+            ends.append(z)
+            kinds.update(k for k, _ in dec)
+        np.testing.assert_allclose(olazy.row_from_ends(lap, r, ends, V), est[r], rtol=1e-14, atol=1e-15)
+    assert "gap" in kinds and ("accept" in kinds or case == "combinatorial")
+    if case == "skewed_hub":
+        assert "cdf" in kinds
+
+
+def test_lazy_walk_flip_changes_one_decision():
+    """Flipping decision i of a walk leaves decisions 0..i-1 as they were and
+    takes decision i the other way, which moves the walk elsewhere for at
+    least one flip of each kind seen."""
+    lap = _skewed_hub()
+    moved = set()
+    for r in range(lap.n):
+        for w in range(8):
+            z, dec = olazy.walk_path(lap, 3, r, w, seed=4)
+            for i, (kind, _) in enumerate(dec):
+                z2, dec2 = olazy.walk_path(lap, 3, r, w, seed=4, flip=i)
+                assert dec2[:i] == dec[:i] and dec2[i][0] == kind
+                if z2 != z:
+                    moved.add(kind)
+    assert {"gap", "cdf"} <= moved
+
+
 def test_lazy_walk_error_below_edge_walks():
     """Same walks-per-row budget on the 2,000-node SBM, (I - L/16)^16 applied
     to a block near the bottom eigenvectors (a solver iterate): the lazy node

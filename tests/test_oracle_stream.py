@@ -111,10 +111,13 @@ def test_minibatch_oja_full_batch_limit_step_is_the_limit_product():
     np.testing.assert_allclose(V.T @ V, np.eye(4), atol=1e-12)
 
 
-def test_minibatch_oja_fixed_point_and_cyclic_batches():
+def test_minibatch_oja_fixed_point_and_drawn_batches():
     """The bottom eigenvectors are a fixed point of the full-batch plain step
-    (lambda I - L keeps them, orth keeps their span); a batch that wraps past
-    the end of the list takes the last edges then the first ones."""
+    (lambda I - L keeps them, orth keeps their span); a batch that starts near
+    the end of the list wraps to its first edges; the solver's steps equal the
+    same factors applied by hand with a textbook QR, batch J starting at the
+    J-th drawn offset, and a solve split in two calls (batch0 = batches drawn
+    before) continues the same stream."""
     from oracle import solver as osol
     n, src, dst, w = small_graph()
     _, s = ost.node_scales(n, src, dst, w)
@@ -124,19 +127,60 @@ def test_minibatch_oja_fixed_point_and_cyclic_batches():
     V = ost.minibatch_oja(n, src, dst, w, s, 0, 2.0, U, batch=len(src), eta=0.5, iters=5)
     assert osol.max_principal_angle(U, V) < 1e-10
     m = len(src)
-    np.testing.assert_array_equal(ost.cyclic_batch(m, m - 3, 0, 5), [m - 3, m - 2, m - 1, 0, 1])
-    np.testing.assert_array_equal(ost.cyclic_batch(m, m - 3, 1, 5), [2, 3, 4, 5, 6])
-    # two limit-polynomial steps (degree 2) whose batches wrap, against the
-    # same factors applied step by step with a textbook QR
+    np.testing.assert_array_equal(ost.drawn_batch(m, m - 3, 5), [m - 3, m - 2, m - 1, 0, 1])
+    offs = ost.batch_offsets(17, m, 0, 400)
+    assert offs.min() >= 0 and offs.max() < m and len(np.unique(offs)) == m   # every offset drawn
     V0 = np.linalg.qr(np.random.default_rng(4).standard_normal((n, 2)))[0]
-    Va = ost.minibatch_oja(n, src, dst, w, s, 2, 2.0, V0, batch=5, eta=0.3, iters=2, start=m - 3)
+    Va = ost.minibatch_oja(n, src, dst, w, s, 2, 2.0, V0, batch=5, eta=0.3, iters=3, seed=17)
     Vh = V0.copy()
     j = 0
-    for _ in range(2):
+    for _ in range(3):
         W = Vh
         for _f in range(2):
-            idx = ost.cyclic_batch(m, m - 3, j, 5)
+            idx = ost.drawn_batch(m, offs[j], 5)
             j += 1
             W = W - ost.edge_batch_apply(n, src[idx], dst[idx], w[idx], s, W) * (m / 5) / 2
         Vh = np.linalg.qr(Vh + 0.3 * W)[0]
     assert osol.max_principal_angle(Va, Vh) < 1e-10
+    V1 = ost.minibatch_oja(n, src, dst, w, s, 2, 2.0, V0, batch=5, eta=0.3, iters=1, seed=17)
+    V2 = ost.minibatch_oja(n, src, dst, w, s, 2, 2.0, V1, batch=5, eta=0.3, iters=2, seed=17, batch0=2)
+    assert osol.max_principal_angle(Va, V2) < 1e-10
+
+
+@pytest.mark.parametrize("ell,b", [(2, 1), (2, 3), (3, 2)])
+def test_drawn_batch_product_is_unbiased(ell, b):
+    """E[(I - (m/b) L_{B_l} / l) ... (I - (m/b) L_{B_1} / l)] = (I - L/l)^l when
+    each factor's batch starts at its own uniform offset: enumerate every
+    offset tuple (m^l of them) and average the product exactly.  A schedule
+    whose factors take disjoint consecutive runs of one list (without
+    replacement) fails this on the same graph."""
+    g = np.random.default_rng(7)
+    n, m = 6, 11
+    src = g.integers(0, n, m)
+    dst = (src + 1 + g.integers(0, n - 1, m)) % n
+    w = g.uniform(0.2, 1.0, m)
+    _, s = ost.node_scales(n, src, dst, w)
+    I = np.eye(n)
+    LB = [ost.edge_batch_apply(n, src[ost.drawn_batch(m, o, b)], dst[ost.drawn_batch(m, o, b)],
+                               w[ost.drawn_batch(m, o, b)], s, I) * (m / b) for o in range(m)]
+    L = incidence_laplacian(n, src, dst, w, s)
+    mean = np.zeros((n, n))
+    import itertools
+    for offs in itertools.product(range(m), repeat=ell):
+        P = I.copy()
+        for o in offs:
+            P = (I - LB[o] / ell) @ P
+        mean += P
+    mean /= m ** ell
+    exact = np.linalg.matrix_power(I - L / ell, ell)
+    np.testing.assert_allclose(mean, exact, atol=1e-12)
+    # consecutive disjoint runs of one list (the factors not independent)
+    if b * ell <= m:
+        bad = np.zeros((n, n))
+        for start in range(m):
+            P = I.copy()
+            for f in range(ell):
+                P = (I - LB[(start + f * b) % m] / ell) @ P
+            bad += P
+        bad /= m
+        assert np.abs(bad - exact).max() > 1e-3
