@@ -202,6 +202,27 @@ sped_status sped_apply_poly(const sped_csr *L, const sped_poly *p, int64_t k, co
                             void *ws, size_t *ws_bytes, sped_stream_t stream);
 
 /*
+ * sped_apply_poly_noalloc -- sped_apply_poly for callers that cannot allocate
+ * device memory or pass a workspace: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels
+ * and results (bit for bit) as sped_apply_poly, without (ws, ws_bytes).
+ * The chain's intermediate F32 blocks live in a library-owned static device
+ * array of SPED_NOALLOC_SCRATCH_BYTES (64 MiB), one per GPU, held from the
+ * library's load on that GPU until the process ends; this call allocates nothing.
+ * Limit: degree >= 3 needs two blocks of n x k floats (each rounded up to
+ * 256 bytes), degree 2 one, degree 1 none; larger n x k returns
+ * SPED_E_WORKSPACE before any launch (n k <= 8,388,608 at degree >= 3, e.g.
+ * 262,144 x 32).  Every call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (different streams or threads) race and give
+ * wrong results; serialise them.  Uses the current device's array; `stream`
+ * must belong to the current device.  Asynchronous on `stream`.
+ */
+#define SPED_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
+                                    int64_t ldx, int32_t xdt, void *Y, int64_t ldy, int32_t ydt,
+                                    sped_stream_t stream);
+
+/*
  * sped_apply_poly_stochastic -- unbiased random-walk estimate of
  * Y = sum_{i=0..degree} coeffs[i] L^i X (Sec. 4.3: eq. walk_summand, Table 1,
  * the edge-incidence graph with self-loops, rejection sampling, prefix reuse).

@@ -8,6 +8,7 @@
 // and the limit form (I - L/l)^l is l steps of U <- U - L U / l.  Intermediate
 // blocks are float32 in two workspace buffers used alternately.
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -129,6 +130,67 @@ extern "C" sped_status sped_apply_poly(const sped_csr *L, const sped_poly *p, in
   const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
   size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
   if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
+  return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, as_stream(stream), nullptr);
+}
+
+// Allocation-free form of sped_apply_poly: the chain's intermediate float32
+// blocks live in this library-owned array instead of a caller workspace.  Each
+// GPU the library runs on holds its own copy from the module's load until the
+// process ends.  In host code `scratch` names a host-side stand-in: kernels get
+// the device address that hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kScratchBytes = SPED_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+sped_status scratch_address(void **out) {
+  int dev = -1;
+  SPED_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices) return fail(SPED_E_DEVICE, "device ordinal outside the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(SPED_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    if (!p) return fail(SPED_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPED_OK;
+}
+}  // namespace
+
+extern "C" sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
+                                               int64_t ldx, int32_t xdt, void *Y, int64_t ldy, int32_t ydt,
+                                               sped_stream_t stream) {
+  clear_error();
+  SPED_TRY(validate_csr(L));
+  SPED_TRY(validate_poly(p));
+  if (k < 1) return fail(SPED_E_INVALID, "k < 1");
+  SPED_TRY(validate_block(X, L->n, k, ldx, xdt, "X"));
+  SPED_TRY(validate_block(Y, L->n, k, ldy, ydt, "Y"));
+  // the same two buffers sped_apply_poly carves from its workspace, each
+  // rounded up to 256 bytes
+  const int nbuf = p->degree >= 3 ? 2 : p->degree - 1;
+  const size_t one = (size_t(L->n) * size_t(k) * sizeof(float) + 255) / 256 * 256;
+  if (L->n > 0 && k > int64_t(kScratchBytes / sizeof(float)) / L->n)
+    return fail(SPED_E_WORKSPACE, "n x k beyond the allocation-free scratch (64 MiB)");
+  if (size_t(nbuf) * one > kScratchBytes)
+    return fail(SPED_E_WORKSPACE, "n x k beyond the allocation-free scratch: " + std::to_string(size_t(nbuf) * one) +
+                                      " bytes needed, 64 MiB available");
+  if (L->n == 0) return SPED_OK;
+  const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
+  size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
+  if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
+  void *base = nullptr;
+  SPED_TRY(scratch_address(&base));
+  float *A = nbuf >= 1 ? static_cast<float *>(base) : nullptr;
+  float *B = nbuf >= 2 ? reinterpret_cast<float *>(static_cast<char *>(base) + one) : nullptr;
   return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, as_stream(stream), nullptr);
 }
 

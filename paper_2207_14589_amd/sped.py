@@ -62,6 +62,7 @@ SIGNATURES = {
     "sped_poly_rebase": [_P(Poly), _c_f64, _c_f64, _P(_c_f64)],
     "sped_apply_poly": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp,
                         _P(_c_sz), _c_vp],
+    "sped_apply_poly_noalloc": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp],
     "sped_apply_poly_stochastic": [_P(CSR), _P(_c_f64), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
                                    _c_i32, _c_i32, _c_i64, _c_u64, _c_u64, _c_vp, _c_vp, _P(_c_sz), _c_vp],
     "sped_apply_poly_hybrid": [_P(CSR), _P(_c_f64), _c_i32, _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp,
@@ -284,6 +285,17 @@ def apply_poly(L: Laplacian, p: PolySpec, X: torch.Tensor, out=None, out_dtype=N
     ps = p.struct()
     _call_ws(lib().sped_apply_poly, "sped_apply_poly",
              (L.ref, ctypes.byref(ps), k, _ptr(X), _ld(X), _dt(X), _ptr(out), _ld(out), _dt(out)), X.device)
+    return out
+
+
+def apply_poly_noalloc(L: Laplacian, p: PolySpec, X: torch.Tensor, out: torch.Tensor):
+    """Y = p(L) X through sped_apply_poly_noalloc: the library's static scratch
+    instead of a workspace, so the call itself allocates nothing; `out` is the
+    caller's.  Calls on one GPU must not overlap in time."""
+    k = X.shape[1]
+    ps = p.struct()
+    _check(lib().sped_apply_poly_noalloc(L.ref, ctypes.byref(ps), k, _ptr(X), _ld(X), _dt(X), _ptr(out), _ld(out),
+                                         _dt(out), _stream(X.device)), "sped_apply_poly_noalloc")
     return out
 
 
