@@ -328,17 +328,23 @@ def time_to_tolerance_powerlaw200k(sped, synth, torch, np):
     L = sped.Laplacian(n, s, d, kind="sym", lcc=True, walk_records=False)
     V0 = synth.gaussian_block_device(L.n, 72, seed=2)
     out = {"workload": "Chung-Lu n=2e5, exponent 2.1, mean degree 16, 64 communities; largest component; "
-                       "k=64 (+8 guard), bf16 storage + float32 refinement, tol 1e-5",
+                       "k=64 (+8 guard), bf16 storage + float32 refinement, tol 1e-5 and 1e-6 "
+                       "(the polynomial runs end with plain iterations once their float32 floor stalls them)",
            "n_lcc": L.n, "nnz": L.nnz}
-    for name, p in (("plain", None), ("sped_limit16", sped.transform("limit", 16))):
-        sped.bottomk(L, 64, p, V0=V0, guard=8, tol=1e-5, max_iters=3000, storage="bf16")  # warm
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = sped.bottomk(L, 64, p, V0=V0, guard=8, tol=1e-5, max_iters=3000, storage="bf16")
-        dt = time.perf_counter() - t0
-        out[name] = {"seconds": round(dt, 4), "iters": r.stats["iters"], "bf16_iters": r.stats["coarse_iters"],
-                     "spmm": r.stats["spmm_count"], "converged": bool(r.converged), "bound": r.stats["bound"]}
-    out["speedup_sped_vs_plain"] = round(out["plain"]["seconds"] / out["sped_limit16"]["seconds"], 3)
+    for tol in (1e-5, 1e-6):
+        for name, p in (("plain", None), ("sped_limit16", sped.transform("limit", 16))):
+            kw = dict(guard=8, tol=tol, max_iters=3000, storage="bf16", polish=2 if p is not None else 0)
+            sped.bottomk(L, 64, p, V0=V0, **kw)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sped.bottomk(L, 64, p, V0=V0, **kw)
+            dt = time.perf_counter() - t0
+            out[f"{name}_{tol:g}"] = {"seconds": round(dt, 4), "iters": r.stats["iters"],
+                                      "bf16_iters": r.stats["coarse_iters"], "polish_iters": r.stats["polish_iters"],
+                                      "spmm": r.stats["spmm_count"], "converged": bool(r.converged),
+                                      "bound": r.stats["bound"]}
+        out[f"speedup_sped_vs_plain_{tol:g}"] = round(out[f"plain_{tol:g}"]["seconds"] /
+                                                      out[f"sped_limit16_{tol:g}"]["seconds"], 3)
     return out
 
 
@@ -386,9 +392,11 @@ def time_to_tolerance_combinatorial(sped, synth, torch, np):
     iteration on lambda_bound I - L contracts the unwanted directions by only
     1 - gap / lambda_bound per step, while (I - L/l)^l with 2l > lambda_bound
     (the smallest multiple of 16 that satisfies it) contracts them by about
-    e^{-gap}.  Same solver, cadence and float32 precision; tolerance 1e-5 on
-    the residual bound (the float32 floor of this operator is near 1e-6);
-    2,000-node and 500k-node SBMs."""
+    e^{-gap}.  Same solver, cadence and float32 precision; tolerances 1e-5
+    and 1e-6 on the residual bound (the plain operator's float32 floor,
+    lambda_bound / gap times the rounding, lies near 1e-6 here; the polynomial
+    runs may hand over to plain iterations when they stall); 2,000-node and
+    500k-node SBMs."""
     out = {}
     cases = (("sbm2000", lambda: synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1), 10, 4, 5000),
              ("sbm500k", lambda: synth.sbm_from_degrees(500_000, 50, 22.8, 1.2, seed=1), 50, 6, 3000))
@@ -397,56 +405,70 @@ def time_to_tolerance_combinatorial(sped, synth, torch, np):
         L = sped.Laplacian(n, s, d, kind="combinatorial")
         ell = 16 * int(np.ceil((L.lambda_bound / 2 + 1) / 16))
         V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 2).astype(np.float32)).cuda()
-        row = {"n": L.n, "k": k, "guard": guard, "lambda_bound": L.lambda_bound, "ell": ell, "tol": 1e-5}
-        for name, p in (("plain", None), (f"sped_limit{ell}", sped.transform("limit", ell, L.lambda_bound))):
-            sped.bottomk(L, k, p, V0=V0, guard=guard, tol=1e-5, max_iters=cap)  # warm
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=1e-5, max_iters=cap)
-            dt = time.perf_counter() - t0
-            row[name] = {"seconds": round(dt, 5), "iters": r.stats["iters"], "spmm": r.stats["spmm_count"],
-                         "converged": bool(r.converged), "bound": r.stats["bound"]}
-        row["speedup_sped_vs_plain"] = round(row["plain"]["seconds"] / row[f"sped_limit{ell}"]["seconds"], 3)
+        row = {"n": L.n, "k": k, "guard": guard, "lambda_bound": L.lambda_bound, "ell": ell}
+        for tol in (1e-5, 1e-6):
+            for name, p in (("plain", None), (f"sped_limit{ell}", sped.transform("limit", ell, L.lambda_bound))):
+                kw = dict(guard=guard, tol=tol, max_iters=cap, polish=2 if p is not None else 0)
+                if tol == 1e-5:
+                    sped.bottomk(L, k, p, V0=V0, **kw)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = sped.bottomk(L, k, p, V0=V0, **kw)
+                dt = time.perf_counter() - t0
+                row[f"{name}_{tol:g}"] = {"seconds": round(dt, 5), "iters": r.stats["iters"],
+                                          "polish_iters": r.stats["polish_iters"], "spmm": r.stats["spmm_count"],
+                                          "converged": bool(r.converged), "bound": r.stats["bound"]}
+            row[f"speedup_sped_vs_plain_{tol:g}"] = round(row[f"plain_{tol:g}"]["seconds"] /
+                                                          row[f"sped_limit{ell}_{tol:g}"]["seconds"], 3)
         out[tag] = row
         del L, V0
         torch.cuda.empty_cache()
     return out
 
 
-def time_to_tolerance_sbm500k(sped, synth, torch, np):
+def time_to_tolerance_sbm500k(sped, synth, torch, np, tol=1e-6):
     """500k-node SBM (50 blocks, mean degree 24, 5% cross), bottom 50 (+6
-    guard) to 1e-5 (above the float32 iterate's noise floor) with the same solver, cadence and precision for: the plain
-    operator 2I - L, the degree-12 limit polynomial, and degree-12 coefficients
-    tuned by gradient descent through PolyApply (time of the tuning reported
-    separately)."""
+    guard) to the 1e-6 bound with the same solver, cadence and precision for:
+    the plain operator 2I - L, the degree-12 limit polynomial, and degree-12
+    coefficients tuned by gradient descent through PolyApply.  The polynomial
+    runs hand over to plain iterations once their float32 floor stalls them
+    (polish_checks = 2).  The coefficients are tuned once on a 25k-node graph
+    of the same family (same blocks count and degrees, so the same spectrum
+    shape) and that time is reported beside the solves."""
     from paper_2207_14589_amd import tune
 
-    n, s, d, _ = synth.sbm_from_degrees(500_000, 50, 22.8, 1.2, seed=1)
-    L = sped.Laplacian(n, s, d, kind="sym")
     k, guard, ell = 50, 6, 12
-    V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 2).astype(np.float32)).cuda()
+    n, s, d, _ = synth.sbm_from_degrees(25_000, 50, 22.8, 1.2, seed=5)
+    Lp = sped.Laplacian(n, s, d, kind="sym")
     Vt = torch.from_numpy(synth.gaussian_block(n, k + guard, 7).astype(np.float32)).cuda()
+    tune.tune_coefficients(Lp, k, ell, Vt, steps=2, unroll=3)  # warm the kernels
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    theta, hist = tune.tune_coefficients(L, k, ell, Vt, steps=60, unroll=3)
+    theta, hist = tune.tune_coefficients(Lp, k, ell, Vt, steps=60, unroll=3)
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
-    out = {"workload": "SBM n=5e5, 50 blocks, mean degree 24, 5% cross; k=50 (+6 guard), tol 1e-5",
-           "tuning": {"seconds": round(tune_s, 3), "steps": len(hist), "loss_first": hist[0],
-                      "loss_best": min(hist), "theta": [float(x) for x in theta]}}
-    ops = (("plain", None), ("sped_limit12", sped.transform("limit", ell)),
-           ("sped_tuned12", sped.monomial(theta, shift=1.0, scale=1.0)))
-    for name, p in ops:
-        sped.bottomk(L, k, p, V0=V0, guard=guard, tol=1e-5, max_iters=4000)  # warm
+    del Lp, Vt
+    n, s, d, _ = synth.sbm_from_degrees(500_000, 50, 22.8, 1.2, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    V0 = torch.from_numpy(synth.gaussian_block(n, k + guard, 2).astype(np.float32)).cuda()
+    out = {"workload": f"SBM n=5e5, 50 blocks, mean degree 24, 5% cross; k=50 (+6 guard), tol {tol:g}",
+           "tuning": {"graph": "SBM n=2.5e4 of the same family", "seconds": round(tune_s, 3), "steps": len(hist),
+                      "loss_first": hist[0], "loss_best": min(hist), "theta": [float(x) for x in theta]}}
+    ops = (("plain", None, 0), ("sped_limit12", sped.transform("limit", ell), 2),
+           ("sped_tuned12", sped.monomial(theta, shift=1.0, scale=1.0), 2))
+    for name, p, polish in ops:
+        sped.bottomk(L, k, p, V0=V0, guard=guard, tol=tol, max_iters=4000, polish=polish)  # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=1e-5, max_iters=4000)
+        r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=tol, max_iters=4000, polish=polish)
         dt = time.perf_counter() - t0
-        out[name] = {"seconds": round(dt, 4), "iters": r.stats["iters"], "spmm": r.stats["spmm_count"],
-                     "converged": bool(r.converged), "bound": r.stats["bound"],
+        out[name] = {"seconds": round(dt, 4), "iters": r.stats["iters"], "polish_iters": r.stats["polish_iters"],
+                     "spmm": r.stats["spmm_count"], "converged": bool(r.converged), "bound": r.stats["bound"],
                      "gap_estimate": r.stats["gap_estimate"]}
-    out["speedup_limit_vs_plain"] = round(out["plain"]["seconds"] / out["sped_limit12"]["seconds"], 3)
-    out["speedup_tuned_vs_plain"] = round(out["plain"]["seconds"] / out["sped_tuned12"]["seconds"], 3)
+    pl = out["plain"]["seconds"]
+    out["speedup_limit_vs_plain"] = round(pl / out["sped_limit12"]["seconds"], 3)
+    out["speedup_tuned_vs_plain"] = round(pl / out["sped_tuned12"]["seconds"], 3)
+    out["speedup_tuned_vs_plain_with_tuning"] = round(pl / (out["sped_tuned12"]["seconds"] + tune_s), 3)
     return out
 
 
@@ -498,15 +520,16 @@ def _sin_angle(U, V, np):
     return float(np.linalg.norm(Q - U @ (U.T @ Q), 2))
 
 
-def rmat26_solver(sped, synth, torch, np, iters=3):
+def rmat26_solver(sped, synth, torch, np, budget_s=20.0):
     """The R-MAT workload at its full shape: scale 26 (2^26 nodes, edge factor
     16, a, b, c = 0.57, 0.19, 0.19, seeded vertex permutation), drawn on the
     device, largest component, symmetric normalised L; bottom 64 (+8 guard)
-    with bf16 iterate storage.  A few solver iterations each with the plain
-    operator, the exact degree-16 limit polynomial, and the limit polynomial
-    estimated by 8 lazy node walks per row, timed end to end (iterations,
-    Cholesky-QR2 and Rayleigh-Ritz checks included).  Prints one progress line
-    per stage."""
+    with bf16 iterate storage.  Each operator runs from the same start block
+    for about `budget_s` seconds (an iteration cap from a one-iteration probe)
+    and records its bound and largest residual at every check: the plain
+    operator, the exact degree-16 limit polynomial, and the same polynomial
+    estimated by lazy node walks (8 per row) for the first 3/4 of the
+    iterations, then exact.  Prints one progress line per stage."""
     t0 = time.perf_counter()
     n0, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
     torch.cuda.synchronize()
@@ -522,24 +545,117 @@ def rmat26_solver(sped, synth, torch, np, iters=3):
     k, guard = 64, 8
     V0 = synth.gaussian_block_device(L.n, k + guard, seed=2)
     out = {"workload": "R-MAT scale 26, edge factor 16 (0.57, 0.19, 0.19), device draw; largest component; "
-                       "sym-normalised L; bottom 64 (+8 guard), bf16 iterate storage",
+                       "sym-normalised L; bottom 64 (+8 guard), bf16 iterate storage, checks every iteration",
            "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree, "generate_s": round(gen_s, 2),
-           "build_s": round(build_s, 2)}
+           "build_s": round(build_s, 2), "budget_s": budget_s}
     p16 = sped.transform("limit", 16)
     runs = (("plain", None, {}), ("sped_limit16_exact", p16, {}),
-            ("sped_limit16_lazy_walks", p16, {"stochastic_iters": iters, "walks_per_row": 8, "sampler": "lazy"}))
-    sped.bottomk(L, k, None, V0=V0, guard=guard, tol=0.0, max_iters=1, storage="bf16")  # warm
+            ("sped_limit16_lazy_then_exact", p16, {"walks_per_row": 8, "sampler": "lazy"}))
     for name, p, kw in runs:
+        kw = dict(kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=iters, storage="bf16", **kw)
+        sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=1, storage="bf16",
+                     **({"stochastic_iters": 1} if "sampler" in kw else {}), **kw)
+        torch.cuda.synchronize()
+        per = time.perf_counter() - t0
+        iters = max(2, int(budget_s / per))
+        if "sampler" in kw:
+            kw["stochastic_iters"] = (3 * iters) // 4
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=iters, storage="bf16",
+                         coarse_tol=1e-30, trace_cap=iters + 1, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        tr = r.stats["trace"]
         out[name] = {"iters": r.stats["iters"], "seconds": round(dt, 3),
                      "seconds_per_iter": round(dt / max(r.stats["iters"], 1), 4), "spmm": r.stats["spmm_count"],
-                     "bound": r.stats["bound"], "gap_estimate": r.stats["gap_estimate"]}
-        print(json.dumps({"rmat26": name, **out[name]}), flush=True)
+                     "bound": r.stats["bound"], "gap_estimate": r.stats["gap_estimate"],
+                     "max_residual": r.stats["max_residual"],
+                     "trace_iter_s_bound_maxres": [[int(a), round(b, 3), c, round(d, 6)] for a, b, c, d in tr]}
+        print(json.dumps({"rmat26": name, **{x: y for x, y in out[name].items() if x != "trace_iter_s_bound_maxres"}}),
+              flush=True)
         del r
+        torch.cuda.empty_cache()
+    return out
+
+
+def power_law_4m_solve(sped, synth, torch, np, tol=1e-5, max_iters=400):
+    """The power-law workload solved at full size: Chung-Lu n = 4e6
+    (exponent 2.1, mean degree 16, 256 communities, device draw), largest
+    component; bottom 64 (+8 guard) with bf16 storage down to its floor, then
+    the float32 refinement to `tol`; the plain operator against the degree-16
+    limit polynomial (which hands over to plain iterations if its float32
+    floor stalls it), same solver and cadence, from one start block."""
+    n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    torch.cuda.empty_cache()
+    V0 = synth.gaussian_block_device(L.n, 72, seed=2)
+    out = {"workload": f"Chung-Lu n=4e6 (device draw), exponent 2.1, mean degree 16, 256 communities; largest "
+                       f"component; k=64 (+8 guard), bf16 storage + float32 refinement, tol {tol:g}",
+           "n_lcc": L.n, "nnz": L.nnz, "max_iters": max_iters}
+    for name, p in (("plain", None), ("sped_limit16", sped.transform("limit", 16))):
+        kw = dict(guard=8, tol=tol, max_iters=max_iters, storage="bf16", polish=2 if p is not None else 0,
+                  trace_cap=max_iters + 1)
+        sped.bottomk(L, 64, p, V0=V0, guard=8, tol=0.0, max_iters=1, storage="bf16")  # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sped.bottomk(L, 64, p, V0=V0, **kw)
+        dt = time.perf_counter() - t0
+        tr = r.stats["trace"]
+        out[name] = {"seconds": round(dt, 3), "iters": r.stats["iters"], "bf16_iters": r.stats["coarse_iters"],
+                     "polish_iters": r.stats["polish_iters"], "spmm": r.stats["spmm_count"],
+                     "converged": bool(r.converged), "bound": r.stats["bound"],
+                     "gap_estimate": r.stats["gap_estimate"],
+                     "trace_every_10th": [[int(a), round(b, 3), c, round(d, 7)] for a, b, c, d in tr[::10]]}
+        print(json.dumps({"power_law_4m": name, **{x: y for x, y in out[name].items() if x != "trace_every_10th"}}),
+              flush=True)
+    out["speedup_sped_vs_plain"] = round(out["plain"]["seconds"] / out["sped_limit16"]["seconds"], 3)
+    return out
+
+
+def rmat26_step(sped, synth, torch, np, reps=5):
+    """One fused step (L X) on the R-MAT scale-26 largest component at the
+    solver's widths: 72 float32 columns (64 + 8 guard; a 288-byte row touches
+    three 128-byte lines), 72 bf16 columns (two lines) and 64 bf16 columns
+    (one line).  Reports the row and entry counts of the three row bins and,
+    per width, the step time, its algorithmic bytes and the 128-byte lines its
+    neighbour-row gathers touch (nnz x lines per row)."""
+    n0, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    torch.cuda.empty_cache()
+    rp = L.rowptr[: L.n + 1]
+    deg = rp[1:] - rp[:-1]
+    bins = [deg <= 128, (deg > 128) & (deg <= 8192), deg > 8192]
+    out = {"workload": "R-MAT scale 26, edge factor 16 (0.57, 0.19, 0.19), device draw; largest component; "
+                       "sym-normalised L; one fused step L X",
+           "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree,
+           "bin_rows": [int(b.sum()) for b in bins], "bin_entries": [int(deg[b].sum()) for b in bins]}
+    del deg, bins, rp
+    one = sped.monomial([0.0, 1.0])
+    for k, dt, lines in ((72, torch.float32, 3), (72, torch.bfloat16, 2), (64, torch.bfloat16, 1)):
+        X = synth.gaussian_block_device(L.n, k, seed=2, dtype=dt)
+        Y = torch.empty_like(X)
+        sped.apply_poly(L, one, X, out=Y)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            sped.apply_poly(L, one, X, out=Y)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        eb = X.element_size()
+        alg = 8 * (L.n + 1) + L.nnz * 8 + 4 * L.n + L.n * k * 2 * eb
+        line_bytes = L.nnz * lines * 128
+        out[f"k{k}_{str(dt).split('.')[-1]}"] = {
+            "step_ms": round(ms, 3), "alg_GB": round(alg / 1e9, 2), "alg_GBps": round(alg / ms / 1e6, 1),
+            "gather_lines_GB": round(line_bytes / 1e9, 1), "gather_lines_TBps": round(line_bytes / ms / 1e9, 2)}
+        print(json.dumps({"rmat26_step": f"k{k}", **out[f"k{k}_{str(dt).split('.')[-1]}"]}), flush=True)
+        del X, Y
         torch.cuda.empty_cache()
     return out
 
@@ -813,6 +929,10 @@ def main():
                     help="measure the chip's rate for the sparse step's row-load pattern")
     ap.add_argument("--rmat26", action="store_true",
                     help="run only the R-MAT scale-26 solver iterations (minutes; not part of the default run)")
+    ap.add_argument("--power-law-solve", action="store_true",
+                    help="solve the 4e6-node power-law workload to 1e-5, plain against SPED (minutes)")
+    ap.add_argument("--rmat26-step", action="store_true",
+                    help="time one fused step on the R-MAT scale-26 graph at 72/64 columns (profiling the bins)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -859,6 +979,12 @@ def main():
         return
     if args.rmat26:
         print(json.dumps({"rmat26_solver": rmat26_solver(sped, synth, torch, np)}), flush=True)
+        return
+    if args.power_law_solve:
+        print(json.dumps({"power_law_4m_solve": power_law_4m_solve(sped, synth, torch, np)}), flush=True)
+        return
+    if args.rmat26_step:
+        print(json.dumps({"rmat26_step": rmat26_step(sped, synth, torch, np)}), flush=True)
         return
     if args.power_law_only:
         print(json.dumps({"power_law_bf16_k64": power_law_bf16(sped, synth, torch, np)}), flush=True)

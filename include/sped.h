@@ -416,6 +416,16 @@ typedef struct {
   int32_t use_graphs;      /* nonzero: each exact iteration's launches are captured once into a
                               HIP graph (per buffer pair, storage and check) and replayed
                               (bit-identical results; fewer launch overheads on small graphs) */
+  int32_t polish_checks;   /* > 0 with p != NULL (solver 0): the float32 iterations on p(L) end
+                              once the largest residual has not dropped by 2% for this many
+                              consecutive checks with the bound at or below 1e3 tol (the rounding
+                              floor of the degree-l chain), and
+                              iterations on the plain operator lambda_bound I - L continue from
+                              its Ritz vectors down to tol (one product per iteration: a lower
+                              floor).  0: off */
+  double *trace;           /* HOST [4 trace_cap] or NULL: each check appends (iteration, seconds
+                              since the call began, stopping bound, largest residual) */
+  int32_t trace_cap;       /* checks the trace holds; later checks are not recorded */
 } sped_solve_opts;
 
 typedef struct {
@@ -428,6 +438,8 @@ typedef struct {
   int32_t converged;
   int32_t cholqr_shifts;   /* breakdowns repaired by the shift */
   int32_t coarse_iters;    /* iterations done with BF16 storage */
+  int32_t polish_iters;    /* iterations done on the plain operator after p(L) stalled */
+  int32_t trace_len;       /* checks recorded in o->trace */
 } sped_solve_stats;
 
 sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p, int64_t k, const void *V0,

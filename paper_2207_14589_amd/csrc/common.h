@@ -315,7 +315,10 @@ struct StepArgs {
   float a, b, g;
   const float *dotw; int64_t lddw;      // non-NULL: accumulate <O, dotw>
   double *dot_partials;                 // [spmm_partials(L)]
+  void *heavy_ws;                       // [spmm_step_ws_bytes(L, k)], 256-byte aligned; NULL if no heavy rows
 };
+// Scratch one fused step needs (the heavy rows' piece partials); 0 without heavy rows.
+size_t spmm_step_ws_bytes(const sped_csr *L, int64_t k);
 // One fused step O = a (L U) + b U + g V over all rows (light, medium, heavy bins).
 sped_status launch_spmm_step(const sped_csr *L, int64_t k, const StepArgs &a, hipStream_t s,
                              int64_t *partials_written = nullptr);
@@ -363,7 +366,7 @@ sped_status walk_estimate_impl(const sped_csr *L, const double *coeffs, int degr
 sped_status hybrid_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int m, int64_t k,
                                  const void *X, int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler,
                                  int64_t walks, uint64_t seed, uint64_t counter, float *T0, float *T1,
-                                 hipStream_t s, int64_t *spmm_count = nullptr);
+                                 void *step_ws, hipStream_t s, int64_t *spmm_count = nullptr);
 // lazy node walks: the per-row largest move weight (n doubles; depends on the
 // graph only), then the walk estimate of (I - L/ell)^ell X that uses it
 sped_status lazy_row_max(const sped_csr *L, double *xmax, hipStream_t s);
@@ -372,8 +375,9 @@ sped_status lazy_walk_impl(const sped_csr *L, int ell, int64_t k, const void *X,
                            hipStream_t s);
 sped_status validate_lazy(const sped_csr *L, int ell, int64_t walks, uint64_t counter);
 
+// step_ws: spmm_step_ws_bytes(L, k) of scratch for every fused step
 sped_status apply_poly_impl(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
                             int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, float *bufA,
-                            float *bufB, hipStream_t s, int64_t *spmm_count);
+                            float *bufB, void *step_ws, hipStream_t s, int64_t *spmm_count);
 
 }  // namespace sped

@@ -47,7 +47,7 @@ sped_status validate_block(const void *p, int64_t n, int64_t k, int64_t ld, int 
 
 sped_status apply_poly_impl(const sped_csr *L, const sped_poly *p, int64_t k, const void *X,
                             int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, float *bufA,
-                            float *bufB, hipStream_t s, int64_t *spmm_count) {
+                            float *bufB, void *step_ws, hipStream_t s, int64_t *spmm_count) {
   const int ell = p->degree;
   float *buf[2] = {bufA, bufB};
   const void *in = X;
@@ -55,6 +55,7 @@ sped_status apply_poly_impl(const sped_csr *L, const sped_poly *p, int64_t k, co
   int tin = xdt;
   for (int i = 1; i <= ell; ++i) {
     StepArgs a{};
+    a.heavy_ws = step_ws;
     a.U = in; a.ldu = ldin; a.tu = tin;
     a.V = X; a.ldv = ldx; a.tv = xdt;
     if (i == ell) {
@@ -123,6 +124,8 @@ extern "C" sped_status sped_apply_poly(const sped_csr *L, const sped_poly *p, in
   Carver c(ws);
   float *A = nbuf >= 1 ? c.take<float>(size_t(L->n) * k) : nullptr;
   float *B = nbuf >= 2 ? c.take<float>(size_t(L->n) * k) : nullptr;
+  const size_t sw = spmm_step_ws_bytes(L, k);
+  void *step_ws = sw ? c.take<char>(sw) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query || L->n == 0) return SPED_OK;
@@ -130,7 +133,7 @@ extern "C" sped_status sped_apply_poly(const sped_csr *L, const sped_poly *p, in
   const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
   size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
   if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
-  return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, as_stream(stream), nullptr);
+  return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, step_ws, as_stream(stream), nullptr);
 }
 
 // Allocation-free form of sped_apply_poly: the chain's intermediate float32
@@ -180,9 +183,10 @@ extern "C" sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_pol
   const size_t one = (size_t(L->n) * size_t(k) * sizeof(float) + 255) / 256 * 256;
   if (L->n > 0 && k > int64_t(kScratchBytes / sizeof(float)) / L->n)
     return fail(SPED_E_WORKSPACE, "n x k beyond the allocation-free scratch (64 MiB)");
-  if (size_t(nbuf) * one > kScratchBytes)
-    return fail(SPED_E_WORKSPACE, "n x k beyond the allocation-free scratch: " + std::to_string(size_t(nbuf) * one) +
-                                      " bytes needed, 64 MiB available");
+  const size_t sw = (spmm_step_ws_bytes(L, k) + 255) / 256 * 256;
+  if (size_t(nbuf) * one + sw > kScratchBytes)
+    return fail(SPED_E_WORKSPACE, "n x k beyond the allocation-free scratch: " +
+                                      std::to_string(size_t(nbuf) * one + sw) + " bytes needed, 64 MiB available");
   if (L->n == 0) return SPED_OK;
   const char *xb = static_cast<const char *>(X), *yb = static_cast<const char *>(Y);
   size_t xs = size_t((L->n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((L->n - 1) * ldy + k) * dtype_size(ydt);
@@ -191,7 +195,8 @@ extern "C" sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_pol
   SPED_TRY(scratch_address(&base));
   float *A = nbuf >= 1 ? static_cast<float *>(base) : nullptr;
   float *B = nbuf >= 2 ? reinterpret_cast<float *>(static_cast<char *>(base) + one) : nullptr;
-  return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, as_stream(stream), nullptr);
+  void *step_ws = sw ? static_cast<char *>(base) + size_t(nbuf) * one : nullptr;
+  return apply_poly_impl(L, p, k, X, ldx, xdt, Y, ldy, ydt, A, B, step_ws, as_stream(stream), nullptr);
 }
 
 extern "C" sped_status sped_poly_backward(const sped_csr *L, int32_t degree, double shift, double scale,
@@ -211,6 +216,8 @@ extern "C" sped_status sped_poly_backward(const sped_csr *L, int32_t degree, dou
   float *P[2] = {c.take<float>(size_t(L->n) * k), c.take<float>(size_t(L->n) * k)};
   int64_t np = spmm_partials(L, k);
   double *partials = c.take<double>(size_t(np > kDotBlocks ? np : kDotBlocks));
+  const size_t sw = spmm_step_ws_bytes(L, k);
+  void *step_ws = sw ? c.take<char>(sw) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -229,6 +236,7 @@ extern "C" sped_status sped_poly_backward(const sped_csr *L, int32_t degree, dou
     a.O = P[(j - 1) & 1]; a.ldo = k; a.to = SPED_F32;
     a.a = float(1.0 / scale); a.b = float(-shift / scale); a.g = 0.f;
     a.dotw = dY; a.lddw = lddy; a.dot_partials = partials;
+    a.heavy_ws = step_ws;
     int64_t written = 0;
     SPED_TRY(launch_spmm_step(L, k, a, s, &written));
     SPED_TRY(launch_reduce_partials(partials, written, dtheta + j, s));

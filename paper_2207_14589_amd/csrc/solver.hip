@@ -122,6 +122,7 @@ struct RRWs {
   double *H, *S, *theta, *resid, *partials, *G, *norm2;
   int *flags;
   const double *jacobi_rel = nullptr;  // device scalar: where the k x k eigensolver stops (NULL: 1e-12)
+  void *step_ws = nullptr;             // spmm_step_ws_bytes(L, k) for the product Z = L Q
 };
 
 // Rayleigh-Ritz of L on span(Q) (Q of storage type dt, Z = L Q in float32);
@@ -130,6 +131,7 @@ struct RRWs {
 sped_status rayleigh_ritz(const sped_csr *L, int64_t n, int k, int kn, const void *Q, int64_t ld, int dt,
                           const RRWs &w, hipStream_t s) {
   StepArgs a{};
+  a.heavy_ws = w.step_ws;
   a.U = Q; a.ldu = ld; a.tu = dt;
   a.V = nullptr; a.ldv = ld; a.tv = dt;
   a.O = w.Z; a.ldo = ld; a.to = SPED_F32;
@@ -200,6 +202,8 @@ extern "C" sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q,
   w.G = c.take<double>(size_t(k) * k);
   w.norm2 = c.take<double>(1);
   w.flags = c.take<int>(4);
+  const size_t sw = spmm_step_ws_bytes(L, k);
+  w.step_ws = sw ? c.take<char>(sw) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -237,6 +241,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (o->stochastic_sampler != 0 && o->stochastic_sampler != 1) return fail(SPED_E_INVALID, "stochastic_sampler");
   const bool lazy = o->stochastic_iters > 0 && o->stochastic_sampler == 1;
   if (o->use_graphs != 0 && o->use_graphs != 1) return fail(SPED_E_INVALID, "use_graphs must be 0 or 1");
+  if (o->polish_checks < 0) return fail(SPED_E_INVALID, "polish_checks < 0");
+  if (o->trace_cap < 0 || (o->trace_cap > 0 && !o->trace)) return fail(SPED_E_INVALID, "trace / trace_cap");
+  if (o->polish_checks > 0 && o->solver != 0)
+    return fail(SPED_E_UNSUPPORTED, "the plain polish follows subspace iteration (solver 0) only");
   if (o->stochastic_exact_terms < 0 || (lazy && o->stochastic_exact_terms != 0))
     return fail(SPED_E_INVALID, "stochastic_exact_terms (edge walks only, >= 0)");
   if (o->stochastic_iters > 0 && !lazy && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
@@ -247,10 +255,12 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     SPED_TRY(validate_lazy(L, p->degree, o->walks_per_row, uint64_t(o->max_iters)));
   }
 
-  // the operator actually iterated on
+  // the operator actually iterated on (op_id 1 once the plain polish starts)
   std::vector<double> plain_c = {L->lambda_bound, -1.0};
-  sped_poly M{SPED_POLY_MONOMIAL, 1, plain_c.data(), 0.0, 1.0};
+  const sped_poly plain_M{SPED_POLY_MONOMIAL, 1, plain_c.data(), 0.0, 1.0};
+  sped_poly M = plain_M;
   if (p) M = *p;
+  int op_id = 0;
   std::vector<double> oja_c;
   if (o->solver == 1) {
     oja_c = (M.kind == SPED_POLY_LIMIT) ? monomial_in_L(M) : std::vector<double>(M.coeffs, M.coeffs + M.degree + 1);
@@ -302,6 +312,9 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   double *Amu = mueg ? c.take<double>(size_t(kb) * kb) : nullptr;
   float *Rtmp = mueg ? c.take<float>(size_t(n) * kb) : nullptr;
   double *lz_max = lazy ? c.take<double>(size_t(n)) : nullptr;
+  const size_t sw = spmm_step_ws_bytes(L, kb);
+  void *step_ws = sw ? c.take<char>(sw) : nullptr;
+  rw.step_ws = step_ws;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -332,9 +345,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
                               lz_max, q));
     } else if (stoch) {
       SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb, dt,
-                                    0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, q, &stats.spmm_count));
+                                    0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, step_ws, q,
+                                    &stats.spmm_count));
     } else {
-      SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, q, &stats.spmm_count));
+      SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, step_ws, q, &stats.spmm_count));
     }
     if (mueg) {
       // V <- normalise(V + eta grad), grad the projected mu-EG gradients
@@ -371,6 +385,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     const void *Q, *W;
     int dt;
     bool check;
+    int op;
     hipGraph_t graph;
     hipGraphExec_t exec;
     int64_t spmm;
@@ -393,10 +408,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   auto run_graph = [&](int dt, void *Q, void *W, bool check) -> sped_status {
     Captured *hit = nullptr;
     for (auto &x : graphs)
-      if (x.Q == Q && x.W == W && x.dt == dt && x.check == check) hit = &x;
+      if (x.Q == Q && x.W == W && x.dt == dt && x.check == check && x.op == op_id) hit = &x;
     if (!hit) {
       if (!cap) SPED_CHECK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-      Captured c{Q, W, dt, check, nullptr, nullptr, 0};
+      Captured c{Q, W, dt, check, op_id, nullptr, nullptr, 0};
       const int64_t before = stats.spmm_count;
       SPED_CHECK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
       const sped_status st = enqueue(dt, Q, W, check, false, cap);
@@ -425,7 +440,10 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   // With stall_checks > 0 the phase also ends when the largest residual has
   // not dropped below 0.98 x its best value for that many consecutive checks
   // (the storage's rounding floor has been reached).
-  auto phase = [&](int dt, void *&Q, void *&W, double tol, int iter_cap, int stall_checks,
+  // Stalls are counted only while the bound is at or below stall_below (the
+  // first iterations of a large block can leave the largest residual flat
+  // while the subspace turns).
+  auto phase = [&](int dt, void *&Q, void *&W, double tol, int iter_cap, int stall_checks, double stall_below,
                    bool *done) -> sped_status {
     *done = false;
     const int first = t + 1;
@@ -469,6 +487,13 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
         // ||R||_2 <= sqrt(min(||R^T R||_inf, ||R||_F^2)); the infinity norm is
         // the tighter one when the residual columns are nearly orthogonal
         stats.bound = gap > 0 ? h_norm2 / gap : INFINITY;
+        if (stats.trace_len < o->trace_cap) {
+          double *tr = o->trace + 4 * stats.trace_len++;
+          tr[0] = t;
+          tr[1] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+          tr[2] = stats.bound;
+          tr[3] = rmax;
+        }
         if (stats.bound <= tol) {
           *done = true;
           return SPED_OK;
@@ -479,7 +504,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
         if (rmax < 0.98 * best) {
           best = rmax;
           since_best = 0;
-        } else if (stall_checks > 0 && ++since_best >= stall_checks) {
+        } else if (stall_checks > 0 && stats.bound <= stall_below && ++since_best >= stall_checks) {
           return SPED_OK;
         }
       }
@@ -494,7 +519,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     void *Qh = Q16, *Wh = W16;
     SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, Wh, kb, SPED_BF16, s));
     SPED_TRY(cholqr(n, int(kb), Wh, Qh, kb, SPED_BF16, o->orth_passes, nullptr, ow, s));
-    SPED_TRY(phase(SPED_BF16, Qh, Wh, coarse_tol, o->max_iters, 8, &done));
+    SPED_TRY(phase(SPED_BF16, Qh, Wh, coarse_tol, o->max_iters, 8, INFINITY, &done));
     stats.coarse_iters = t;
     // refinement sweep: the bf16 iterate seeds float32 iterations
     SPED_TRY(copy_block(n, int(kb), Qh, kb, SPED_BF16, W, kb, SPED_F32, s));
@@ -508,7 +533,19 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     SPED_TRY(cholqr(n, int(kb), W, Q, kb, SPED_F32, o->orth_passes, nullptr, ow, s));
   }
   done = false;
-  if (t < o->max_iters) SPED_TRY(phase(SPED_F32, Q, W, o->tol, o->max_iters, 0, &done));
+  const bool polish = o->polish_checks > 0 && p != nullptr;
+  // the polynomial's float32 floor lies within a few hundred times tol; stalls
+  // farther up are the block still turning
+  if (t < o->max_iters)
+    SPED_TRY(phase(SPED_F32, Q, W, o->tol, o->max_iters, polish ? o->polish_checks : 0, 1e3 * o->tol, &done));
+  if (polish && !done && t < o->max_iters) {
+    // p(L) has reached its rounding floor: plain iterations from its Ritz vectors (in Q)
+    const int before = t;
+    M = plain_M;
+    op_id = 1;
+    SPED_TRY(phase(SPED_F32, Q, W, o->tol, o->max_iters, 0, INFINITY, &done));
+    stats.polish_iters = t - before;
+  }
   sped_status result = done ? SPED_OK : SPED_E_NOT_CONVERGED;
   stats.iters = t;
   stats.converged = result == SPED_OK;

@@ -9,7 +9,11 @@
 //   light   d <= SPED_LIGHT_MAX : a group of G lanes per row, 256/G rows per block
 //   medium  d <= SPED_MEDIUM_MAX: one 64-lane wavefront per row, 64/G lane groups
 //           split the entries, partial sums meet by cross-lane xor shuffles
-//   heavy   d >  SPED_MEDIUM_MAX: one 256-thread block per row, LDS reduction
+//   heavy   d >  SPED_MEDIUM_MAX: the row is cut into pieces of kPiece entries;
+//           each piece is one 256-thread block (LDS reduction) that writes its
+//           partial sum to the step workspace, and a second kernel adds a
+//           row's partials in piece order and applies the epilogue, so a hub
+//           row spreads over many CUs and the result is deterministic
 // Each lane owns VEC consecutive columns; G = next_pow2(k / VEC) lanes cover
 // a row of the block (columns beyond 64 VEC are tiled over blockIdx.y).  The
 // G lanes of a group load 4G consecutive (col, val) pairs with two 16-byte
@@ -294,41 +298,116 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
   }
 }
 
-template <typename TU, typename TV, typename TO, int VEC, bool DOT, bool STRAIGHT>
-__global__ __launch_bounds__(kBlock) void spmm_heavy(
-    const int32_t *__restrict__ rows, int64_t nnz, int k, int G, int lgG, const int64_t *__restrict__ rowptr,
-    const int32_t *__restrict__ col, const float *__restrict__ val, const float *__restrict__ diag,
-    const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O,
-    int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw, double *__restrict__ partials) {
-  using S = Step<TU, TV, TO, VEC, DOT>;
+// Pieces of the heavy rows: hp[h] = sum over heavy rows h' < h of
+// ceil(d_h' / kPiece), h = 0 .. n_heavy (hp[n_heavy] = the piece count).  One
+// block: each thread counts a contiguous run of rows, then an exclusive scan
+// over the threads' counts.
+constexpr int64_t kPiece = SPED_MEDIUM_MAX;
+
+__global__ __launch_bounds__(1024) void heavy_plan_kernel(int64_t n_heavy, const int32_t *__restrict__ rows,
+                                                          const int64_t *__restrict__ rowptr,
+                                                          int64_t *__restrict__ hp) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n_heavy + 1023) / 1024;
+  const int64_t lo = min(n_heavy, per * t), hi = min(n_heavy, lo + per);
+  int64_t cnt = 0;
+  for (int64_t h = lo; h < hi; ++h) {
+    const int64_t r = rows[h];
+    cnt += (rowptr[r + 1] - rowptr[r] + kPiece - 1) / kPiece;
+  }
+  part[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
+    const int64_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - cnt;
+  for (int64_t h = lo; h < hi; ++h) {
+    hp[h] = run;
+    const int64_t r = rows[h];
+    run += (rowptr[r + 1] - rowptr[r] + kPiece - 1) / kPiece;
+  }
+  if (t == 1023) hp[n_heavy] = part[1023];
+}
+
+// One block per piece (blocks loop over the pieces): the piece's entries are
+// shared by the block's lane groups as in a medium row, the groups' sums meet
+// in LDS in a fixed order and the block writes the piece's partial row (float32,
+// the block's columns) to part[piece * k + c].
+template <typename TU, int VEC, bool STRAIGHT>
+__global__ __launch_bounds__(kBlock) void spmm_heavy_pieces(
+    int64_t n_heavy, const int32_t *__restrict__ rows, const int64_t *__restrict__ hp, int64_t nnz, int k, int G,
+    int lgG, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ col, const float *__restrict__ val,
+    const TU *__restrict__ U, int64_t ldu, float *__restrict__ part) {
+  using S = Step<TU, float, float, VEC, false>;
   __shared__ float red[kBlock * VEC];
   const int lig = threadIdx.x & (G - 1);
   const int sub = threadIdx.x >> lgG;
   const int nsub = kBlock >> lgG;
-  const int64_t row = rows[blockIdx.x];
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   const bool col_ok = c0 < k;
-  const int64_t beg = rowptr[row], end = rowptr[row + 1];
-  float acc[VEC];
+  const int64_t total = hp[n_heavy];
+  for (int64_t pc = blockIdx.x; pc < total; pc += gridDim.x) {
+    // the heavy row holding piece pc: largest h with hp[h] <= pc
+    int64_t lo = 0, hi = n_heavy - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (hp[mid] <= pc) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t row = rows[lo];
+    const int64_t beg = rowptr[row] + (pc - hp[lo]) * kPiece;
+    const int64_t end = min(rowptr[row + 1], beg + kPiece);
+    float acc[VEC];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
-  if (STRAIGHT)
-    S::template gather_straight<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
-  else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+    if (STRAIGHT)
+      S::template gather_straight<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
+    else S::template gather4<true>(col, val, U, ldu, beg, end, nnz, G, lig, sub, nsub, c0, col_ok, acc);
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
-  __syncthreads();
+    for (int v = 0; v < VEC; ++v) red[threadIdx.x * VEC + v] = acc[v];
+    __syncthreads();
+    if (sub == 0 && col_ok) {
+      for (int sidx = 1; sidx < nsub; ++sidx)
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) acc[v] += red[(sidx * G + lig) * VEC + v];
+      VecIO<float, VEC>::store(part + pc * k + c0, acc);
+    }
+    __syncthreads();  // red is reused by the next piece
+  }
+}
+
+// One lane group per heavy row: the row's piece partials added in piece
+// order, then the epilogue.
+template <typename TU, typename TV, typename TO, int VEC, bool DOT>
+__global__ __launch_bounds__(kBlock) void spmm_heavy_finish(
+    int64_t n_heavy, const int32_t *__restrict__ rows, const int64_t *__restrict__ hp, int k, int G, int lgG,
+    const float *__restrict__ diag, const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V, int64_t ldv,
+    TO *__restrict__ O, int64_t ldo, Coef cf, const float *__restrict__ W, int64_t ldw,
+    const float *__restrict__ part, double *__restrict__ partials) {
+  using S = Step<TU, TV, TO, VEC, DOT>;
+  const int lig = threadIdx.x & (G - 1);
+  const int64_t h = int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG);
+  const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
   double dsum = 0.0;
-  if (sub == 0) {
-    for (int s = 1; s < nsub; ++s)
+  if (h < n_heavy && c0 < k) {
+    float acc[VEC];
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) acc[v] += red[(s * G + lig) * VEC + v];
-    if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+    for (int v = 0; v < VEC; ++v) acc[v] = 0.f;
+    for (int64_t pc = hp[h]; pc < hp[h + 1]; ++pc) {
+      float x[VEC];
+      VecIO<float, VEC>::load(part + pc * k + c0, x);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) acc[v] += x[v];
+    }
+    dsum = S::epilogue(rows[h], c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
   }
   if (DOT) {
-    __syncthreads();
-    __shared__ double dred[kBlock / 64];
-    double t = block_sum_double(dsum, dred);
+    __shared__ double red[kBlock / 64];
+    double t = block_sum_double(dsum, red);
     if (threadIdx.x == 0) partials[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = t;
   }
 }
@@ -346,6 +425,9 @@ __global__ __launch_bounds__(kBlock) void reduce_partials_kernel(const double *_
   }
   if (threadIdx.x == 0) *out = red[0];
 }
+
+// The piece prefix hp[0 .. n_heavy], rounded up to 256 bytes.
+size_t heavy_plan_bytes(const sped_csr *L) { return (size_t(L->n_heavy + 1) * sizeof(int64_t) + 255) / 256 * 256; }
 
 struct Geometry {
   int vec, G, lgG, ytiles;
@@ -378,13 +460,24 @@ Geometry geometry(const sped_csr *L, int64_t k, int vec) {
   for (int x = 0; x < kXcds; ++x) most = std::max(most, (g.xr.r[x + 1] - g.xr.r[x] + rpb - 1) / rpb);
   g.light_blocks = most * kXcds;
   g.medium_blocks = (L->n_medium + 3) / 4;
-  g.heavy_blocks = L->n_heavy;
+  g.heavy_blocks = (L->n_heavy + rpb - 1) / rpb;  // finishing blocks, one lane group per heavy row
   return g;
 }
 
 int64_t partial_count(const Geometry &g) {
   return (g.light_blocks + g.medium_blocks + g.heavy_blocks) * g.ytiles;
 }
+
+// Upper bound on the pieces of the heavy rows: ceil(d / kPiece) <= d / kPiece + 1
+// and the heavy rows hold at most nnz entries, so the total is at most
+// ceil(nnz / kPiece) + n_heavy.
+int64_t max_pieces(const sped_csr *L) {
+  return L->n_heavy > 0 ? (L->nnz + kPiece - 1) / kPiece + L->n_heavy : 0;
+}
+
+// Blocks of the piece kernel: enough to fill the chip several times over,
+// each looping over pieces.
+constexpr int64_t kPieceBlocks = 2048;
 
 template <typename TU, typename TV, typename TO, int VEC, bool DOT>
 sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const Geometry &g,
@@ -425,17 +518,26 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     SPED_CHECK_HIP(hipGetLastError());
     if (DOT) part += g.medium_blocks * g.ytiles;
   }
-  if (g.heavy_blocks > 0) {
-    const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
-#define SPED_HEAVY(ST)                                                                                     \
-  hipLaunchKernelGGL((spmm_heavy<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s,                    \
-                     L->bins + L->n_medium, L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val,        \
-                     L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
+  if (L->n_heavy > 0) {
+    if (!a.heavy_ws) return fail(SPED_E_WORKSPACE, "heavy rows need the step workspace");
+    const int32_t *hrows = L->bins + L->n_medium;
+    int64_t *hp = static_cast<int64_t *>(a.heavy_ws);
+    float *hpart = reinterpret_cast<float *>(static_cast<char *>(a.heavy_ws) + heavy_plan_bytes(L));
+    hipLaunchKernelGGL(heavy_plan_kernel, dim3(1), dim3(1024), 0, s, L->n_heavy, hrows, L->rowptr, hp);
+    SPED_CHECK_HIP(hipGetLastError());
+    const dim3 pgrid = dim3(unsigned(std::min<int64_t>(max_pieces(L), kPieceBlocks)), unsigned(g.ytiles));
+#define SPED_PIECES(ST)                                                                                     \
+  hipLaunchKernelGGL((spmm_heavy_pieces<TU, VEC, ST>), pgrid, dim3(kBlock), 0, s, L->n_heavy, hrows, hp,    \
+                     L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, U, a.ldu, hpart)
     if constexpr (VEC == 4) {
-      if (straight) SPED_HEAVY(true);
+      if (straight) SPED_PIECES(true);
     }
-    if (!straight) SPED_HEAVY(false);
-#undef SPED_HEAVY
+    if (!straight) SPED_PIECES(false);
+#undef SPED_PIECES
+    SPED_CHECK_HIP(hipGetLastError());
+    const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
+    hipLaunchKernelGGL((spmm_heavy_finish<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n_heavy, hrows, hp,
+                       int(k), g.G, g.lgG, L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, hpart, part);
     SPED_CHECK_HIP(hipGetLastError());
   }
   return SPED_OK;
@@ -462,6 +564,11 @@ sped_status dispatch_types(const sped_csr *L, int64_t k, const StepArgs &a, cons
 }
 
 }  // namespace
+
+size_t spmm_step_ws_bytes(const sped_csr *L, int64_t k) {
+  if (L->n_heavy <= 0) return 0;
+  return heavy_plan_bytes(L) + size_t(max_pieces(L)) * size_t(k) * sizeof(float);
+}
 
 int64_t spmm_partials(const sped_csr *L, int64_t k) {
   return partial_count(geometry(L, k, 1));  // upper bound: vec = 1 gives the most blocks

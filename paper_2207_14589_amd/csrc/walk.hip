@@ -651,7 +651,7 @@ namespace sped {
 sped_status hybrid_estimate_impl(const sped_csr *L, const double *coeffs, int degree, int m, int64_t k,
                                  const void *X, int64_t ldx, int xdt, void *Y, int64_t ldy, int ydt, int sampler,
                                  int64_t walks, uint64_t seed, uint64_t counter, float *T0, float *T1,
-                                 hipStream_t s, int64_t *spmm_count) {
+                                 void *step_ws, hipStream_t s, int64_t *spmm_count) {
   if (L->n == 0) return SPED_OK;
   if (m == 0)
     return walk_estimate_impl(L, coeffs, degree, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
@@ -674,6 +674,7 @@ sped_status hybrid_estimate_impl(const sped_csr *L, const double *coeffs, int de
   int next = sampled ? 1 : 0;
   for (int i = m - 1; i >= 0; --i) {
     StepArgs a{};
+    a.heavy_ws = step_ws;
     a.U = U; a.ldu = ldu; a.tu = tu;
     a.V = X; a.ldv = ldx; a.tv = xdt;
     if (i == 0) {
@@ -722,6 +723,8 @@ extern "C" sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *c
   float *T[2] = {nullptr, nullptr};
   if (m >= 1) T[0] = c.take<float>(size_t(n > 0 ? n : 1) * size_t(k));
   if (m >= 2) T[1] = c.take<float>(size_t(n > 0 ? n : 1) * size_t(k));
+  const size_t sw = m >= 1 ? spmm_step_ws_bytes(L, k) : 0;
+  void *step_ws = sw ? c.take<char>(sw) : nullptr;
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query || n == 0) return SPED_OK;
@@ -729,7 +732,7 @@ extern "C" sped_status sped_apply_poly_hybrid(const sped_csr *L, const double *c
   size_t xs = size_t((n - 1) * ldx + k) * dtype_size(xdt), ys = size_t((n - 1) * ldy + k) * dtype_size(ydt);
   if (xb < yb + ys && yb < xb + xs) return fail(SPED_E_INVALID, "X and Y overlap");
   return hybrid_estimate_impl(L, coeffs, degree, m, k, X, ldx, xdt, Y, ldy, ydt, sampler, walks, seed, counter,
-                              T[0], T[1], as_stream(stream));
+                              T[0], T[1], step_ws, as_stream(stream));
 }
 
 namespace sped {

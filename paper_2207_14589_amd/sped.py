@@ -44,13 +44,15 @@ class SolveOpts(ctypes.Structure):
                 ("check_every", _c_i32), ("guard", _c_i32), ("orth_passes", _c_i32),
                 ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64),
                 ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32), ("stochastic_exact_terms", _c_i32),
-                ("use_graphs", _c_i32)]
+                ("use_graphs", _c_i32), ("polish_checks", _c_i32), ("trace", ctypes.POINTER(_c_f64)),
+                ("trace_cap", _c_i32)]
 
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", _c_i32), ("spmm_count", _c_i64), ("seconds", _c_f64), ("max_residual", _c_f64),
                 ("gap_estimate", _c_f64), ("bound", _c_f64), ("converged", _c_i32),
-                ("cholqr_shifts", _c_i32), ("coarse_iters", _c_i32)]
+                ("cholqr_shifts", _c_i32), ("coarse_iters", _c_i32), ("polish_iters", _c_i32),
+                ("trace_len", _c_i32)]
 
 
 _P = ctypes.POINTER
@@ -382,7 +384,7 @@ class SolveResult:
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
             seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=0,
-            graphs=False):
+            graphs=False, polish=0, trace_cap=0):
     dev = L.device
     kb = k + guard
     if V0 is None:
@@ -395,7 +397,12 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
                   check_every=check_every, guard=guard, orth_passes=orth_passes,
                   stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
                   coarse_tol=coarse_tol, stochastic_sampler={"importance": 0, "lazy": 1}[sampler],
-                  stochastic_exact_terms=int(exact_terms), use_graphs=int(bool(graphs)))
+                  stochastic_exact_terms=int(exact_terms), use_graphs=int(bool(graphs)),
+                  polish_checks=int(polish))
+    trace = np.zeros((max(int(trace_cap), 1), 4))
+    if trace_cap > 0:
+        o.trace = trace.ctypes.data_as(ctypes.POINTER(_c_f64))
+        o.trace_cap = int(trace_cap)
     st = SolveStats()
     ps = poly.struct() if poly is not None else None
     status, _ = _call_ws(lib().sped_bottomk_solve, "sped_bottomk_solve",
@@ -404,6 +411,8 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
                           rs.ctypes.data_as(ctypes.POINTER(_c_f64)), ctypes.byref(o), ctypes.byref(st)), dev,
                          allow=(E_NOT_CONVERGED,))
     stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
+    if trace_cap > 0:
+        stats["trace"] = trace[: st.trace_len].tolist()
     return SolveResult(ev, V_out, rs, stats, status == OK)
 
 

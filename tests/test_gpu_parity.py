@@ -695,6 +695,33 @@ def test_tuned_coefficients_converge_to_true_subspace(sped):
          f"vs limit {r0.stats['iters']}")
 
 
+def test_plain_polish_reaches_1e6_past_the_chain_floor(sped):
+    """The degree-12 limit polynomial on a 4,000-node SBM settles near its
+    float32 rounding floor around 1e-6; with polish_checks the solver hands
+    its Ritz vectors to plain iterations on 2I - L once the residual stalls,
+    and reaches 1e-6.  The reported bound dominates the true sine of the
+    largest angle to the dense-eigh subspace, and the Ritz values match."""
+    _say("plain polish after the degree-12 limit operator, 4,000-node SBM, tol 1e-6")
+    n, s, d, _ = synth.sbm_bernoulli([500] * 8, 0.03, 0.0005, seed=3)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 8)
+    V0 = torch.from_numpy(synth.gaussian_block(n, 12, 2).astype(np.float32)).cuda()
+    p = sped.transform("limit", 12)
+    r = sped.bottomk(L, 8, p, V0=V0, guard=4, tol=1e-6, max_iters=600, polish=2)
+    r0 = sped.bottomk(L, 8, p, V0=V0, guard=4, tol=1e-6, max_iters=600)
+    _say(f"  polish: converged {r.converged} in {r.stats['iters']} iterations ({r.stats['polish_iters']} plain), "
+         f"bound {r.stats['bound']:.2e}; without: converged {r0.converged}, bound {r0.stats['bound']:.2e}")
+    assert r.converged and r.stats["bound"] <= 1e-6
+    ang = osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64))
+    assert np.sin(ang) <= r.stats["bound"]
+    np.testing.assert_allclose(r.evals, lam, rtol=1e-6, atol=1e-7)
+    # the polish is refused for the other solvers
+    with pytest.raises(sped.SpedError) as e:
+        sped.bottomk(L, 8, p, V0=V0, guard=4, tol=1e-6, max_iters=5, polish=2, solver="oja", eta=1.0)
+    assert e.value.status == sped.E_UNSUPPORTED
+
+
 def test_mu_eigengame_trajectory_parity(sped):
     """mu-EigenGame on the GPU follows the oracle's trajectory: same start
     block, same step, 60 iterations of the degree-8 limit operator on the

@@ -8,8 +8,20 @@
   forward, X gradient and coefficient gradient against the float64 oracle.
 * R-MAT scale 26 (67M nodes, edge factor 16, a = 0.57, b = c = 0.19,
   symmetrised, repeats and self-loops removed): one fused step on a 64-column
-  bf16 block checked row by row on 2,000 sampled rows, whose exact values the
-  oracle computes straight from the edge list.
+  bf16 block checked row by row on 2,000 sampled rows and the 16 largest hubs
+  (heavy rows of up to about 10^6 entries, cut into pieces), whose exact values
+  the oracle computes straight from the edge list.
+* Chung-Lu power-law graph at a tenth of the size (4e5 nodes, the same
+  exponent, mean degree and 256 communities, so the 64 wanted vectors are
+  still fewer than the communities): three solver iterations of the
+  degree-16 limit polynomial on 64 + 8 columns from one start block.  The
+  span of M^3 V0 (the library's chain and Cholesky-QR) against the oracle's,
+  and the solver's Ritz values after 3 iterations (float32 and bf16 storage)
+  against the oracle's subspace iteration.
+* R-MAT scale 22 (same parameters, largest component): the degree-16 limit
+  chain on a 72-column float32 block (the solver's 64 + 8 columns), every row
+  of 4 columns against the oracle's float64 chain; hubs of up to about
+  1.6 * 10^5 entries go through the heavy pieces.
 """
 import gc
 
@@ -84,6 +96,57 @@ def test_sbm_500k_polyapply_gradients(sped):
     np.testing.assert_allclose(theta.grad.numpy(), dth_r, rtol=2e-5, atol=2e-5 * np.abs(dth_r).max())
 
 
+def _threaded(apply, workers=16):
+    """Apply a column-separable oracle operator on column slices in threads
+    (scipy's sparse products release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def run(V):
+        sl = np.array_split(np.arange(V.shape[1]), min(workers, V.shape[1]))
+        with ThreadPoolExecutor(len(sl)) as ex:
+            parts = list(ex.map(lambda c: apply(np.ascontiguousarray(V[:, c])), sl))
+        return np.concatenate(parts, axis=1)
+    return run
+
+
+def test_power_law_trajectory_parity_k64(sped):
+    _say("Chung-Lu 4e5, 256 communities, k=64+8, 3 iterations of the degree-16 limit operator vs the oracle")
+    from oracle import solver as osol
+    n, s, d, _ = synth.chung_lu(400_000, 2.1, 16.0, 256, 0.95, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym", lcc=True, walk_records=False)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED, lcc=True)
+    assert L.n == ref.n
+    k, guard, ell, T = 64, 8, 16, 3
+    V0n = synth.gaussian_block(L.n, k + guard, 2).astype(np.float32)
+    apply_M = _threaded(lambda V: opoly.apply_limit_product(ref.L, ell, V))
+    # the iteration core: span(M^3 V0) from the chain and Cholesky QR2
+    p = sped.transform("limit", ell)
+    Q = torch.from_numpy(V0n).cuda()
+    W = torch.empty_like(Q)
+    for _ in range(T):
+        sped.apply_poly(L, p, Q, out=W)
+        sped.orthonormalize(W, passes=2)
+        Q, W = W, Q
+    Wo = V0n.astype(np.float64)
+    for _ in range(T):
+        Wo = osol.orthonormal(apply_M(Wo))
+    ang = osol.max_principal_angle(Wo, Q.cpu().numpy().astype(np.float64))
+    _say(f"  span of M^3 V0: largest angle {ang:.2e}")
+    assert ang < 1e-5
+    # the solver: Ritz values of L on span(M^3 V0) (Rayleigh-Ritz rotates the
+    # basis but keeps the span), float32 and bf16 storage
+    theta = osol.rayleigh_ritz(ref.L, Wo)[0][:k]
+    V0 = torch.from_numpy(V0n).cuda()
+    r32 = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=T)
+    np.testing.assert_allclose(r32.evals, theta, rtol=1e-5, atol=1e-6)
+    r16 = sped.bottomk(L, k, p, V0=V0, guard=guard, tol=0.0, max_iters=T, storage="bf16")
+    assert r16.stats["coarse_iters"] == T
+    # bf16 storage (u = 2^-9) perturbs the iterate, and so the Ritz values
+    np.testing.assert_allclose(r16.evals, theta, rtol=0, atol=3e-3)
+    _say(f"  Ritz values: float32 max err {np.abs(r32.evals - theta).max():.2e}, "
+         f"bf16 {np.abs(r16.evals - theta).max():.2e}")
+
+
 def test_rmat_scale26_sampled_rows(sped):
     _say("R-MAT scale 26 on the device: build, one fused step on a 64-column bf16 block")
     n, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
@@ -96,12 +159,16 @@ def test_rmat_scale26_sampled_rows(sped):
     Y = sped.apply_poly(L, sped.monomial([0.0, 1.0]), X, out_dtype=torch.float32)
     rng = np.random.default_rng(0)
     deg_host = None
-    rows = np.unique(np.concatenate([rng.choice(n, 1990, replace=False),
-                                     np.arange(10)]))
     src_h = src.cpu().numpy()
     dst_h = dst.cpu().numpy()
     del src, dst
     gc.collect()
+    deg = np.bincount(src_h, minlength=n) + np.bincount(dst_h, minlength=n)
+    hubs = np.argsort(deg)[-16:]
+    _say(f"  largest degrees {np.sort(deg[hubs])[::-1][:4].tolist()}, heavy rows {L.n_heavy}")
+    assert deg[hubs].min() > 8192  # the hubs are heavy rows
+    rows = np.unique(np.concatenate([rng.choice(n, 1990, replace=False), np.arange(10), hubs]))
+    del deg
 
     def xrows(ids):
         t = torch.as_tensor(np.asarray(ids, dtype=np.int64), device="cuda")
@@ -113,3 +180,25 @@ def test_rmat_scale26_sampled_rows(sped):
     # one fused step: each output is one float32 sum of d products of float32 values
     assert (np.abs(got - want) / scale).max() < 1e-5
     del deg_host
+
+
+def test_rmat_scale22_chain_with_heavy_pieces(sped):
+    _say("R-MAT scale 22, largest component, degree-16 limit chain on 72 float32 columns")
+    n, src, dst = synth.rmat_device(22, 16, 0.57, 0.19, 0.19, seed=1)
+    src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
+    L = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    ref = olap.laplacian(n, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
+    assert L.n == ref.n and L.max_degree == int(ref.count_degree.max())
+    _say(f"  n_lcc={L.n} nnz={L.nnz} max_degree={L.max_degree} medium={L.n_medium} heavy={L.n_heavy}")
+    assert L.n_heavy >= 10 and L.max_degree > 8 * 8192  # hubs cut into many pieces
+    X = synth.gaussian_block_device(L.n, 72, seed=2, dtype=torch.float32)
+    Y = sped.apply_poly(L, sped.transform("limit", 16), X)
+    cols = [0, 17, 40, 71]
+    Yr = opoly.apply_limit_product(ref.L, 16, X[:, cols].cpu().numpy().astype(np.float64))
+    Yg = Y[:, cols].cpu().numpy().astype(np.float64)
+    assert _rel(Yg, Yr) < 3e-5
+    assert np.abs(Yg - Yr).max() < 2e-4 * np.abs(Yr).max()
+    # the heavy rows themselves, elementwise
+    hr = L.bins[L.n_medium:L.n_medium + L.n_heavy].long().cpu().numpy()
+    assert np.abs(Yg[hr] - Yr[hr]).max() < 2e-4 * np.abs(Yr).max()
