@@ -813,6 +813,19 @@ def estimator_comparison(sped, torch, L, p, coeffs, Q, X, ell, walks, stream):
         row["ms"] = round(sorted(a.elapsed_time(b) for a, b in evs)[len(evs) // 2], 4)
         hyb[f"exact_terms_{m}"] = row
     out["exact_low_sampled_tail"] = hyb
+    # the solver driven by random estimates only: where each estimator's noise
+    # leaves the iterate (bottom 28 + 4 guard, 30 iterations from one start)
+    V0 = torch.from_numpy(X).cuda()
+    floor = {}
+    for name, kw in (("edge_walk", {"exact_terms": 0}), ("exact_terms_2", {"exact_terms": 2}),
+                     ("lazy_walk", {"sampler": "lazy"})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sped.bottomk(L, 28, p, V0=V0, guard=4, tol=0.0, max_iters=30, stochastic_iters=30, walks_per_row=walks,
+                         **kw)
+        floor[name] = {"max_residual": r.stats["max_residual"], "bound": r.stats["bound"],
+                       "seconds": round(time.perf_counter() - t0, 4)}
+    out["solver_noise_floor_30_random_iterations"] = floor
     return out
 
 

@@ -65,8 +65,12 @@ class _Walker:
         # position of the reverse entry (b -> a) of each entry (a -> b)
         key_fwd = self.row_of * np.int64(self.n) + self.col
         key_rev = self.col * np.int64(self.n) + self.row_of
-        order = np.argsort(key_fwd)
-        self.rev = order[np.searchsorted(key_fwd[order], key_rev)]
+        # the graph is symmetric, so both key arrays hold the same set: the
+        # j-th smallest reverse key belongs to the entry whose forward key is
+        # the j-th smallest
+        order = np.argsort(key_fwd, kind="stable")
+        self.rev = np.empty_like(order)
+        self.rev[np.argsort(key_rev, kind="stable")] = order
         assert np.array_equal(key_fwd[self.rev], key_rev)
         self.s = lap.scale
 

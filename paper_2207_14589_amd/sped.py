@@ -383,10 +383,17 @@ class SolveResult:
 
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
-            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=0,
+            seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=None,
             graphs=False, polish=0, trace_cap=0):
     dev = L.device
     kb = k + guard
+    if exact_terms is None:
+        # random iterations with edge walks default to the first two terms of
+        # the polynomial exact and the tail sampled (about 9x less error on
+        # the iterate than the all-sampled estimate for 4% more time); the
+        # lazy node walk takes none
+        deg = 1 if poly is None else poly.degree
+        exact_terms = min(2, deg) if (stochastic_iters > 0 and sampler == "importance") else 0
     if V0 is None:
         g = torch.Generator(device="cpu").manual_seed(v0_seed)
         V0 = torch.randn(L.n, kb, generator=g, dtype=torch.float64).to(torch.float32).to(dev)

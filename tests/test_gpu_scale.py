@@ -18,6 +18,9 @@
   span of M^3 V0 (the library's chain and Cholesky-QR) against the oracle's,
   and the solver's Ritz values after 3 iterations (float32 and bf16 storage)
   against the oracle's subspace iteration.
+* R-MAT scale 20 (same parameters, largest component): the importance edge
+  walk and the lazy node walk (8 walks per row, degree 16) against the
+  oracle's walks on sampled rows that include the 8 largest hubs.
 * R-MAT scale 22 (same parameters, largest component): the degree-16 limit
   chain on a 72-column float32 block (the solver's 64 + 8 columns), every row
   of 4 columns against the oracle's float64 chain; hubs of up to about
@@ -202,3 +205,30 @@ def test_rmat_scale22_chain_with_heavy_pieces(sped):
     # the heavy rows themselves, elementwise
     hr = L.bins[L.n_medium:L.n_medium + L.n_heavy].long().cpu().numpy()
     assert np.abs(Yg[hr] - Yr[hr]).max() < 2e-4 * np.abs(Yr).max()
+
+
+def test_rmat_scale20_walks_on_hub_rows(sped):
+    _say("R-MAT scale 20, largest component: edge walks and lazy walks on sampled rows and the hubs")
+    from oracle import lazywalk as olazy
+    from oracle import walk as owalk
+    n, src, dst = synth.rmat_device(20, 16, 0.57, 0.19, 0.19, seed=3)
+    src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
+    L = sped.Laplacian(n, src, dst, kind="sym", lcc=True)
+    del src, dst
+    ref = olap.laplacian(n, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
+    assert L.n == ref.n
+    deg = ref.count_degree
+    hubs = np.argsort(deg)[-8:]
+    med = np.nonzero((deg > 128) & (deg <= 8192))[0][:8]
+    rows = np.unique(np.concatenate([np.random.default_rng(1).choice(L.n, 300, replace=False), hubs, med]))
+    _say(f"  n_lcc={L.n} nnz={L.nnz} hub degrees {np.sort(deg[hubs])[::-1][:3].tolist()}")
+    X = synth.gaussian_block(L.n, 8, 4).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    c = opoly.limit_exp(16).coeffs
+    Y = sped.apply_poly_stochastic(L, c, Xd, walks=8, seed=3, counter=1).cpu().numpy()
+    Yr = owalk.estimate_importance(ref, c, X.astype(np.float64), 8, seed=3, counter=1, rows=rows)
+    scale = np.abs(Yr).max(axis=1, keepdims=True) + 1.0
+    assert (np.abs(Y[rows] - Yr) / scale).max() < 1e-4
+    Yl = sped.apply_limit_lazy(L, 16, Xd, 8, seed=3).cpu().numpy()
+    Ylo = olazy.estimate_lazy(ref, 16, X.astype(np.float64), 8, seed=3, rows=rows)
+    assert np.abs(Yl[rows] - Ylo).max() <= 2e-6 * np.abs(Ylo).max()
