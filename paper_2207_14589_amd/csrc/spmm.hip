@@ -175,15 +175,13 @@ struct Step {
     }
   }
 
-  // O[row] = a (diag U[row] - acc) + b U[row] + g V[row]; returns <O[row], W[row]>
-  // over this lane's columns when DOT.
-  __device__ static double epilogue(int64_t row, int c0, const float *__restrict__ diag,
-                                    const TU *__restrict__ U, int64_t ldu, const TV *__restrict__ V,
-                                    int64_t ldv, TO *__restrict__ O, int64_t ldo, Coef cf,
-                                    const float *__restrict__ W, int64_t ldw, const float (&acc)[VEC]) {
+  // O[row] = a (dg U[row] - acc) + b U[row] + g V[row] with dg = L_row,row;
+  // returns <O[row], W[row]> over this lane's columns when DOT.
+  __device__ static double epilogue(int64_t row, int c0, float dg, const TU *__restrict__ U, int64_t ldu,
+                                    const TV *__restrict__ V, int64_t ldv, TO *__restrict__ O, int64_t ldo,
+                                    Coef cf, const float *__restrict__ W, int64_t ldw, const float (&acc)[VEC]) {
     float u[VEC], o[VEC];
     VecIO<TU, VEC>::load(U + row * ldu + c0, u);
-    const float dg = diag[row];
 #pragma unroll
     for (int v = 0; v < VEC; ++v) o[v] = cf.a * (dg * u[v] - acc[v]) + cf.b * u[v];
     if (cf.g != 0.f) {
@@ -251,7 +249,10 @@ __global__ __launch_bounds__(kBlock) void spmm_light(
       if (STRAIGHT)
         S::template gather_straight<false>(col, val, U, ldu, beg, end, nnz, G, lig, 0, 1, c0, col_ok, acc);
       else S::template gather4<false>(col, val, U, ldu, beg, end, nnz, G, lig, 0, 1, c0, col_ok, acc);
-      if (col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+      // diag == NULL: the normalised Laplacian, whose diagonal is 1 on rows
+      // with entries and 0 on isolated rows
+      const float dg = diag ? diag[row] : (end > beg ? 1.f : 0.f);
+      if (col_ok) dsum = S::epilogue(row, c0, dg, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
     }
   }
   if (DOT) {
@@ -289,7 +290,8 @@ __global__ __launch_bounds__(kBlock) void spmm_medium(
     for (int off = G; off < 64; off <<= 1)
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
-    if (sub == 0 && col_ok) dsum = S::epilogue(row, c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+    if (sub == 0 && col_ok)
+      dsum = S::epilogue(row, c0, diag ? diag[row] : 1.f, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
   }
   if (DOT) {
     __shared__ double red[kBlock / 64];
@@ -403,7 +405,8 @@ __global__ __launch_bounds__(kBlock) void spmm_heavy_finish(
 #pragma unroll
       for (int v = 0; v < VEC; ++v) acc[v] += x[v];
     }
-    dsum = S::epilogue(rows[h], c0, diag, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
+    const int64_t row = rows[h];
+    dsum = S::epilogue(row, c0, diag ? diag[row] : 1.f, U, ldu, V, ldv, O, ldo, cf, W, ldw, acc);
   }
   if (DOT) {
     __shared__ double red[kBlock / 64];
@@ -483,6 +486,8 @@ template <typename TU, typename TV, typename TO, int VEC, bool DOT>
 sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const Geometry &g,
                          hipStream_t s) {
   Coef cf{a.a, a.b, a.g};
+  // the normalised Laplacian's diagonal follows from the row pointers
+  const float *dgp = L->kind == SPED_LAP_SYM_NORMALIZED ? nullptr : L->diag;
   const TU *U = static_cast<const TU *>(a.U);
   const TV *V = static_cast<const TV *>(a.V);
   TO *O = static_cast<TO *>(a.O);
@@ -494,12 +499,12 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     if constexpr (VEC == 4) {
       if (straight)
         hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, true>), grid, dim3(kBlock), 0, s, g.xr, L->nnz, int(k),
-                           g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
+                           g.G, g.lgG, L->rowptr, L->col, L->val, dgp, U, a.ldu, V, a.ldv, O, a.ldo,
                            cf, a.dotw, a.lddw, part);
     }
     if (!straight)
       hipLaunchKernelGGL((spmm_light<TU, TV, TO, VEC, DOT, false>), grid, dim3(kBlock), 0, s, g.xr, L->nnz, int(k),
-                         g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu, V, a.ldv, O, a.ldo,
+                         g.G, g.lgG, L->rowptr, L->col, L->val, dgp, U, a.ldu, V, a.ldv, O, a.ldo,
                          cf, a.dotw, a.lddw, part);
     SPED_CHECK_HIP(hipGetLastError());
     if (DOT) part += g.light_blocks * g.ytiles;
@@ -508,7 +513,7 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     const dim3 grid = dim3(unsigned(g.medium_blocks), unsigned(g.ytiles));
 #define SPED_MEDIUM(ST)                                                                                    \
   hipLaunchKernelGGL((spmm_medium<TU, TV, TO, VEC, DOT, ST>), grid, dim3(kBlock), 0, s, L->n_medium,      \
-                     L->bins, L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, L->diag, U, a.ldu,     \
+                     L->bins, L->nnz, int(k), g.G, g.lgG, L->rowptr, L->col, L->val, dgp, U, a.ldu,     \
                      V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, part)
     if constexpr (VEC == 4) {
       if (straight) SPED_MEDIUM(true);
@@ -537,7 +542,7 @@ sped_status launch_typed(const sped_csr *L, int64_t k, const StepArgs &a, const 
     SPED_CHECK_HIP(hipGetLastError());
     const dim3 grid = dim3(unsigned(g.heavy_blocks), unsigned(g.ytiles));
     hipLaunchKernelGGL((spmm_heavy_finish<TU, TV, TO, VEC, DOT>), grid, dim3(kBlock), 0, s, L->n_heavy, hrows, hp,
-                       int(k), g.G, g.lgG, L->diag, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, hpart, part);
+                       int(k), g.G, g.lgG, dgp, U, a.ldu, V, a.ldv, O, a.ldo, cf, a.dotw, a.lddw, hpart, part);
     SPED_CHECK_HIP(hipGetLastError());
   }
   return SPED_OK;
