@@ -213,6 +213,53 @@ def locality_sweep():
                       "copy_GBps_read_plus_write": round(2 * nbytes / us / 1e3, 1)}), flush=True)
 
 
+def sstep_sweep():
+    """The degree-16 limit chain on 10^6-node SBMs (mean degree 20, k = 32
+    float32) whose block size is 125, 1,000 or 10,000 rows and whose mean
+    degree between blocks is 1 (5% of edges), 0.1 or 0: 16 single fused steps
+    against 8 launches of two steps each on
+    LDS-resident row blocks (sped_apply_poly_blocked, block_rows = the block
+    size, capped at 1,000), same algorithmic bytes (16 single steps)."""
+    import numpy as np
+    import torch
+
+    from paper_2207_14589_amd import sped, synth
+
+    n, ell = 1_000_000, 16
+    X = torch.from_numpy(synth.gaussian_block(n, 32, 2).astype(np.float32)).cuda()
+    Y = torch.empty_like(X)
+    p = sped.transform("limit", ell)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = []
+    for bs, d_out in ((125, 1.0), (125, 0.1), (125, 0.0), (1000, 1.0), (1000, 0.1), (10000, 1.0)):
+        _, s, d, _ = synth.sbm_from_degrees(n, n // bs, 20.0 - d_out, d_out, seed=1)
+        L = sped.Laplacian(n, s, d, kind="sym", walk_records=False)
+        B = min(bs, 1000)
+        single = timed(lambda: sped.apply_poly(L, p, X, out=Y))
+        ref = Y.clone()
+        fused = timed(lambda: sped.apply_poly_blocked(L, p, X, B, out=Y))
+        alg = ell * spmm_step_bytes(L.n, L.nnz, 32)
+        row = {"block": bs, "cross_degree": d_out, "block_rows": B, "nnz": L.nnz, "single_steps_ms": round(single, 4),
+               "two_step_launches_ms": round(fused, 4), "speedup": round(single / fused, 3),
+               "single_GBps": round(alg / single / 1e6, 1), "two_step_GBps": round(alg / fused / 1e6, 1),
+               "rel_diff": float((Y - ref).norm() / ref.norm())}
+        print(json.dumps(row), flush=True)
+        out.append(row)
+        del L
+    return out
+
+
 def _host_info():
     """Host cores, CPU model and RAM, read from the OS."""
     import os
@@ -950,11 +997,16 @@ def main():
                     help="run the copy-calibrated workload for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="summarise the two counter databases into the committed traffic file")
+    ap.add_argument("--sstep-sweep", action="store_true",
+                    help="time the chain as single steps and as two-step launches on LDS row blocks")
     ap.add_argument("--locality-sweep", action="store_true",
                     help="time the fused step against neighbourhood locality, and a plain copy")
     args = ap.parse_args()
     if args.locality_sweep:
         locality_sweep()
+        return
+    if args.sstep_sweep:
+        print(json.dumps({"sstep_sweep": sstep_sweep()}), flush=True)
         return
     if args.write_traffic:
         write_traffic(*args.write_traffic)

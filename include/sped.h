@@ -223,6 +223,30 @@ sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_poly *p, int64
                                     sped_stream_t stream);
 
 /*
+ * sped_apply_poly_blocked -- Y = M X as sped_apply_poly, with the chain's
+ * steps fused two at a time (a matrix-powers form for graphs whose rows are
+ * ordered by community; Sec. 4.3 remarks that the structure of L can be
+ * exploited).  Each launch gives one workgroup the `block_rows` consecutive
+ * rows [b B, (b+1) B): it loads their rows of the current block into LDS,
+ * forms the first step's rows there (neighbours outside the block read from
+ * global memory), overwrites the LDS copy with them, and forms the second
+ * step (neighbours outside the block are recomputed from the first step's
+ * input).  The intermediate block never reaches global memory.  An odd
+ * degree ends with one single fused step.  Equal to sped_apply_poly up to the
+ * order of the float32 sums; fast only when most neighbours of a row lie in
+ * its block.
+ *  X, Y        DEVICE F32 n x k, 16-byte aligned, ldx and ldy multiples of 4
+ *  k           4, 8, 16, 32 or 64
+ *  block_rows  1 .. min(8 x 4096 / k, 160 KiB / (4 k)) (1000 for k = 32)
+ *  ws          two n x k F32 blocks plus the heavy rows' step scratch, or the
+ *              size-query form
+ * Asynchronous on `stream`.
+ */
+sped_status sped_apply_poly_blocked(const sped_csr *L, const sped_poly *p, int64_t block_rows, int64_t k,
+                                    const void *X, int64_t ldx, int32_t xdt, void *Y, int64_t ldy, int32_t ydt,
+                                    void *ws, size_t *ws_bytes, sped_stream_t stream);
+
+/*
  * sped_apply_poly_stochastic -- unbiased random-walk estimate of
  * Y = sum_{i=0..degree} coeffs[i] L^i X (Sec. 4.3: eq. walk_summand, Table 1,
  * the edge-incidence graph with self-loops, rejection sampling, prefix reuse).

@@ -65,6 +65,8 @@ SIGNATURES = {
     "sped_apply_poly": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp,
                         _P(_c_sz), _c_vp],
     "sped_apply_poly_noalloc": [_P(CSR), _P(Poly), _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32, _c_vp],
+    "sped_apply_poly_blocked": [_P(CSR), _P(Poly), _c_i64, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64, _c_i32,
+                                _c_vp, _P(_c_sz), _c_vp],
     "sped_apply_poly_stochastic": [_P(CSR), _P(_c_f64), _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp, _c_i64,
                                    _c_i32, _c_i32, _c_i64, _c_u64, _c_u64, _c_vp, _c_vp, _P(_c_sz), _c_vp],
     "sped_apply_poly_hybrid": [_P(CSR), _P(_c_f64), _c_i32, _c_i32, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp,
@@ -298,6 +300,19 @@ def apply_poly_noalloc(L: Laplacian, p: PolySpec, X: torch.Tensor, out: torch.Te
     ps = p.struct()
     _check(lib().sped_apply_poly_noalloc(L.ref, ctypes.byref(ps), k, _ptr(X), _ld(X), _dt(X), _ptr(out), _ld(out),
                                          _dt(out), _stream(X.device)), "sped_apply_poly_noalloc")
+    return out
+
+
+def apply_poly_blocked(L: Laplacian, p: PolySpec, X: torch.Tensor, block_rows: int, out=None):
+    """Y = p(L) X with pairs of steps fused on LDS-resident blocks of
+    `block_rows` consecutive rows (sped_apply_poly_blocked); float32 only."""
+    k = X.shape[1]
+    if out is None:
+        out = torch.empty(L.n, k, dtype=torch.float32, device=X.device)
+    ps = p.struct()
+    _call_ws(lib().sped_apply_poly_blocked, "sped_apply_poly_blocked",
+             (L.ref, ctypes.byref(ps), int(block_rows), k, _ptr(X), _ld(X), _dt(X), _ptr(out), _ld(out), _dt(out)),
+             X.device)
     return out
 
 

@@ -260,3 +260,29 @@ def test_edge_apply_binding_rejects_bad_tensors(lib):
     sped._device_vector(torch.zeros(10, dtype=torch.float32), "scale", torch.float32, 10, cpu)
     with pytest.raises(TypeError):
         sped._device_block(torch.zeros(4, 3, dtype=torch.float64), "X")
+
+
+def test_blocked_chain_validation(lib):
+    """Host checks of the two-steps-per-launch chain: float32 blocks, k a power
+    of two from 4 to 64, block_rows within the LDS and register budget, and
+    the workspace size query (two n x k float blocks)."""
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 1000, 8000, sped.SYM_NORMALIZED
+    c.rowptr = c.diag = c.scale = c.col = c.val = 16
+    p = sped.transform("limit", 16).struct()
+    X, Y = 4096, 1 << 20   # fake, 16-byte aligned, never dereferenced
+    need = ctypes.c_size_t(0)
+    f = lib.sped_apply_poly_blocked
+    assert f(ctypes.byref(c), ctypes.byref(p), 125, 12, X, 12, sped.F32, Y, 12, sped.F32, None,
+             ctypes.byref(need), None) == sped.E_UNSUPPORTED                       # k = 12
+    assert f(ctypes.byref(c), ctypes.byref(p), 125, 32, X, 32, sped.BF16, Y, 32, sped.F32, None,
+             ctypes.byref(need), None) == sped.E_UNSUPPORTED                       # bf16 X
+    assert f(ctypes.byref(c), ctypes.byref(p), 1281, 32, X, 32, sped.F32, Y, 32, sped.F32, None,
+             ctypes.byref(need), None) == sped.E_INVALID                           # 1281 x 32 floats > 160 KiB
+    assert f(ctypes.byref(c), ctypes.byref(p), 0, 32, X, 32, sped.F32, Y, 32, sped.F32, None,
+             ctypes.byref(need), None) == sped.E_INVALID                           # block_rows 0
+    assert f(ctypes.byref(c), ctypes.byref(p), 125, 32, X + 4, 32, sped.F32, Y, 32, sped.F32, None,
+             ctypes.byref(need), None) == sped.E_INVALID                           # misaligned X
+    assert f(ctypes.byref(c), ctypes.byref(p), 1000, 32, X, 32, sped.F32, Y, 32, sped.F32, None,
+             ctypes.byref(need), None) == sped.OK
+    assert need.value >= 2 * 1000 * 32 * 4

@@ -1232,3 +1232,36 @@ def test_minibatch_oja_edge_cases(sped):
     with pytest.raises(sped.SpedError) as ei:
         sped.minibatch_oja(n, _pinned(bad, torch.int32), dh, V.clone(), degree=0, batch=1000, iters=2)
     assert ei.value.status == sped.E_INVALID
+
+
+@pytest.mark.parametrize("case", ["sbm125_limit16", "hub_taylor5", "sbm_degree1", "sbm_degree2_tail"])
+def test_blocked_chain_parity(sped, case):
+    """sped_apply_poly_blocked (two fused steps per launch on LDS-resident row
+    blocks) against the oracle's chain and against the single-step chain:
+    a community-ordered SBM with blocks of 125 rows (block_rows 125, 95% of
+    neighbours inside the block), the weighted hub graph with blocks that
+    ignore its structure (most neighbours outside: the recompute path, an odd
+    degree ending with one single step, Horner terms g X), degree 1 and 2, and
+    a last block shorter than block_rows."""
+    _say(f"blocked chain {case}")
+    if case == "hub_taylor5":
+        n, s, d, w = mixed_degree_graph()
+        L = sped.Laplacian(n, s, d, w, kind="sym")
+        ref = olap.laplacian(n, s, d, w, kind=olap.SYM_NORMALIZED)
+        k, B, p, op = 8, 300, sped.transform("taylor_exp", 5), opoly.taylor_exp(5)
+    else:
+        n, s, d, _ = synth.sbm_from_degrees(25_000, 200, 19.0, 1.0, seed=3)
+        L = sped.Laplacian(n, s, d, kind="sym")
+        ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+        deg = {"sbm125_limit16": 16, "sbm_degree1": 1, "sbm_degree2_tail": 2}[case]
+        k, B = 32, (125 if case != "sbm_degree2_tail" else 333)
+        p, op = sped.transform("limit", deg), opoly.limit_exp(deg)
+    X = synth.gaussian_block(n, k, 5).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Y = sped.apply_poly_blocked(L, p, Xd, B).cpu().numpy()
+    Y1 = sped.apply_poly(L, p, Xd).cpu().numpy()
+    Yr = opoly.apply_terms(ref.L, op, X.astype(np.float64))
+    assert _rel(Y, Yr) < 3e-5
+    assert np.abs(Y - Yr).max() < 2e-4 * np.abs(Yr).max()
+    # the same arithmetic as the single-step chain up to the order of the sums
+    assert _rel(Y, Y1) < 1e-5
