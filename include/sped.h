@@ -431,7 +431,7 @@ typedef struct {
   int32_t orth_passes;     /* Cholesky-QR passes per iteration (1 or 2) */
   int32_t stochastic_iters;/* first iterations use the random estimate (stochastic_sampler) */
   int64_t walks_per_row;   /* walks per row for those iterations */
-  uint64_t seed;           /* Philox key; iteration t uses counter t */
+  uint64_t seed;           /* Philox key; iteration t (1, 2, ...) uses counter counter_base + t */
   double coarse_tol;       /* BF16 phase stops at this bound (<= 0: 1e-2) */
   int32_t stochastic_sampler; /* 0 = importance edge walks (Sec. 4.3), 1 = lazy node walks
                                  (sped_apply_limit_lazy; needs the limit polynomial, solver 0 or 2) */
@@ -450,6 +450,9 @@ typedef struct {
   double *trace;           /* HOST [4 trace_cap] or NULL: each check appends (iteration, seconds
                               since the call began, stopping bound, largest residual) */
   int32_t trace_cap;       /* checks the trace holds; later checks are not recorded */
+  uint64_t counter_base;   /* added to the walk counters: a stochastic solve resumed from the
+                              block an earlier call returned after T iterations continues that
+                              call's random stream with counter_base = T */
 } sped_solve_opts;
 
 typedef struct {

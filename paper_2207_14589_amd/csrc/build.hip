@@ -373,8 +373,8 @@ extern "C" sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *s
   b.splits = c.take<int64_t>(kXcds + 1);
   b.best = c.take<unsigned long long>(1);
   b.err = c.take<int>(4);
-  b.changed = b.err + 1;
-  b.maxcount = b.err + 2;
+  b.changed = b.err ? b.err + 1 : nullptr;  // NULL in the size query
+  b.maxcount = b.err ? b.err + 2 : nullptr;
   b.temp_bytes = cub_temp_bytes(n, cnt > 0 ? cnt : 1);
   b.temp = c.take<char>(b.temp_bytes);
   bool query;

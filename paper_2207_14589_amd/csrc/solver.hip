@@ -249,10 +249,13 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     return fail(SPED_E_INVALID, "stochastic_exact_terms (edge walks only, >= 0)");
   if (o->stochastic_iters > 0 && !lazy && (o->walks_per_row < 1 || !L->wentry || !L->wnode))
     return fail(SPED_E_INVALID, "stochastic iterations need walks_per_row >= 1 and the walk records");
+  if (o->stochastic_iters > 0 &&
+      (o->counter_base >= (uint64_t(1) << 32) || o->counter_base + uint64_t(o->max_iters) >= (uint64_t(1) << 32)))
+    return fail(SPED_E_INVALID, "walk counters (counter_base + iterations) must stay below 2^32");
   if (lazy) {
     if (!p || p->kind != SPED_POLY_LIMIT) return fail(SPED_E_INVALID, "lazy walks estimate the limit polynomial only");
     if (o->solver == 1) return fail(SPED_E_UNSUPPORTED, "lazy walks with block Oja (M + I/eta) are not supported");
-    SPED_TRY(validate_lazy(L, p->degree, o->walks_per_row, uint64_t(o->max_iters)));
+    SPED_TRY(validate_lazy(L, p->degree, o->walks_per_row, o->counter_base + uint64_t(o->max_iters)));
   }
 
   // the operator actually iterated on (op_id 1 once the plain polish starts)
@@ -341,11 +344,13 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   // or mu-EigenGame update, and with `check` the Rayleigh-Ritz step.
   auto enqueue = [&](int dt, void *Q, void *W, bool check, bool stoch, hipStream_t q) -> sped_status {
     if (stoch && lazy) {
-      SPED_TRY(lazy_walk_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed, uint64_t(t),
+      SPED_TRY(lazy_walk_impl(L, M.degree, kb, Q, kb, dt, W, kb, dt, o->walks_per_row, o->seed,
+                              o->counter_base + uint64_t(t),
                               lz_max, q));
     } else if (stoch) {
       SPED_TRY(hybrid_estimate_impl(L, walk_c.data(), M.degree, o->stochastic_exact_terms, kb, Q, kb, dt, W, kb, dt,
-                                    0, o->walks_per_row, o->seed, uint64_t(t), bufA, bufB, step_ws, q,
+                                    0, o->walks_per_row, o->seed, o->counter_base + uint64_t(t), bufA, bufB,
+                                    step_ws, q,
                                     &stats.spmm_count));
     } else {
       SPED_TRY(apply_poly_impl(L, &M, kb, Q, kb, dt, W, kb, dt, bufA, bufB, step_ws, q, &stats.spmm_count));

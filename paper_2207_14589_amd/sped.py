@@ -45,7 +45,7 @@ class SolveOpts(ctypes.Structure):
                 ("stochastic_iters", _c_i32), ("walks_per_row", _c_i64), ("seed", _c_u64),
                 ("coarse_tol", _c_f64), ("stochastic_sampler", _c_i32), ("stochastic_exact_terms", _c_i32),
                 ("use_graphs", _c_i32), ("polish_checks", _c_i32), ("trace", ctypes.POINTER(_c_f64)),
-                ("trace_cap", _c_i32)]
+                ("trace_cap", _c_i32), ("counter_base", _c_u64)]
 
 
 class SolveStats(ctypes.Structure):
@@ -399,7 +399,7 @@ class SolveResult:
 def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol=1e-6, max_iters=1000,
             check_every=1, orth_passes=2, solver="subspace", eta=1.0, stochastic_iters=0, walks_per_row=8,
             seed=3, v0_seed=2, storage="f32", coarse_tol=1e-2, sampler="importance", exact_terms=None,
-            graphs=False, polish=0, trace_cap=0):
+            graphs=False, polish=0, trace_cap=0, counter_base=0, log_path=None):
     dev = L.device
     kb = k + guard
     if exact_terms is None:
@@ -420,7 +420,9 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
                   stochastic_iters=stochastic_iters, walks_per_row=walks_per_row, seed=seed,
                   coarse_tol=coarse_tol, stochastic_sampler={"importance": 0, "lazy": 1}[sampler],
                   stochastic_exact_terms=int(exact_terms), use_graphs=int(bool(graphs)),
-                  polish_checks=int(polish))
+                  polish_checks=int(polish), counter_base=int(counter_base))
+    if log_path is not None and trace_cap <= 0:
+        trace_cap = max_iters
     trace = np.zeros((max(int(trace_cap), 1), 4))
     if trace_cap > 0:
         o.trace = trace.ctypes.data_as(ctypes.POINTER(_c_f64))
@@ -435,6 +437,14 @@ def bottomk(L: Laplacian, k, poly: PolySpec | None = None, V0=None, guard=4, tol
     stats = {f: getattr(st, f) for f, _ in SolveStats._fields_}
     if trace_cap > 0:
         stats["trace"] = trace[: st.trace_len].tolist()
+    if log_path is not None:
+        # one JSON line per check, then one for the result
+        import json
+        with open(log_path, "a") as fh:
+            for it, sec, bound, rmax in stats["trace"]:
+                fh.write(json.dumps({"iter": int(it), "seconds": sec, "bound": bound, "max_residual": rmax}) + "\n")
+            fh.write(json.dumps({"result": {f: getattr(st, f) for f, _ in SolveStats._fields_},
+                                 "status": int(status)}) + "\n")
     return SolveResult(ev, V_out, rs, stats, status == OK)
 
 

@@ -1265,3 +1265,31 @@ def test_blocked_chain_parity(sped, case):
     assert np.abs(Y - Yr).max() < 2e-4 * np.abs(Yr).max()
     # the same arithmetic as the single-step chain up to the order of the sums
     assert _rel(Y, Y1) < 1e-5
+
+
+def test_stochastic_counter_base_and_check_log(sped, tmp_path):
+    """counter_base shifts the walk counters of the random iterations (a
+    resumed solve draws fresh walks; the same base repeats them bit for bit;
+    counters past 2^32 are refused), and log_path writes one JSON line per
+    check plus the result."""
+    import json
+    _say("solver counter_base and per-check log")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    V0 = torch.from_numpy(synth.gaussian_block(n, 14, 2).astype(np.float32)).cuda()
+    p = sped.transform("limit", 8)
+    kw = dict(V0=V0, guard=4, tol=0.0, max_iters=5, stochastic_iters=5, walks_per_row=4)
+    a = sped.bottomk(L, 10, p, counter_base=0, **kw).V
+    b = sped.bottomk(L, 10, p, counter_base=0, **kw).V
+    c = sped.bottomk(L, 10, p, counter_base=7, **kw).V
+    assert torch.equal(a, b)
+    assert not torch.equal(a, c)
+    with pytest.raises(sped.SpedError) as e:
+        sped.bottomk(L, 10, p, counter_base=(1 << 32) - 3, **kw)
+    assert e.value.status == sped.E_INVALID
+    log = tmp_path / "checks.jsonl"
+    r = sped.bottomk(L, 10, p, V0=V0, guard=4, tol=1e-6, max_iters=300, log_path=str(log))
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == r.stats["iters"] + 1  # check_every = 1
+    assert lines[-1]["result"]["converged"] == 1
+    assert lines[-2]["bound"] == r.stats["bound"] <= 1e-6
