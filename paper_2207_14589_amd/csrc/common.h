@@ -202,6 +202,99 @@ struct VecNT<bf16_t, 4> {
   }
 };
 
+// Eight elements per lane (16 bytes of bf16; two 16-byte halves of float).
+template <>
+struct VecIO<float, 8> {
+  __device__ static void load(const float *p, float (&o)[8]) {
+    const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w; o[4] = b.x; o[5] = b.y; o[6] = b.z; o[7] = b.w;
+  }
+  __device__ static void store(float *p, const float (&o)[8]) {
+    reinterpret_cast<float4 *>(p)[0] = make_float4(o[0], o[1], o[2], o[3]);
+    reinterpret_cast<float4 *>(p)[1] = make_float4(o[4], o[5], o[6], o[7]);
+  }
+};
+template <>
+struct VecIO<bf16_t, 8> {
+  __device__ static void load(const bf16_t *p, float (&o)[8]) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      o[2 * i] = bf16_to_f32(bf16_t(w[i] & 0xffff));
+      o[2 * i + 1] = bf16_to_f32(bf16_t(w[i] >> 16));
+    }
+  }
+  __device__ static void store(bf16_t *p, const float (&o)[8]) {
+    uint4 v;
+    v.x = uint32_t(f32_to_bf16(o[0])) | (uint32_t(f32_to_bf16(o[1])) << 16);
+    v.y = uint32_t(f32_to_bf16(o[2])) | (uint32_t(f32_to_bf16(o[3])) << 16);
+    v.z = uint32_t(f32_to_bf16(o[4])) | (uint32_t(f32_to_bf16(o[5])) << 16);
+    v.w = uint32_t(f32_to_bf16(o[6])) | (uint32_t(f32_to_bf16(o[7])) << 16);
+    *reinterpret_cast<uint4 *>(p) = v;
+  }
+};
+template <>
+struct VecNT<float, 8> {
+  __device__ static void store(float *p, const float (&o)[8]) {
+    f32x4_t a = {o[0], o[1], o[2], o[3]}, b = {o[4], o[5], o[6], o[7]};
+    __builtin_nontemporal_store(a, reinterpret_cast<f32x4_t *>(p));
+    __builtin_nontemporal_store(b, reinterpret_cast<f32x4_t *>(p) + 1);
+  }
+};
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+template <>
+struct VecNT<bf16_t, 8> {
+  __device__ static void store(bf16_t *p, const float (&o)[8]) {
+    u32x4_t v = {uint32_t(f32_to_bf16(o[0])) | (uint32_t(f32_to_bf16(o[1])) << 16),
+                 uint32_t(f32_to_bf16(o[2])) | (uint32_t(f32_to_bf16(o[3])) << 16),
+                 uint32_t(f32_to_bf16(o[4])) | (uint32_t(f32_to_bf16(o[5])) << 16),
+                 uint32_t(f32_to_bf16(o[6])) | (uint32_t(f32_to_bf16(o[7])) << 16)};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4_t *>(p));
+  }
+};
+
+// One neighbour row's VEC elements as loaded, before conversion: bf16 rows
+// stay packed (two per register) until the multiply-add, so the 8 row loads a
+// lane keeps in flight take half the registers.
+template <typename T, int VEC>
+struct RawRow {
+  float f[VEC];
+  __device__ void load(const T *p) { VecIO<T, VEC>::load(p, f); }
+  __device__ void zero() {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) f[v] = 0.f;
+  }
+  __device__ float get(int v) const { return f[v]; }
+};
+template <int VEC>
+struct RawRow<bf16_t, VEC> {
+  static_assert(VEC % 2 == 0 || VEC == 1, "bf16 rows are held in pairs");
+  static constexpr int W = VEC >= 2 ? VEC / 2 : 1;
+  uint32_t w[W];
+  __device__ void load(const bf16_t *p) {
+    if constexpr (VEC == 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(p);
+      w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else if constexpr (VEC == 4) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p);
+      w[0] = v.x; w[1] = v.y;
+    } else if constexpr (VEC == 2) {
+      w[0] = *reinterpret_cast<const uint32_t *>(p);
+    } else {
+      w[0] = uint32_t(*p);
+    }
+  }
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < W; ++i) w[i] = 0u;
+  }
+  __device__ float get(int v) const {
+    const uint32_t x = w[v >> 1];
+    return bf16_to_f32(bf16_t((v & 1) ? (x >> 16) : (x & 0xffff)));
+  }
+};
+
 // Workgroups are handed to the 8 XCDs round-robin in dispatch order.  This
 // maps hardware block b to logical block (b % 8) * per + b / 8 so that each
 // XCD walks one contiguous stretch of logical blocks (rows), keeping the rows

@@ -94,18 +94,16 @@ struct Step {
           sv[u] = (t + u < cnt) ? __shfl(v4[u & 3], src, G) : 0.f;
         }
         if (col_ok) {
-          float x[8][VEC];
+          RawRow<TU, VEC> x[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            if (t + u < cnt) VecIO<TU, VEC>::load(U + int64_t(j[u]) * ldu + c0, x[u]);
-            else
-#pragma unroll
-              for (int v = 0; v < VEC; ++v) x[u][v] = 0.f;
+            if (t + u < cnt) x[u].load(U + int64_t(j[u]) * ldu + c0);
+            else x[u].zero();
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(sv[u], x[u][v], acc[v]);
+            for (int v = 0; v < VEC; ++v) acc[v] = fmaf(sv[u], x[u].get(v), acc[v]);
         }
       }
       if (PREFETCH) {
@@ -152,18 +150,18 @@ struct Step {
           keep[u] = (t + u < cnt) ? 0xffffffffu : 0u;
         }
         if (col_ok) {
-          float x[8][VEC];
+          RawRow<TU, VEC> x[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int32_t jj = (t + u < cnt) ? j[u] : j[0];
-            VecIO<TU, VEC>::load(U + int64_t(jj) * ldu + c0, x[u]);
+            x[u].load(U + int64_t(jj) * ldu + c0);
           }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int v = 0; v < VEC; ++v)
               acc[v] = fmaf(__uint_as_float(__float_as_uint(sv[u]) & keep[u]),
-                            __uint_as_float(__float_as_uint(x[u][v]) & keep[u]), acc[v]);
+                            __uint_as_float(__float_as_uint(x[u].get(v)) & keep[u]), acc[v]);
         }
       }
       if (PREFETCH) {
@@ -568,6 +566,26 @@ sped_status dispatch_types(const sped_csr *L, int64_t k, const StepArgs &a, cons
   return fail(SPED_E_UNSUPPORTED, "spmm dtype combination");
 }
 
+// 8 columns per lane for a bf16 gathered block (one 16-byte load per lane and
+// row): half the lanes per row, so a wavefront keeps twice the rows in flight.
+sped_status dispatch_bf16_vec8(const sped_csr *L, int64_t k, const StepArgs &a, const Geometry &g,
+                               hipStream_t s) {
+  const bool v32 = a.tv == SPED_F32, o32 = a.to == SPED_F32;
+  if (!v32 && !o32) return launch_typed<bf16_t, bf16_t, bf16_t, 8, false>(L, k, a, g, s);
+  if (!v32 && o32) return launch_typed<bf16_t, bf16_t, float, 8, false>(L, k, a, g, s);
+  if (v32 && o32) return launch_typed<bf16_t, float, float, 8, false>(L, k, a, g, s);
+  return launch_typed<bf16_t, float, bf16_t, 8, false>(L, k, a, g, s);
+}
+
+bool vec8_ok(int64_t k, std::initializer_list<int64_t> lds, std::initializer_list<const void *> ptrs) {
+  if (k % 8) return false;
+  for (int64_t ld : lds)
+    if (ld % 8) return false;
+  for (const void *p : ptrs)
+    if (p && (reinterpret_cast<uintptr_t>(p) & 15)) return false;
+  return true;
+}
+
 }  // namespace
 
 size_t spmm_step_ws_bytes(const sped_csr *L, int64_t k) {
@@ -594,8 +612,12 @@ sped_status launch_spmm_step(const sped_csr *L, int64_t k, const StepArgs &a, hi
     b.ldv = a.ldu;
     b.tv = a.tu;
   }
-  Geometry g = geometry(L, k, vec);
   const bool dot = a.dotw != nullptr;
+  if (vec == 4 && !dot && a.tu == SPED_BF16 && vec8_ok(k, {a.ldu, b.ldv, a.ldo}, {a.U, b.V, a.O})) {
+    if (partials_written) *partials_written = 0;
+    return dispatch_bf16_vec8(L, k, b, geometry(L, k, 8), s);
+  }
+  Geometry g = geometry(L, k, vec);
   if (partials_written) *partials_written = dot ? partial_count(g) : 0;
   if (vec == 4) return dot ? dispatch_types<4, true>(L, k, b, g, s) : dispatch_types<4, false>(L, k, b, g, s);
   if (vec == 2) return dot ? dispatch_types<2, true>(L, k, b, g, s) : dispatch_types<2, false>(L, k, b, g, s);

@@ -172,6 +172,30 @@ def test_apply_poly_bf16(sped, xdt, ydt):
     assert _rel(Y, Yr) < tol
 
 
+@pytest.mark.parametrize("k", [8, 64, 72])
+@pytest.mark.parametrize("ydt", ["bf16", "f32"])
+def test_bf16_gather_eight_columns_per_lane(sped, k, ydt):
+    """A bf16 block whose width is a multiple of 8 is gathered 8 columns per
+    lane (one 16-byte load per lane and row): one step L X and the degree-3
+    Taylor chain on the hub graph (light, medium and heavy rows), against the
+    oracle on the bf16-rounded input."""
+    n, src, dst, w = mixed_degree_graph()
+    _say(f"bf16 8-column gathers k={k} y={ydt}")
+    L = sped.Laplacian(n, src, dst, w, kind="sym")
+    ref = olap.laplacian(n, src, dst, w, kind=olap.SYM_NORMALIZED)
+    Xb = torch.from_numpy(synth.gaussian_block(n, k, 6).astype(np.float32)).cuda().to(torch.bfloat16)
+    X64 = Xb.float().cpu().numpy().astype(np.float64)
+    out_dt = torch.bfloat16 if ydt == "bf16" else torch.float32
+    Y = sped.apply_poly(L, sped.monomial([0.0, 1.0]), Xb, out_dtype=out_dt).float().cpu().numpy()
+    Yr = ref.L @ X64
+    # one float32 sum per entry, then (bf16 output) one rounding of 2^-9
+    rel = 2.0 ** -8 if ydt == "bf16" else 1e-5
+    assert np.all(np.abs(Y - Yr) <= rel * np.abs(Yr) + 1e-5 * np.abs(Yr).max())
+    Y3 = sped.apply_poly(L, sped.transform("taylor_exp", 3), Xb, out_dtype=out_dt).float().cpu().numpy()
+    Y3r = opoly.apply_terms(ref.L, opoly.taylor_exp(3), X64)
+    assert _rel(Y3, Y3r) < (3e-5 + (2.0 ** -8 if ydt == "bf16" else 0.0))
+
+
 def test_apply_poly_padded_ld_and_tiny(sped):
     """leading dimension > k, k = 1, and n smaller than one block."""
     _say("apply_poly padded ld / k=1 / tiny n")
