@@ -562,7 +562,9 @@ sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t l
   const bool vec4 = kin % 4 == 0 && ldx % 4 == 0 && xa % (4 * sizeof(TX)) == 0;
   if (vec4) {
     const int kmax = kin > kout ? kin : kout;
-    const int TB = kmax <= 16 ? 1 : kmax <= 32 ? 2 : kmax <= 64 ? 4 : 8;
+    // 16-column tiles; 5 and 6 are instantiated so that widths of 65..96 (the
+    // solver's 64 + guard) do not pay for 8 tiles of matrix-core work
+    const int TB = kmax <= 16 ? 1 : kmax <= 32 ? 2 : kmax <= 64 ? 4 : kmax <= 80 ? 5 : kmax <= 96 ? 6 : 8;
     const size_t shm = size_t((kin + 15) & ~15) * tsmm4_lds_stride(16 * TB) * sizeof(float);
     const int64_t strips = (n + 15) / 16;
     const int64_t want = (strips + 15) / 16;  // about 4 strips per wavefront
@@ -577,6 +579,8 @@ sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t l
     if (TB == 1) SPED_TSMM4(1)
     else if (TB == 2) SPED_TSMM4(2)
     else if (TB == 4) SPED_TSMM4(4)
+    else if (TB == 5) SPED_TSMM4(5)
+    else if (TB == 6) SPED_TSMM4(6)
     else SPED_TSMM4(8)
 #undef SPED_TSMM4
     SPED_CHECK_HIP(hipGetLastError());
@@ -597,6 +601,8 @@ sped_status launch_tsmm_t(int64_t n, int kin, int kout, const void *X, int64_t l
   if (TBO <= 1) SPED_TSMM(1)
   else if (TBO <= 2) SPED_TSMM(2)
   else if (TBO <= 4) SPED_TSMM(4)
+  else if (TBO == 5) SPED_TSMM(5)
+  else if (TBO == 6) SPED_TSMM(6)
   else SPED_TSMM(8)
 #undef SPED_TSMM
   SPED_CHECK_HIP(hipGetLastError());
@@ -660,10 +666,17 @@ sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *pa
     if (TA == 2 && TB == 1) return launch_gram_narrow_t<LD, 2, 1, SYM>(n, ka, kb, ld, partials, p, s);
     return launch_gram_narrow_t<LD, 2, 2, SYM>(n, ka, kb, ld, partials, p, s);
   }
+  // TBM = TB where instantiated: column tiles past TB would still be loaded
+  // (clamped) by every lane, and the wide kernel is bound by its load
+  // instructions
   if (TA <= 4) {
     if (TB <= 4) return launch_gram_wide_t<LD, 4, 4, SYM>(n, ka, kb, ld, partials, p, s);
+    if (TB == 5) return launch_gram_wide_t<LD, 5, 4, SYM>(n, ka, kb, ld, partials, p, s);
+    if (TB == 6) return launch_gram_wide_t<LD, 6, 4, SYM>(n, ka, kb, ld, partials, p, s);
     return launch_gram_wide_t<LD, 8, 4, SYM>(n, ka, kb, ld, partials, p, s);
   }
+  if (TB == 5) return launch_gram_wide_t<LD, 5, 8, SYM>(n, ka, kb, ld, partials, p, s);
+  if (TB == 6) return launch_gram_wide_t<LD, 6, 8, SYM>(n, ka, kb, ld, partials, p, s);
   return launch_gram_wide_t<LD, 8, 8, SYM>(n, ka, kb, ld, partials, p, s);
 }
 
