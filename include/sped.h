@@ -418,7 +418,10 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  *  resid   HOST double [k] or NULL: final residual norms
  *  o, st   HOST options / statistics
  * Synchronous.  Returns SPED_E_NOT_CONVERGED (with outputs and stats filled)
- * when max_iters is reached first.
+ * when max_iters is reached first.  A start block that is rank deficient (a
+ * repeated or zero column) has those columns replaced by uniform random ones
+ * (Philox keyed by seed) before the first iteration, counted in
+ * st->reseeded; a start block that is not finite returns SPED_E_NUMERIC.
  */
 typedef struct {
   int32_t solver;          /* 0 = subspace iteration (eta = inf), 1 = block Oja,
@@ -467,6 +470,7 @@ typedef struct {
   int32_t coarse_iters;    /* iterations done with BF16 storage */
   int32_t polish_iters;    /* iterations done on the plain operator after p(L) stalled */
   int32_t trace_len;       /* checks recorded in o->trace */
+  int32_t reseeded;        /* start-block columns replaced by random ones (rank deficient V0) */
 } sped_solve_stats;
 
 sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p, int64_t k, const void *V0,

@@ -97,6 +97,42 @@ sped_status scale_cols(int64_t n, int k, const float *X, int64_t ldx, const doub
   return SPED_OK;
 }
 
+// Columns of an orthonormalised start block whose squared norm came out
+// below 1/4 (the start block was rank deficient there: a repeated or zero
+// column, which the shifted Cholesky leaves near zero); bad[k] counts them,
+// and bad[k + 1] is set when the Gram is not finite.
+__global__ void flag_columns_kernel(int k, const double *__restrict__ G, int *__restrict__ bad) {
+  if (threadIdx.x == 0) {
+    bad[k] = 0;
+    bad[k + 1] = 0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double d = G[j * k + j];
+    bool finite = isfinite(d);
+    for (int c = 0; c < k; ++c) finite = finite && isfinite(G[j * k + c]);
+    bad[j] = finite && d < 0.25 ? 1 : 0;
+    if (bad[j]) atomicAdd(bad + k, 1);
+    if (!finite) atomicOr(bad + k + 1, 1);
+  }
+}
+
+// Fresh uniform [-1, 1) entries in the flagged columns: Philox keyed by the
+// solver seed, counter (row, column, 0xFFFFFFFF - attempt, 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void reseed_columns_kernel(int64_t n, int k, T *__restrict__ Q, int64_t ld,
+                                                                const int *__restrict__ bad, uint32_t k0,
+                                                                uint32_t k1, uint32_t attempt) {
+  const int64_t total = n * k;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total; i += int64_t(gridDim.x) * kBlock) {
+    const int64_t r = i / k;
+    const int c = int(i - r * k);
+    if (!bad[c]) continue;
+    const double u = uniform53(k0, k1, uint32_t(r), uint32_t(c), 0xFFFFFFFFu - attempt, 0);
+    Q[r * ld + c] = from_f32<T>(float(2.0 * u - 1.0));
+  }
+}
+
 struct OrthWs {
   double *G, *T, *partials;
   int *flags;
@@ -518,12 +554,45 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     return SPED_OK;
   };
 
+  // First orthonormalisation of the start block (W -> Q, storage dt): one
+  // Cholesky-QR pass, then columns left near zero (V0 rank deficient there)
+  // are replaced by random ones and the block orthonormalised again, up to 3
+  // times; then the remaining passes.
+  int *bad = reinterpret_cast<int *>(rw.resid);  // kb + 2 ints inside the kb doubles of resid (kb >= 2)
+  auto start_block = [&](int dt, const void *Win, void *Qout) -> sped_status {
+    SPED_TRY(cholqr(n, int(kb), Win, Qout, kb, dt, 1, nullptr, ow, s));
+    for (int attempt = 0; attempt < 3; ++attempt) {
+      SPED_TRY(launch_gram(n, int(kb), int(kb), Qout, kb, dt, Qout, kb, dt, ow.G, ow.partials, s));
+      hipLaunchKernelGGL(flag_columns_kernel, dim3(1), dim3(128), 0, s, int(kb), ow.G, bad);
+      SPED_CHECK_HIP(hipGetLastError());
+      int hb[2] = {0, 0};
+      SPED_CHECK_HIP(hipMemcpyAsync(hb, bad + kb, sizeof(hb), hipMemcpyDeviceToHost, s));
+      SPED_CHECK_HIP(hipStreamSynchronize(s));
+      if (hb[1]) return fail(SPED_E_NUMERIC, "start block is not finite");
+      if (hb[0] == 0) break;
+      stats.reseeded += hb[0];
+      int64_t blocks = (n * kb + kBlock - 1) / kBlock;
+      if (blocks > 8192) blocks = 8192;
+      const uint32_t k0 = uint32_t(o->seed), k1 = uint32_t(o->seed >> 32);
+      if (dt == SPED_BF16)
+        hipLaunchKernelGGL(reseed_columns_kernel<bf16_t>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, n, int(kb),
+                           static_cast<bf16_t *>(Qout), kb, bad, k0, k1, uint32_t(attempt));
+      else
+        hipLaunchKernelGGL(reseed_columns_kernel<float>, dim3(unsigned(blocks)), dim3(kBlock), 0, s, n, int(kb),
+                           static_cast<float *>(Qout), kb, bad, k0, k1, uint32_t(attempt));
+      SPED_CHECK_HIP(hipGetLastError());
+      SPED_TRY(cholqr(n, int(kb), Qout, Qout, kb, dt, 1, nullptr, ow, s));
+    }
+    if (o->orth_passes > 1) SPED_TRY(cholqr(n, int(kb), Qout, Qout, kb, dt, o->orth_passes - 1, nullptr, ow, s));
+    return SPED_OK;
+  };
+
   void *Q = Q32, *W = W32;
   bool done = false;
   if (two_phase) {
     void *Qh = Q16, *Wh = W16;
     SPED_TRY(copy_block(n, int(kb), V0, ldv0, SPED_F32, Wh, kb, SPED_BF16, s));
-    SPED_TRY(cholqr(n, int(kb), Wh, Qh, kb, SPED_BF16, o->orth_passes, nullptr, ow, s));
+    SPED_TRY(start_block(SPED_BF16, Wh, Qh));
     SPED_TRY(phase(SPED_BF16, Qh, Wh, coarse_tol, o->max_iters, 8, INFINITY, &done));
     stats.coarse_iters = t;
     // refinement sweep: the bf16 iterate seeds float32 iterations
@@ -535,7 +604,7 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
     SPED_TRY(launch_gram(n, int(kb), int(kb), W, kb, SPED_F32, W, kb, SPED_F32, G3, ow.partials, s));
     SPED_TRY(scale_cols(n, int(kb), static_cast<const float *>(W), kb, G3, static_cast<float *>(Q), kb, s));
   } else {
-    SPED_TRY(cholqr(n, int(kb), W, Q, kb, SPED_F32, o->orth_passes, nullptr, ow, s));
+    SPED_TRY(start_block(SPED_F32, W, Q));
   }
   done = false;
   const bool polish = o->polish_checks > 0 && p != nullptr;

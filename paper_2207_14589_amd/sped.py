@@ -52,7 +52,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iters", _c_i32), ("spmm_count", _c_i64), ("seconds", _c_f64), ("max_residual", _c_f64),
                 ("gap_estimate", _c_f64), ("bound", _c_f64), ("converged", _c_i32),
                 ("cholqr_shifts", _c_i32), ("coarse_iters", _c_i32), ("polish_iters", _c_i32),
-                ("trace_len", _c_i32)]
+                ("trace_len", _c_i32), ("reseeded", _c_i32)]
 
 
 _P = ctypes.POINTER

@@ -1318,3 +1318,29 @@ def test_stochastic_counter_base_and_check_log(sped, tmp_path):
     assert len(lines) == r.stats["iters"] + 1  # check_every = 1
     assert lines[-1]["result"]["converged"] == 1
     assert lines[-2]["bound"] == r.stats["bound"] <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_rank_deficient_start_block_reseeded(sped, storage):
+    """A start block with a repeated column and a zero column: those columns
+    are replaced by random ones before the first iteration (counted in the
+    stats) and the solve reaches the dense-eigh subspace; a start block with
+    a NaN is refused with SPED_E_NUMERIC."""
+    _say(f"rank-deficient start block, storage {storage}")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    lam, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = synth.gaussian_block(n, 14, 2).astype(np.float32)
+    V0[:, 3] = V0[:, 1]
+    V0[:, 7] = 0.0
+    r = sped.bottomk(L, 10, sped.transform("limit", 8), V0=torch.from_numpy(V0).cuda(), guard=4, tol=1e-6,
+                     max_iters=3000, storage=storage)
+    assert r.stats["reseeded"] == 2
+    assert r.converged
+    assert osol.max_principal_angle(U, r.V.cpu().numpy().astype(np.float64)) <= 1e-6
+    V0[5, 2] = np.nan
+    with pytest.raises(sped.SpedError) as e:
+        sped.bottomk(L, 10, sped.transform("limit", 8), V0=torch.from_numpy(V0).cuda(), guard=4, tol=1e-6,
+                     max_iters=10)
+    assert e.value.status == sped.E_NUMERIC
