@@ -143,6 +143,10 @@ def _dt(t):
 
 
 def _ld(t):
+    """Leading dimension of a device block; every block handed to the library
+    goes through here, so a host tensor is refused before any pointer is."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("blocks must be CUDA tensors on the library's device")
     if t.dim() != 2 or t.stride(1) != 1:
         raise ValueError("blocks must be 2-D with unit column stride")
     return t.stride(0)

@@ -286,3 +286,15 @@ def test_blocked_chain_validation(lib):
     assert f(ctypes.byref(c), ctypes.byref(p), 1000, 32, X, 32, sped.F32, Y, 32, sped.F32, None,
              ctypes.byref(need), None) == sped.OK
     assert need.value >= 2 * 1000 * 32 * 4
+
+
+def test_binding_refuses_host_blocks(lib):
+    """Every dense block passes through the binding's leading-dimension check,
+    which refuses host tensors before a pointer reaches the library."""
+    import torch
+    with pytest.raises(TypeError):
+        sped.gram(torch.zeros(16, 4))
+    with pytest.raises(TypeError):
+        sped.orthonormalize(torch.zeros(16, 4))
+    with pytest.raises(TypeError):
+        sped.cluster_embed(torch.zeros(16, 4), 2)
