@@ -225,8 +225,9 @@ sped_status sped_apply_poly_noalloc(const sped_csr *L, const sped_poly *p, int64
 /*
  * sped_apply_poly_blocked -- Y = M X as sped_apply_poly, with the chain's
  * steps fused two at a time (a matrix-powers form for graphs whose rows are
- * ordered by community; Sec. 4.3 remarks that the structure of L can be
- * exploited).  Each launch gives one workgroup the `block_rows` consecutive
+ * ordered by community).  Sec. 4.3 weighs ways of forming a product of l
+ * factors (a binary tree in log l time, or walks that use L's incidence
+ * structure); this fuses consecutive factors per block of rows instead.  Each launch gives one workgroup the `block_rows` consecutive
  * rows [b B, (b+1) B): it loads their rows of the current block into LDS,
  * forms the first step's rows there (neighbours outside the block read from
  * global memory), overwrites the LDS copy with them, and forms the second

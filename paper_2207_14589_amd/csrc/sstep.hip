@@ -1,6 +1,7 @@
 // Two consecutive fused steps per launch on row blocks held in LDS (a
 // matrix-powers form of the chain p(L) X for graphs whose rows are ordered by
-// community; Sec. 4.3 notes that the structure of L can be exploited):
+// community; Sec. 4.3 weighs ways of forming a product of l factors, and this
+// fuses consecutive factors per block of rows):
 //   U1 = a1 (L U) + b1 U + g1 X,   U2 = a2 (L U1) + b2 U1 + g2 X
 // One workgroup owns the B consecutive rows [b B, (b+1) B).  It loads those
 // rows of U into LDS with coalesced reads, forms U1 for them (neighbour rows
