@@ -707,6 +707,65 @@ def rmat26_step(sped, synth, torch, np, reps=5):
     return out
 
 
+def reorder_leg(sped, synth, torch, np, graph="powerlaw4m", reps=10):
+    """Node orders for gather locality (sped_laplacian_csr_ordered), timed
+    apart from the solve: the build with each order against the plain build,
+    the order alone on the built Laplacian, and one fused step L X per block
+    width on each numbering.  powerlaw4m: the 4e6-node Chung-Lu workload
+    (largest component); rmat26: R-MAT scale 26 (largest component)."""
+    if graph == "rmat26":
+        n0, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
+        widths = ((64, torch.bfloat16, 1), (72, torch.bfloat16, 2), (72, torch.float32, 3))
+        reps = 3
+        desc = "R-MAT scale 26, edge factor 16 (0.57, 0.19, 0.19), device draw; largest component"
+    else:
+        n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
+        widths = ((64, torch.bfloat16, 1), (64, torch.float32, 2))
+        desc = ("Chung-Lu n=4e6 (device draw), exponent 2.1, mean degree 16, 256 communities; largest "
+                "component")
+    out = {"workload": desc + "; sym-normalised L; one fused step L X per width", "reps": reps}
+    one = sped.monomial([0.0, 1.0])
+    for order in (None, "degree", "cuthill_mckee"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False, order=order)
+        torch.cuda.synchronize()
+        rec = {"build_s": round(time.perf_counter() - t0, 3)}
+        if order is None:
+            out["n_lcc"], out["nnz"] = L.n, L.nnz
+            for method in ("degree", "cuthill_mckee"):
+                sped.locality_order(L, method)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sped.locality_order(L, method)
+                torch.cuda.synchronize()
+                rec[f"order_only_{method}_s"] = round(time.perf_counter() - t0, 3)
+        for k, dt, lines in widths:
+            X = synth.gaussian_block_device(L.n, k, seed=2, dtype=dt)
+            Y = torch.empty_like(X)
+            sped.apply_poly(L, one, X, out=Y)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                sped.apply_poly(L, one, X, out=Y)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            ms = float(np.median(ts))
+            alg = 8 * (L.n + 1) + L.nnz * 8 + 4 * L.n + L.n * k * 2 * X.element_size()
+            rec[f"k{k}_{str(dt).split('.')[-1]}"] = {"step_ms": round(ms, 3), "alg_GBps": round(alg / ms / 1e6, 1)}
+            del X, Y
+            torch.cuda.empty_cache()
+        name = order or "given_ids"
+        out[name] = rec
+        print(json.dumps({"reorder": graph, "order": name, **rec}), flush=True)
+        del L
+        torch.cuda.empty_cache()
+    return out
+
+
 def paper_experiments(sped, synth, torch, np):
     """Qualitative reproductions of the paper's own synthetic experiments on
     the GPU solvers (combinatorial Laplacian, as there).
@@ -999,6 +1058,8 @@ def main():
                     help="summarise the two counter databases into the committed traffic file")
     ap.add_argument("--sstep-sweep", action="store_true",
                     help="time the chain as single steps and as two-step launches on LDS row blocks")
+    ap.add_argument("--reorder", choices=["powerlaw4m", "rmat26"],
+                    help="build with each node order and time one fused step per block width on each")
     ap.add_argument("--locality-sweep", action="store_true",
                     help="time the fused step against neighbourhood locality, and a plain copy")
     args = ap.parse_args()
@@ -1050,6 +1111,9 @@ def main():
         return
     if args.rmat26_step:
         print(json.dumps({"rmat26_step": rmat26_step(sped, synth, torch, np)}), flush=True)
+        return
+    if args.reorder:
+        print(json.dumps({"reorder": reorder_leg(sped, synth, torch, np, args.reorder)}), flush=True)
         return
     if args.power_law_only:
         print(json.dumps({"power_law_bf16_k64": power_law_bf16(sped, synth, torch, np)}), flush=True)

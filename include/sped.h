@@ -142,6 +142,45 @@ sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *src, const i
                                sped_stream_t stream);
 
 /*
+ * Node orders for gather locality.  p(L)V (Sec. 4.2) is the same operator
+ * under any relabelling of the nodes, with the rows of V permuted alike; the
+ * paper fixes no order.  An order that places neighbours at nearby ids lets
+ * the sparse products' neighbour-row gathers share cache lines.
+ *  SPED_ORDER_CUTHILL_MCKEE  breadth-first search from the node of largest
+ *      degree (ties: smallest id), appending the unvisited neighbours of
+ *      each dequeued node by increasing (degree, id) (Cuthill and McKee,
+ *      1969); nodes outside that node's component follow in increasing id.
+ *  SPED_ORDER_DEGREE  decreasing degree, ties in increasing id.
+ * Degree = number of distinct neighbours (row length of L's off-diagonal part).
+ */
+typedef enum { SPED_ORDER_CUTHILL_MCKEE = 0, SPED_ORDER_DEGREE = 1 } sped_order;
+
+/*
+ * sped_locality_order -- the position of each node of L in the order `method`.
+ *  L           built by sped_laplacian_csr (its rowptr and col are read; the
+ *              off-diagonal pattern must be symmetric)
+ *  new_of_old  DEVICE int32 [L->n], written: a permutation of 0 .. n-1
+ * One host synchronisation per search level.  The result is deterministic
+ * (independent of the order in which the device's atomics land).
+ */
+sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_of_old, void *ws,
+                                size_t *ws_bytes, sped_stream_t stream);
+
+/*
+ * sped_laplacian_csr_ordered -- sped_laplacian_csr, with the kept nodes
+ * numbered in the order `method` computed on the built Laplacian: the graph
+ * is built, ordered, relabelled and built again.  Arguments as for
+ * sped_laplacian_csr; old_of_new (DEVICE int32 [n] or NULL) receives the
+ * original id of each row of the result, so a block V given in original ids
+ * enters as V[old_of_new] and results return by the inverse scatter.  The
+ * workspace holds both builds' needs plus 2m + 3n int32.
+ */
+sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                       const float *w, int32_t kind, int32_t lcc_only, int32_t method,
+                                       sped_csr *out, int32_t *old_of_new, void *ws, size_t *ws_bytes,
+                                       sped_stream_t stream);
+
+/*
  * A polynomial of the Laplacian (Sec. 4.1-4.2, Table 2, reversed by eq. reveig).
  *  SPED_POLY_MONOMIAL: M = sum_{i=0..degree} coeffs[i] Lt^i,
  *                      Lt = (L - shift I) / scale, evaluated by Horner's rule.

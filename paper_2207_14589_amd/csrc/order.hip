@@ -1,0 +1,369 @@
+// Node orders for gather locality, and the Laplacian built in such an order.
+//
+// p(L)V (Sec. 4.2) is the same operator under any relabelling of the nodes,
+// with the rows of V permuted alike; the paper fixes no order.  Placing the
+// neighbours of a node at nearby ids makes the neighbour-row gathers of the
+// sparse products land on fewer distinct cache lines.
+//
+// Cuthill-McKee on the device: a level-synchronous breadth-first search.  The
+// queue form appends the unvisited neighbours of each dequeued node by
+// increasing (degree, id); a node is appended by its earliest-placed
+// neighbour, which lies in the previous level.  So each level is the set of
+// nodes first reached from the previous one, sorted by (position of the
+// earliest-placed neighbour, degree, id): one wavefront per frontier node
+// takes atomicMin of its position over its unplaced neighbours (the first to
+// lower a neighbour's key appends it to the level's list), then two stable
+// radix sorts (by id, then by (key, degree)) fix the level's order.  The
+// result does not depend on the order of the atomics.  Nodes outside the
+// search's component follow in increasing id.
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <climits>
+
+#include "common.h"
+
+namespace sped {
+namespace {
+
+constexpr int kOB = 256;
+inline unsigned oblocks(int64_t n) { return unsigned(std::max<int64_t>(1, (n + kOB - 1) / kOB)); }
+
+int bits_for(uint64_t v) {  // smallest b with v < 2^b
+  int b = 0;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+__global__ void fill_i32(int64_t n, int32_t *__restrict__ a, int32_t v) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// largest (degree, -id): key = degree << 32 | (2^32 - 1 - id)
+__global__ void root_key(int64_t n, const int64_t *__restrict__ rowptr, unsigned long long *__restrict__ best) {
+  __shared__ unsigned long long red[kOB];
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  unsigned long long key = 0;
+  if (i < n)
+    key = (static_cast<unsigned long long>(rowptr[i + 1] - rowptr[i]) << 32) | (0xFFFFFFFFull - uint64_t(i));
+  red[threadIdx.x] = key;
+  __syncthreads();
+  for (int h = kOB / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(best, red[0]);
+}
+
+__global__ void place_root(const unsigned long long *__restrict__ best, int32_t *__restrict__ pos,
+                           int32_t *__restrict__ order) {
+  const int32_t r = int32_t(0xFFFFFFFFull - (*best & 0xFFFFFFFFull));
+  pos[r] = 0;
+  order[0] = r;
+}
+
+// One wavefront per frontier node (positions lo .. lo + cnt - 1).
+__global__ __launch_bounds__(kOB) void expand_level(int64_t lo, int64_t cnt, const int32_t *__restrict__ order,
+                                                    const int64_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const int32_t *__restrict__ pos,
+                                                    int32_t *__restrict__ pkey, int32_t *__restrict__ cand,
+                                                    int32_t *__restrict__ ncand) {
+  const int64_t f = int64_t(blockIdx.x) * (kOB / 64) + threadIdx.x / 64;
+  if (f >= cnt) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t q = int32_t(lo + f);
+  const int32_t v = order[q];
+  const int64_t end = rowptr[v + 1];
+  for (int64_t e = rowptr[v] + lane; e < end; e += 64) {
+    const int32_t u = col[e];
+    if (pos[u] < 0) {
+      const int32_t old = atomicMin(&pkey[u], q);
+      if (old == INT_MAX) cand[atomicAdd(ncand, 1)] = u;
+    }
+  }
+}
+
+// (earliest-placed neighbour's position - lo) << dbits | degree
+__global__ void level_keys(int64_t cnt, int64_t lo, int dbits, const int32_t *__restrict__ ids,
+                           const int32_t *__restrict__ pkey, const int64_t *__restrict__ rowptr,
+                           uint64_t *__restrict__ keys) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t u = ids[i];
+  keys[i] = (uint64_t(int64_t(pkey[u]) - lo) << dbits) | uint64_t(rowptr[u + 1] - rowptr[u]);
+}
+
+__global__ void place_run(int64_t cnt, int64_t base, const int32_t *__restrict__ ids, int32_t *__restrict__ pos,
+                          int32_t *__restrict__ order) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i >= cnt) return;
+  const int32_t u = ids[i];
+  pos[u] = int32_t(base + i);
+  order[base + i] = u;
+}
+
+__global__ void unplaced_flags(int64_t n, const int32_t *__restrict__ pos, char *__restrict__ flags) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n) flags[i] = pos[i] < 0;
+}
+
+// descending degree as an ascending key; ids 0..n-1 as values
+__global__ void degree_keys(int64_t n, const int64_t *__restrict__ rowptr, uint32_t *__restrict__ keys,
+                            int32_t *__restrict__ ids) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = ~uint32_t(rowptr[i + 1] - rowptr[i]);
+  ids[i] = int32_t(i);
+}
+
+struct OrderWs {
+  int32_t *pkey, *order, *cand, *candS, *ids2;
+  uint64_t *k2, *k2s;
+  uint32_t *k32, *k32s;
+  char *flags;
+  int32_t *ncand;
+  int64_t *nsel;
+  unsigned long long *best;
+  void *temp;
+  size_t temp_bytes;
+};
+
+size_t order_temp_bytes(int64_t n) {
+  const int64_t c = n > 0 ? n : 1;
+  size_t a = 0, b = 0, d = 0, e = 0;
+  (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (uint32_t *)nullptr, (uint32_t *)nullptr, c);
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, b, (uint64_t *)nullptr, (uint64_t *)nullptr, (int32_t *)nullptr,
+                                     (int32_t *)nullptr, c);
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, d, (uint32_t *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr,
+                                     (int32_t *)nullptr, c);
+  hipcub::CountingInputIterator<int32_t> ids(0);
+  (void)hipcub::DeviceSelect::Flagged(nullptr, e, ids, (char *)nullptr, (int32_t *)nullptr, (int64_t *)nullptr, c);
+  return std::max(std::max(a, b), std::max(d, e));
+}
+
+OrderWs carve_order(Carver &c, int64_t n) {
+  const int64_t m = n > 0 ? n : 1;
+  OrderWs o;
+  o.pkey = c.take<int32_t>(m);
+  o.order = c.take<int32_t>(m);
+  o.cand = c.take<int32_t>(m);
+  o.candS = c.take<int32_t>(m);
+  o.ids2 = c.take<int32_t>(m);
+  o.k2 = c.take<uint64_t>(m);
+  o.k2s = c.take<uint64_t>(m);
+  o.k32 = reinterpret_cast<uint32_t *>(o.k2);  // the degree order reuses the 64-bit key arrays
+  o.k32s = reinterpret_cast<uint32_t *>(o.k2s);
+  o.flags = c.take<char>(m);
+  o.ncand = c.take<int32_t>(1);
+  o.nsel = c.take<int64_t>(1);
+  o.best = c.take<unsigned long long>(1);
+  o.temp_bytes = order_temp_bytes(n);
+  o.temp = c.take<char>(o.temp_bytes);
+  return o;
+}
+
+sped_status cuthill_mckee(const sped_csr *L, int32_t *pos, const OrderWs &o, hipStream_t s) {
+  const int64_t n = L->n;
+  hipLaunchKernelGGL(fill_i32, dim3(oblocks(n)), dim3(kOB), 0, s, n, pos, int32_t(-1));
+  hipLaunchKernelGGL(fill_i32, dim3(oblocks(n)), dim3(kOB), 0, s, n, o.pkey, int32_t(INT_MAX));
+  SPED_CHECK_HIP(hipMemsetAsync(o.best, 0, sizeof(unsigned long long), s));
+  hipLaunchKernelGGL(root_key, dim3(oblocks(n)), dim3(kOB), 0, s, n, L->rowptr, o.best);
+  hipLaunchKernelGGL(place_root, dim3(1), dim3(1), 0, s, o.best, pos, o.order);
+  SPED_CHECK_HIP(hipGetLastError());
+  unsigned long long best = 0;  // its high half is the largest degree
+  SPED_CHECK_HIP(hipMemcpyAsync(&best, o.best, sizeof(best), hipMemcpyDeviceToHost, s));
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  const int dbits = bits_for(best >> 32);
+  const int idbits = bits_for(uint64_t(n));
+  int64_t lo = 0, hi = 1;
+  while (lo < hi) {
+    const int64_t cnt = hi - lo;
+    SPED_CHECK_HIP(hipMemsetAsync(o.ncand, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(expand_level, dim3(unsigned((cnt + kOB / 64 - 1) / (kOB / 64))), dim3(kOB), 0, s, lo, cnt,
+                       o.order, L->rowptr, L->col, pos, o.pkey, o.cand, o.ncand);
+    SPED_CHECK_HIP(hipGetLastError());
+    int32_t found = 0;
+    SPED_CHECK_HIP(hipMemcpyAsync(&found, o.ncand, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPED_CHECK_HIP(hipStreamSynchronize(s));
+    if (found <= 0) break;
+    if (hi + found > n) return fail(SPED_E_INVALID, "adjacency is not symmetric or has repeated entries");
+    size_t tb = o.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortKeys(o.temp, tb, reinterpret_cast<uint32_t *>(o.cand),
+                                                     reinterpret_cast<uint32_t *>(o.candS), found, 0,
+                                                     std::max(idbits, 1), s));
+    const int kbits = bits_for(uint64_t(cnt - 1)) + dbits;
+    hipLaunchKernelGGL(level_keys, dim3(oblocks(found)), dim3(kOB), 0, s, int64_t(found), lo, dbits, o.candS, o.pkey,
+                       L->rowptr, o.k2);
+    SPED_CHECK_HIP(hipGetLastError());
+    tb = o.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(o.temp, tb, o.k2, o.k2s, o.candS, o.ids2, found, 0,
+                                                      std::max(kbits, 1), s));
+    hipLaunchKernelGGL(place_run, dim3(oblocks(found)), dim3(kOB), 0, s, int64_t(found), hi, o.ids2, pos, o.order);
+    SPED_CHECK_HIP(hipGetLastError());
+    lo = hi;
+    hi += found;
+  }
+  if (hi < n) {  // nodes outside the searched component, in increasing id
+    hipLaunchKernelGGL(unplaced_flags, dim3(oblocks(n)), dim3(kOB), 0, s, n, pos, o.flags);
+    SPED_CHECK_HIP(hipGetLastError());
+    hipcub::CountingInputIterator<int32_t> ids(0);
+    size_t tb = o.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceSelect::Flagged(o.temp, tb, ids, o.flags, o.cand, o.nsel, n, s));
+    hipLaunchKernelGGL(place_run, dim3(oblocks(n - hi)), dim3(kOB), 0, s, n - hi, hi, o.cand, pos, o.order);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  return SPED_OK;
+}
+
+sped_status degree_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipStream_t s) {
+  const int64_t n = L->n;
+  hipLaunchKernelGGL(degree_keys, dim3(oblocks(n)), dim3(kOB), 0, s, n, L->rowptr, o.k32, o.cand);
+  SPED_CHECK_HIP(hipGetLastError());
+  size_t tb = o.temp_bytes;
+  SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(o.temp, tb, o.k32, o.k32s, o.cand, o.candS, n, 0, 32, s));
+  hipLaunchKernelGGL(place_run, dim3(oblocks(n)), dim3(kOB), 0, s, n, int64_t(0), o.candS, pos, o.order);
+  SPED_CHECK_HIP(hipGetLastError());
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  return SPED_OK;
+}
+
+sped_status run_order(const sped_csr *L, int32_t method, int32_t *pos, const OrderWs &o, hipStream_t s) {
+  if (L->n == 0) return SPED_OK;
+  return method == SPED_ORDER_CUTHILL_MCKEE ? cuthill_mckee(L, pos, o, s) : degree_order(L, pos, o, s);
+}
+
+// map[old_of_new1[i]] = pos[i] for the kept nodes; -1 elsewhere
+__global__ void scatter_kept(int64_t n1, const int32_t *__restrict__ old_of_new1, const int32_t *__restrict__ pos,
+                             int32_t *__restrict__ map) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n1) map[old_of_new1[i]] = pos[i];
+}
+
+__global__ void dropped_flags(int64_t n, const int32_t *__restrict__ map, int64_t *__restrict__ flags) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n) flags[i] = map[i] < 0;
+}
+
+__global__ void place_dropped(int64_t n, int64_t n1, const int64_t *__restrict__ rank, int32_t *__restrict__ map) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n && map[i] < 0) map[i] = int32_t(n1 + rank[i]);
+}
+
+// endpoints outside [0, n) are left as they are, for the build to reject
+__global__ void relabel(int64_t m, int64_t n, const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
+                        const int32_t *__restrict__ map, int32_t *__restrict__ src2, int32_t *__restrict__ dst2) {
+  const int64_t e = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (e >= m) return;
+  const int32_t a = src[e], b = dst[e];
+  src2[e] = (a >= 0 && a < n) ? map[a] : a;
+  dst2[e] = (b >= 0 && b < n) ? map[b] : b;
+}
+
+__global__ void compose_old(int64_t n1, const int32_t *__restrict__ old_of_new1, const int32_t *__restrict__ pos,
+                            int32_t *__restrict__ old_of_new) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n1) old_of_new[pos[i]] = old_of_new1[i];
+}
+
+// the build's workspace size (a size query: nothing runs)
+size_t build_ws_bytes(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, int32_t kind) {
+  size_t b = 0;
+  sped_csr probe{};
+  sped_laplacian_csr(n, m, src, dst, nullptr, kind, 0, &probe, nullptr, nullptr, &b, nullptr);
+  return b;
+}
+
+}  // namespace
+}  // namespace sped
+
+using namespace sped;
+
+extern "C" sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_of_old, void *ws,
+                                           size_t *ws_bytes, sped_stream_t stream) {
+  clear_error();
+  if (method != SPED_ORDER_CUTHILL_MCKEE && method != SPED_ORDER_DEGREE) return fail(SPED_E_INVALID, "method");
+  if (!L) return fail(SPED_E_INVALID, "L NULL");
+  if (L->n < 0 || L->n >= (int64_t(1) << 31) - 1) return fail(SPED_E_INVALID, "n outside [0, 2^31 - 1)");
+  Carver c(ws);
+  const OrderWs o = carve_order(c, L->n);
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+  if (L->n > 0 && (!L->rowptr || !L->col || !new_of_old)) return fail(SPED_E_INVALID, "NULL array");
+  return run_order(L, method, new_of_old, o, as_stream(stream));
+}
+
+extern "C" sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                                  const float *w, int32_t kind, int32_t lcc_only, int32_t method,
+                                                  sped_csr *out, int32_t *old_of_new, void *ws, size_t *ws_bytes,
+                                                  sped_stream_t stream) {
+  clear_error();
+  if (method != SPED_ORDER_CUTHILL_MCKEE && method != SPED_ORDER_DEGREE) return fail(SPED_E_INVALID, "method");
+  if (n < 0 || n >= (int64_t(1) << 31) - 1) return fail(SPED_E_INVALID, "n outside [0, 2^31 - 1)");
+  if (m < 0 || m > (int64_t(1) << 40)) return fail(SPED_E_INVALID, "m out of range");
+  if (m > 0 && (!src || !dst)) return fail(SPED_E_INVALID, "src/dst NULL");
+  if (kind != SPED_LAP_COMBINATORIAL && kind != SPED_LAP_SYM_NORMALIZED) return fail(SPED_E_INVALID, "kind");
+  if (!out) return fail(SPED_E_INVALID, "out NULL");
+  // region A serves the two builds and the order in turn; region B holds the
+  // relabelled edges and the maps between the three labellings
+  const size_t a_bytes = std::max(build_ws_bytes(n, m, src, dst, kind), [&] {
+    Carver t(nullptr);
+    carve_order(t, n);
+    size_t scan = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int64_t *)nullptr, (int64_t *)nullptr, n > 0 ? n : 1);
+    return std::max(t.bytes(), ((scan + 255) & ~size_t(255)) + 2 * (size_t(n + 1) * 8 + 256));
+  }());
+  Carver c(ws);
+  char *regionA = c.take<char>(a_bytes);
+  int32_t *src2 = c.take<int32_t>(m > 0 ? m : 1);
+  int32_t *dst2 = c.take<int32_t>(m > 0 ? m : 1);
+  int32_t *oon1 = c.take<int32_t>(n > 0 ? n : 1);
+  int32_t *pos = c.take<int32_t>(n > 0 ? n : 1);
+  int32_t *map = c.take<int32_t>(n > 0 ? n : 1);
+  bool query;
+  SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
+  if (query) return SPED_OK;
+  hipStream_t s = as_stream(stream);
+  size_t ab = a_bytes;
+  SPED_TRY(sped_laplacian_csr(n, m, src, dst, w, kind, lcc_only, out, oon1, regionA, &ab, stream));
+  const int64_t n1 = out->n;
+  if (n1 == 0) {
+    return SPED_OK;
+  }
+  ab = a_bytes;
+  SPED_TRY(sped_locality_order(out, method, pos, regionA, &ab, stream));
+  SPED_CHECK_HIP(hipMemsetAsync(map, 0xFF, sizeof(int32_t) * n, s));  // -1
+  hipLaunchKernelGGL(scatter_kept, dim3(oblocks(n1)), dim3(kOB), 0, s, n1, oon1, pos, map);
+  SPED_CHECK_HIP(hipGetLastError());
+  if (n1 < n) {  // nodes outside the kept component: after it, in increasing id
+    Carver t(regionA);
+    int64_t *flags = t.take<int64_t>(n + 1);
+    int64_t *rank = t.take<int64_t>(n + 1);
+    void *temp = t.take<char>(0);
+    size_t tb = a_bytes - (static_cast<char *>(temp) - regionA);
+    hipLaunchKernelGGL(dropped_flags, dim3(oblocks(n)), dim3(kOB), 0, s, n, map, flags);
+    SPED_CHECK_HIP(hipGetLastError());
+    SPED_CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, flags, rank, n, s));
+    hipLaunchKernelGGL(place_dropped, dim3(oblocks(n)), dim3(kOB), 0, s, n, n1, rank, map);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  if (m > 0) {
+    hipLaunchKernelGGL(relabel, dim3(oblocks(m)), dim3(kOB), 0, s, m, n, src, dst, map, src2, dst2);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  // The kept component now holds ids 0 .. n1-1 and node 0, so the largest-
+  // component rule keeps it again and its increasing-id relabelling is the
+  // identity: the rows come out in the computed order.
+  ab = a_bytes;
+  SPED_TRY(sped_laplacian_csr(n, m, src2, dst2, w, kind, lcc_only, out, nullptr, regionA, &ab, stream));
+  if (out->n != n1) return fail(SPED_E_INVALID, "reordered build kept a different node count");
+  if (old_of_new) {
+    hipLaunchKernelGGL(compose_old, dim3(oblocks(n1)), dim3(kOB), 0, s, n1, oon1, pos, old_of_new);
+    SPED_CHECK_HIP(hipGetLastError());
+  }
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  return SPED_OK;
+}

@@ -59,6 +59,9 @@ _P = ctypes.POINTER
 SIGNATURES = {
     "sped_laplacian_csr": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_i32, _c_i32, _P(CSR), _c_vp, _c_vp,
                            _P(_c_sz), _c_vp],
+    "sped_locality_order": [_P(CSR), _c_i32, _c_vp, _c_vp, _P(_c_sz), _c_vp],
+    "sped_laplacian_csr_ordered": [_c_i64, _c_i64, _c_vp, _c_vp, _c_vp, _c_i32, _c_i32, _c_i32, _P(CSR), _c_vp,
+                                   _c_vp, _P(_c_sz), _c_vp],
     "sped_transform_coeffs": [_c_i32, _c_i32, _c_f64, _c_f64, _P(_c_f64), _P(_c_f64), _P(_c_f64)],
     "sped_poly_monomial": [_P(Poly), _P(_c_f64)],
     "sped_poly_rebase": [_P(Poly), _c_f64, _c_f64, _P(_c_f64)],
@@ -174,11 +177,21 @@ def _call_ws(fn, where, args_before_ws, device, allow=()):
 
 
 # ------------------------------------------------------------------ Laplacian
-class Laplacian:
-    """Device split CSR of L = diag - S built by sped_laplacian_csr."""
+ORDERS = {"cuthill_mckee": 0, "cm": 0, "degree": 1}
 
-    def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda", walk_records=True):
+
+class Laplacian:
+    """Device split CSR of L = diag - S built by sped_laplacian_csr.
+
+    order: None keeps the given ids (the largest component, if `lcc`, in
+    increasing id); "cuthill_mckee" / "cm" or "degree" numbers the rows in
+    that order (sped_laplacian_csr_ordered).  old_of_new holds the original id
+    of each row either way."""
+
+    def __init__(self, n, src, dst, w=None, kind="sym", lcc=False, device="cuda", walk_records=True, order=None):
         dev = torch.device(device)
+        if order is not None and order not in ORDERS:
+            raise ValueError(f"order must be None or one of {sorted(ORDERS)}")
 
         def dev_tensor(x, dt):
             if isinstance(x, torch.Tensor):
@@ -211,10 +224,15 @@ class Laplacian:
         c.wentry, c.wnode = (self.wentry.data_ptr(), self.wnode.data_ptr()) if walk_records else (None, None)
         kind_i = {"sym": SYM_NORMALIZED, "combinatorial": COMBINATORIAL}[kind] if isinstance(kind, str) else kind
         self.kind = kind_i
-        fn = lib().sped_laplacian_csr
-        _call_ws(fn, "sped_laplacian_csr",
-                 (n, m, _ptr(src), _ptr(dst), _ptr(wt), kind_i, int(bool(lcc)), ctypes.byref(c),
-                  _ptr(self.old_of_new)), dev)
+        if order is None:
+            _call_ws(lib().sped_laplacian_csr, "sped_laplacian_csr",
+                     (n, m, _ptr(src), _ptr(dst), _ptr(wt), kind_i, int(bool(lcc)), ctypes.byref(c),
+                      _ptr(self.old_of_new)), dev)
+        else:
+            _call_ws(lib().sped_laplacian_csr_ordered, "sped_laplacian_csr_ordered",
+                     (n, m, _ptr(src), _ptr(dst), _ptr(wt), kind_i, int(bool(lcc)), ORDERS[order],
+                      ctypes.byref(c), _ptr(self.old_of_new)), dev)
+        self.order = order
         self.c = c
         self.n, self.nnz = c.n, c.nnz
         self.max_degree, self.lambda_bound = c.max_degree, c.lambda_bound
@@ -231,6 +249,15 @@ class Laplacian:
         n, nnz = self.n, self.nnz
         return (self.rowptr[: n + 1].cpu().numpy(), self.col[:nnz].cpu().numpy(), self.val[:nnz].cpu().numpy(),
                 self.diag[:n].cpu().numpy(), self.scale[:n].cpu().numpy())
+
+
+def locality_order(L: Laplacian, method="cuthill_mckee"):
+    """Position of each row of L in the order `method` (device int32 [L.n])."""
+    if method not in ORDERS:
+        raise ValueError(f"method must be one of {sorted(ORDERS)}")
+    out = torch.empty(max(L.n, 1), dtype=torch.int32, device=L.device)
+    _call_ws(lib().sped_locality_order, "sped_locality_order", (L.ref, ORDERS[method], _ptr(out)), L.device)
+    return out[: L.n]
 
 
 # ------------------------------------------------------------------ polynomials

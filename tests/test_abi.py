@@ -298,3 +298,28 @@ def test_binding_refuses_host_blocks(lib):
         sped.orthonormalize(torch.zeros(16, 4))
     with pytest.raises(TypeError):
         sped.cluster_embed(torch.zeros(16, 4), 2)
+
+
+def test_locality_order_validation(lib):
+    """Node orders: an unknown method or a NULL input is refused before any
+    device work; the ordered build's size query is host arithmetic."""
+    need = ctypes.c_size_t(0)
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 100, 400, sped.SYM_NORMALIZED
+    assert lib.sped_locality_order(ctypes.byref(c), 2, None, None, ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_locality_order(None, 0, None, None, ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_locality_order(ctypes.byref(c), 0, None, None, ctypes.byref(need), None) == sped.OK
+    assert need.value >= 100 * (5 * 4 + 2 * 8)
+    out = sped.CSR()
+    assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, sped.SYM_NORMALIZED, 1, 7, ctypes.byref(out), None,
+                                          None, ctypes.byref(need), None) == sped.E_INVALID
+    assert b"method" in lib.sped_last_error()
+    assert lib.sped_laplacian_csr_ordered(100, 200, None, None, None, sped.SYM_NORMALIZED, 1, 0, ctypes.byref(out),
+                                          None, None, ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, 9, 1, 0, ctypes.byref(out), None, None,
+                                          ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, sped.SYM_NORMALIZED, 1, 0, ctypes.byref(out),
+                                          None, None, ctypes.byref(need), None) == sped.OK
+    assert need.value >= 2 * 200 * 4 + 3 * 100 * 4
+    with pytest.raises(ValueError):
+        sped.Laplacian(3, [0], [1], order="rcm")
