@@ -173,7 +173,7 @@ sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_
  * sped_laplacian_csr; old_of_new (DEVICE int32 [n] or NULL) receives the
  * original id of each row of the result, so a block V given in original ids
  * enters as V[old_of_new] and results return by the inverse scatter.  The
- * workspace holds both builds' needs plus 2m + 3n int32.
+ * workspace holds the larger of the build's and the order's needs plus 2m + 3n int32.
  */
 sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                        const float *w, int32_t kind, int32_t lcc_only, int32_t method,

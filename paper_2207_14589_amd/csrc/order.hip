@@ -242,24 +242,19 @@ __global__ void scatter_kept(int64_t n1, const int32_t *__restrict__ old_of_new1
   if (i < n1) map[old_of_new1[i]] = pos[i];
 }
 
-__global__ void dropped_flags(int64_t n, const int32_t *__restrict__ map, int64_t *__restrict__ flags) {
-  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (i < n) flags[i] = map[i] < 0;
-}
-
-__global__ void place_dropped(int64_t n, int64_t n1, const int64_t *__restrict__ rank, int32_t *__restrict__ map) {
-  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (i < n && map[i] < 0) map[i] = int32_t(n1 + rank[i]);
-}
-
-// endpoints outside [0, n) are left as they are, for the build to reject
+// Kept edges take their endpoints' positions; an edge of a dropped component
+// becomes the self-loop (0, 0), which the build ignores; endpoints outside
+// [0, n) are left as they are, for the build to reject.
 __global__ void relabel(int64_t m, int64_t n, const int32_t *__restrict__ src, const int32_t *__restrict__ dst,
                         const int32_t *__restrict__ map, int32_t *__restrict__ src2, int32_t *__restrict__ dst2) {
   const int64_t e = int64_t(blockIdx.x) * kOB + threadIdx.x;
   if (e >= m) return;
   const int32_t a = src[e], b = dst[e];
-  src2[e] = (a >= 0 && a < n) ? map[a] : a;
-  dst2[e] = (b >= 0 && b < n) ? map[b] : b;
+  int32_t a2 = (a >= 0 && a < n) ? map[a] : a;
+  int32_t b2 = (b >= 0 && b < n) ? map[b] : b;
+  if ((a >= 0 && a < n && a2 < 0) || (b >= 0 && b < n && b2 < 0)) a2 = b2 = 0;
+  src2[e] = a2;
+  dst2[e] = b2;
 }
 
 __global__ void compose_old(int64_t n1, const int32_t *__restrict__ old_of_new1, const int32_t *__restrict__ pos,
@@ -312,9 +307,7 @@ extern "C" sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const in
   const size_t a_bytes = std::max(build_ws_bytes(n, m, src, dst, kind), [&] {
     Carver t(nullptr);
     carve_order(t, n);
-    size_t scan = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (int64_t *)nullptr, (int64_t *)nullptr, n > 0 ? n : 1);
-    return std::max(t.bytes(), ((scan + 255) & ~size_t(255)) + 2 * (size_t(n + 1) * 8 + 256));
+    return t.bytes();
   }());
   Carver c(ws);
   char *regionA = c.take<char>(a_bytes);
@@ -330,35 +323,20 @@ extern "C" sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const in
   size_t ab = a_bytes;
   SPED_TRY(sped_laplacian_csr(n, m, src, dst, w, kind, lcc_only, out, oon1, regionA, &ab, stream));
   const int64_t n1 = out->n;
-  if (n1 == 0) {
-    return SPED_OK;
-  }
+  if (n1 == 0) return SPED_OK;
   ab = a_bytes;
   SPED_TRY(sped_locality_order(out, method, pos, regionA, &ab, stream));
-  SPED_CHECK_HIP(hipMemsetAsync(map, 0xFF, sizeof(int32_t) * n, s));  // -1
+  SPED_CHECK_HIP(hipMemsetAsync(map, 0xFF, sizeof(int32_t) * n, s));  // -1: not kept
   hipLaunchKernelGGL(scatter_kept, dim3(oblocks(n1)), dim3(kOB), 0, s, n1, oon1, pos, map);
   SPED_CHECK_HIP(hipGetLastError());
-  if (n1 < n) {  // nodes outside the kept component: after it, in increasing id
-    Carver t(regionA);
-    int64_t *flags = t.take<int64_t>(n + 1);
-    int64_t *rank = t.take<int64_t>(n + 1);
-    void *temp = t.take<char>(0);
-    size_t tb = a_bytes - (static_cast<char *>(temp) - regionA);
-    hipLaunchKernelGGL(dropped_flags, dim3(oblocks(n)), dim3(kOB), 0, s, n, map, flags);
-    SPED_CHECK_HIP(hipGetLastError());
-    SPED_CHECK_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, flags, rank, n, s));
-    hipLaunchKernelGGL(place_dropped, dim3(oblocks(n)), dim3(kOB), 0, s, n, n1, rank, map);
-    SPED_CHECK_HIP(hipGetLastError());
-  }
   if (m > 0) {
     hipLaunchKernelGGL(relabel, dim3(oblocks(m)), dim3(kOB), 0, s, m, n, src, dst, map, src2, dst2);
     SPED_CHECK_HIP(hipGetLastError());
   }
-  // The kept component now holds ids 0 .. n1-1 and node 0, so the largest-
-  // component rule keeps it again and its increasing-id relabelling is the
-  // identity: the rows come out in the computed order.
+  // The kept nodes now carry ids 0 .. n1-1 in the computed order and every
+  // other edge is a self-loop: the second build takes all n1 nodes as they are.
   ab = a_bytes;
-  SPED_TRY(sped_laplacian_csr(n, m, src2, dst2, w, kind, lcc_only, out, nullptr, regionA, &ab, stream));
+  SPED_TRY(sped_laplacian_csr(n1, m, src2, dst2, w, kind, 0, out, nullptr, regionA, &ab, stream));
   if (out->n != n1) return fail(SPED_E_INVALID, "reordered build kept a different node count");
   if (old_of_new) {
     hipLaunchKernelGGL(compose_old, dim3(oblocks(n1)), dim3(kOB), 0, s, n1, oon1, pos, old_of_new);

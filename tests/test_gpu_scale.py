@@ -232,3 +232,27 @@ def test_rmat_scale20_walks_on_hub_rows(sped):
     Yl = sped.apply_limit_lazy(L, 16, Xd, 8, seed=3).cpu().numpy()
     Ylo = olazy.estimate_lazy(ref, 16, X.astype(np.float64), 8, seed=3, rows=rows)
     assert np.abs(Yl[rows] - Ylo).max() <= 2e-6 * np.abs(Ylo).max()
+
+
+def test_rmat_scale18_locality_orders(sped):
+    """Both node orders on an R-MAT scale-18 largest component (hubs of
+    thousands of neighbours, ~10 search levels) equal the oracle's exactly;
+    the ordered build numbers its rows in that order."""
+    from oracle import order as oorder
+    _say("R-MAT scale 18, largest component: Cuthill-McKee and degree orders, ordered build")
+    n, src, dst = synth.rmat_device(18, 16, 0.57, 0.19, 0.19, seed=5)
+    src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
+    L = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False)
+    ref = olap.laplacian(n, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
+    rowptr, col, _ = ref.adjacency()
+    assert L.n == ref.n
+    _say(f"  n_lcc={L.n} nnz={L.nnz} max_degree={L.max_degree}")
+    for method, want in (("cuthill_mckee", oorder.cuthill_mckee(ref.n, rowptr, col)),
+                         ("degree", oorder.degree_order(ref.n, rowptr))):
+        got = sped.locality_order(L, method).cpu().numpy()
+        np.testing.assert_array_equal(got, want)
+        Lo = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False, order=method)
+        placed = np.argsort(want)  # the node at each position
+        np.testing.assert_array_equal(Lo.old_of_new.cpu().numpy(), ref.old_of_new[placed])
+        np.testing.assert_array_equal(np.diff(Lo.rowptr[: Lo.n + 1].cpu().numpy()), np.diff(rowptr)[placed])
+        del Lo
