@@ -78,7 +78,9 @@ __global__ __launch_bounds__(kOB) void expand_level(int64_t lo, int64_t cnt, con
   const int64_t end = rowptr[v + 1];
   for (int64_t e = rowptr[v] + lane; e < end; e += 64) {
     const int32_t u = col[e];
-    if (pos[u] < 0) {
+    // a key already at or below q needs no atomic (the node is claimed; a
+    // stale read only costs an atomic that changes nothing)
+    if (pos[u] < 0 && __hip_atomic_load(&pkey[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > q) {
       const int32_t old = atomicMin(&pkey[u], q);
       if (old == INT_MAX) cand[atomicAdd(ncand, 1)] = u;
     }
@@ -287,7 +289,7 @@ extern "C" sped_status sped_locality_order(const sped_csr *L, int32_t method, in
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
-  if (L->n > 0 && (!L->rowptr || !L->col || !new_of_old)) return fail(SPED_E_INVALID, "NULL array");
+  if (L->n > 0 && (!L->rowptr || !new_of_old || (L->nnz > 0 && !L->col))) return fail(SPED_E_INVALID, "NULL array");
   return run_order(L, method, new_of_old, o, as_stream(stream));
 }
 
