@@ -440,13 +440,14 @@ def test_stochastic_unbiased(sped):
 
 @pytest.mark.parametrize("dt", ["f32", "bf16"])
 @pytest.mark.parametrize("ka,kb", [(20, 36), (56, 56), (61, 128), (100, 7), (128, 128), (32, 32), (18, 30),
-                                   (31, 32), (14, 24)])
+                                   (31, 32), (14, 24), (72, 72), (65, 80), (40, 48)])
 def test_gram_parity(sped, dt, ka, kb):
     """G = A^T B against float64 numpy on the same (rounded) operands: narrow
     (both widths <= 32; column pairs when both are even and above 16, else one
-    column per lane), wide with 4 or 8 wavefronts per block, odd widths and a
-    ragged row count; the symmetric form is exactly symmetric and the
-    reduction order is fixed."""
+    column per lane), wide with 4 or 8 wavefronts per block, symmetric Grams
+    of 33-80 columns on the narrow kernel (3, 4 and 5 tiles a side), odd
+    widths and a ragged row count; the symmetric form is exactly symmetric
+    and the reduction order is fixed."""
     _say(f"gram {dt} {ka}x{kb}")
     g = np.random.default_rng(ka * 1000 + kb)
     n = 100_003
