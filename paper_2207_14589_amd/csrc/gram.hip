@@ -45,8 +45,13 @@ __device__ inline void load2_as_double<bf16_t>(const bf16_t *p, double &x0, doub
 // Operand loaders of the Gram kernels: element (row, c) of the left and right
 // factors, converted to float64; a2/b2 give elements c and c + 1 (c even,
 // rows aligned to two elements).
+// kPairWaves: wavefronts per block of the column-pair Gram.  With 512 blocks
+// a plain loader is fastest at 4 (the fixed-order LDS merge is 4 steps), the
+// residual loader, whose two operand streams want more loads in flight, at 8
+// (1e6 x 32 float32: 53 us against 62 at 16 and 90 at 4).
 template <typename T1, typename T2>
 struct PlainLoad {
+  static constexpr int kPairWaves = 4;
   const T1 *A;
   int64_t lda;
   const T2 *B;
@@ -60,6 +65,7 @@ struct PlainLoad {
 // Residual block R = Z - Q diag(theta) formed on the fly (both factors are R).
 template <typename TQ>
 struct ResidLoad {
+  static constexpr int kPairWaves = 8;
   const float *Z;
   const TQ *Q;
   int64_t ld;
@@ -282,17 +288,15 @@ __global__ __launch_bounds__(kNarrowBlock) void gram_narrow_kernel(int64_t n, in
 // the transpose of (0, 1) and is not formed.  Otherwise as the one-column
 // form: unconditional loads, two alternating fragment buffers, the
 // wavefronts adding their tiles into LDS in wavefront order, one partial per
-// block.  Blocks of 4 wavefronts (kPairWaves): against 16, the symmetric
-// 1e6 x 32 float32 Gram went from 48.9 to 36.8 us and A^T B from 81.1 to
-// 51.9 us (the LDS merge is 4 steps instead of 16 and more blocks are
-// resident per CU).
-constexpr int kPairWaves = 4;
+// block.  Blocks of LD::kPairWaves wavefronts: with plain loads 4 against
+// 16 took the symmetric 1e6 x 32 float32 Gram from 48.9 to 36.8 us and A^T B
+// from 81.1 to 51.9 us.
 template <typename LD, bool SYM>
-__global__ __launch_bounds__(64 * kPairWaves) void gram_pair_kernel(int64_t n, int ka, int kb, LD ld,
-                                                                    int64_t rows_per_block,
-                                                                    double *__restrict__ partials) {
+__global__ __launch_bounds__(64 * LD::kPairWaves) void gram_pair_kernel(int64_t n, int ka, int kb, LD ld,
+                                                                        int64_t rows_per_block,
+                                                                        double *__restrict__ partials) {
   constexpr int KU = 4;
-  constexpr int NW = kPairWaves;
+  constexpr int NW = LD::kPairWaves;
   constexpr int W = 32;
   __shared__ double red[W * W];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -623,10 +627,9 @@ struct GramPlan {
 };
 
 GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
-  (void)sym;
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
   GramPlan p;
-  p.narrow = TA <= 2 && TB <= 2;
+  p.narrow = (TA <= 2 && TB <= 2) || (sym && TA <= 5 && TB <= 5);
   const int64_t unit = p.narrow ? 1024 : 128;  // rows per block at least
   const int64_t align = p.narrow ? 256 : 64;
   const int64_t cap = p.narrow ? kGramBlocks : kWideBlocks;
@@ -660,10 +663,10 @@ template <typename LD, bool SYM>
 sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *partials, const GramPlan &p,
                              hipStream_t s, bool pairs) {
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
-  // column pairs fill the four 16 x 16 tiles only when both widths exceed 16
-  if (p.narrow && pairs && ka % 2 == 0 && kb % 2 == 0 && ka > 16 && kb > 16) {
-    hipLaunchKernelGGL((gram_pair_kernel<LD, SYM>), dim3(p.nblocks), dim3(64 * kPairWaves), 0, s, n, ka, kb, ld,
-                       p.rows_per_block, partials);
+  // column pairs fill the four 16 x 16 tiles only when both widths are in (16, 32]
+  if (p.narrow && pairs && TA == 2 && TB == 2 && ka % 2 == 0 && kb % 2 == 0 && ka > 16 && kb > 16) {
+    hipLaunchKernelGGL((gram_pair_kernel<LD, SYM>), dim3(p.nblocks), dim3(64 * LD::kPairWaves), 0, s, n, ka, kb,
+                       ld, p.rows_per_block, partials);
     SPED_CHECK_HIP(hipGetLastError());
     return SPED_OK;
   }
@@ -671,17 +674,20 @@ sped_status launch_gram_maxt(int64_t n, int ka, int kb, const LD &ld, double *pa
     if (TA == 1 && TB == 1) return launch_gram_narrow_t<LD, 1, 1, SYM>(n, ka, kb, ld, partials, p, s);
     if (TA == 1 && TB == 2) return launch_gram_narrow_t<LD, 1, 2, SYM>(n, ka, kb, ld, partials, p, s);
     if (TA == 2 && TB == 1) return launch_gram_narrow_t<LD, 2, 1, SYM>(n, ka, kb, ld, partials, p, s);
-    return launch_gram_narrow_t<LD, 2, 2, SYM>(n, ka, kb, ld, partials, p, s);
+    if (TA == 2 && TB == 2) return launch_gram_narrow_t<LD, 2, 2, SYM>(n, ka, kb, ld, partials, p, s);
+    // A symmetric Gram up to 80 columns (the plan's 512 blocks): each
+    // wavefront forms all of its rows' tiles, so no row is loaded twice.
+    // Against the wide kernel, whose wavefronts each reload whole rows: 1e6 x
+    // 56 float32 177.8 -> 101.5 us (residual Gram 234.6 -> 123.5 us), 1e6 x 72
+    // float32 268.3 -> 174.5 us (residual 377.9 -> 209.5 us), 4e6 x 64 bf16
+    // 598.5 -> 366.3 us.  For A^T B (two operands, twice the fragment
+    // registers, one wavefront per SIMD) the wide kernel stays ahead in
+    // float32, so the plan keeps those wide.
+    if (SYM && TA == 3) return launch_gram_narrow_t<LD, 3, 3, SYM>(n, ka, kb, ld, partials, p, s);
+    if (SYM && TA == 4) return launch_gram_narrow_t<LD, 4, 4, SYM>(n, ka, kb, ld, partials, p, s);
+    if (SYM && TA == 5) return launch_gram_narrow_t<LD, 5, 5, SYM>(n, ka, kb, ld, partials, p, s);
+    return fail(SPED_E_UNSUPPORTED, "gram: no narrow kernel for this width");
   }
-  // A symmetric Gram up to 80 columns: each wavefront forms all of its rows'
-  // tiles (the narrow kernel), so no row is loaded twice.  Against the wide
-  // kernel, whose wavefronts each reload whole rows: 500k x 56 float32 88.5 ->
-  // 69.2 us, 4e6 x 64 bf16 598.5 -> 366.3 us, 1e6 x 72 float32 267.2 -> 198.5 us,
-  // 4e6 x 72 bf16 1009 -> 648 us.  For A^T B (two operands, twice the fragment
-  // registers, one wavefront per SIMD) the wide kernel stays ahead in float32.
-  if (SYM && TA == 3) return launch_gram_narrow_t<LD, 3, 3, SYM>(n, ka, kb, ld, partials, p, s);
-  if (SYM && TA == 4) return launch_gram_narrow_t<LD, 4, 4, SYM>(n, ka, kb, ld, partials, p, s);
-  if (SYM && TA == 5) return launch_gram_narrow_t<LD, 5, 5, SYM>(n, ka, kb, ld, partials, p, s);
   // TBM = TB where instantiated: column tiles past TB would still be loaded
   // (clamped) by every lane, and the wide kernel is bound by its load
   // instructions
