@@ -143,3 +143,36 @@ def test_ordered_build_edge_cases(sped):
     # lcc of an edgeless graph keeps one node
     L = sped.Laplacian(5, [], [], lcc=True, order="cuthill_mckee")
     assert L.n == 1
+
+
+def test_solve_on_ordered_laplacian(sped):
+    """The bottom-10 span solved on a Cuthill-McKee-numbered Laplacian, mapped
+    back through old_of_new, is the dense-eigh span of the original graph
+    (SBM n=2000, 10 blocks, plus an isolated pair outside the largest
+    component), and k-means labels map back the same way."""
+    from oracle import kmeans as okm
+    from oracle import solver as osol
+    n, s, d, labels = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    s = np.concatenate([s, [n]])
+    d = np.concatenate([d, [n + 1]])
+    n_all = n + 2
+    _say("bottom-10 solve on the ordered Laplacian, mapped back")
+    L = sped.Laplacian(n_all, s, d, kind="sym", lcc=True, order="cuthill_mckee")
+    base = olap.laplacian(n_all, s, d, kind=olap.SYM_NORMALIZED, lcc=True)
+    assert L.n == base.n == n
+    lam, U, _ = osol.dense_bottom_k(base.dense(), 10)
+    oon = L.old_of_new.long().cpu().numpy()          # original id of each ordered row
+    pos = np.empty(base.n, np.int64)
+    pos[np.searchsorted(base.old_of_new, oon)] = np.arange(L.n)  # ordered row of each kept node
+    k, guard = 10, 4
+    V0 = synth.gaussian_block(n, k + guard, 2).astype(np.float32)
+    V0o = torch.from_numpy(V0[np.argsort(pos)]).cuda()
+    r = sped.bottomk(L, k, sped.transform("limit", 8), V0=V0o, guard=guard, tol=1e-6, max_iters=3000)
+    assert r.converged, r.stats
+    Vback = r.V.cpu().numpy().astype(np.float64)[pos]
+    ang = osol.max_principal_angle(U, Vback)
+    assert ang <= 1e-6, (ang, r.stats)
+    np.testing.assert_allclose(r.evals[1:], lam[1:], rtol=1e-6)
+    lab, _, _, _ = sped.cluster_embed(r.V, 10, seed=1)
+    lab_back = lab.cpu().numpy()[pos]
+    assert okm.adjusted_rand_index(lab_back, labels) > 0.99
