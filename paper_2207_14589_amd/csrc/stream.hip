@@ -28,6 +28,13 @@ constexpr int kBlock = 256;
 #define GRID_STRIDE(i, n) \
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < (n); i += int64_t(gridDim.x) * blockDim.x)
 
+// One lane group walks a run of kEdgeRun consecutive edges.  The update of
+// the source row is kept in registers while consecutive edges share their
+// source and added with atomics once per run of equal sources (an edge list
+// sorted by source, the usual layout, then pays about one source flush per
+// node instead of one per edge); the destination row gets its atomics per
+// edge.  Invalid edges are counted once each (first column tile, lane 0).
+constexpr int kEdgeRun = 8;
 template <typename TX, int VEC>
 __global__ __launch_bounds__(kBlock) void edge_apply_kernel(int64_t m, const int32_t *__restrict__ src,
                                                             const int32_t *__restrict__ dst,
@@ -37,45 +44,82 @@ __global__ __launch_bounds__(kBlock) void edge_apply_kernel(int64_t m, const int
                                                             float *__restrict__ Y, int64_t ldy, float alpha,
                                                             unsigned long long *__restrict__ invalid) {
   const int lig = threadIdx.x & (G - 1);
-  const int64_t e = int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG);
-  if (e >= m) return;
-  const int32_t i = src[e], j = dst[e];
-  const float wt = w ? w[e] : 1.f;
-  if (i < 0 || i >= n || j < 0 || j >= n || !(wt > 0.f) || !isfinite(wt)) {
-    if (lig == 0 && blockIdx.y == 0 && invalid) atomicAdd(invalid, 1ull);
-    return;
-  }
+  const int64_t e0 = (int64_t(blockIdx.x) * (kBlock >> lgG) + (threadIdx.x >> lgG)) * kEdgeRun;
+  if (e0 >= m) return;
   const int c0 = blockIdx.y * 64 * VEC + lig * VEC;
-  if (i == j || c0 >= k) return;
-  const float si = scale ? scale[i] : 1.f, sj = scale ? scale[j] : 1.f;
-  float xi[VEC], xj[VEC];
-  VecIO<TX, VEC>::load(X + int64_t(i) * ldx + c0, xi);
-  VecIO<TX, VEC>::load(X + int64_t(j) * ldx + c0, xj);
-  const float fi = alpha * wt * si, fj = -alpha * wt * sj;
+  const bool col_ok = c0 < k;
+  int32_t cur = -1;  // source row held in acc (uniform over the lane group)
+  float cur_s = 0.f, xc[VEC], acc[VEC];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) {
-    const float d = si * xi[v] - sj * xj[v];
-    unsafeAtomicAdd(Y + int64_t(i) * ldy + c0 + v, fi * d);
-    unsafeAtomicAdd(Y + int64_t(j) * ldy + c0 + v, fj * d);
+  for (int v = 0; v < VEC; ++v) acc[v] = xc[v] = 0.f;
+  auto flush = [&]() {
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      unsafeAtomicAdd(Y + int64_t(cur) * ldy + c0 + v, acc[v]);
+      acc[v] = 0.f;
+    }
+  };
+  for (int r = 0; r < kEdgeRun; ++r) {
+    const int64_t e = e0 + r;
+    if (e >= m) break;
+    const int32_t i = src[e], j = dst[e];
+    const float wt = w ? w[e] : 1.f;
+    if (i < 0 || i >= n || j < 0 || j >= n || !(wt > 0.f) || !isfinite(wt)) {
+      if (lig == 0 && blockIdx.y == 0 && invalid) atomicAdd(invalid, 1ull);
+      continue;
+    }
+    if (i == j || !col_ok) continue;
+    if (i != cur) {
+      if (cur >= 0) flush();
+      cur = i;
+      cur_s = scale ? scale[i] : 1.f;
+      VecIO<TX, VEC>::load(X + int64_t(i) * ldx + c0, xc);
+    }
+    const float sj = scale ? scale[j] : 1.f;
+    float xj[VEC];
+    VecIO<TX, VEC>::load(X + int64_t(j) * ldx + c0, xj);
+    const float fi = alpha * wt * cur_s, fj = -alpha * wt * sj;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const float d = cur_s * xc[v] - sj * xj[v];
+      acc[v] = fmaf(fi, d, acc[v]);
+      unsafeAtomicAdd(Y + int64_t(j) * ldy + c0 + v, fj * d);
+    }
   }
+  if (cur >= 0) flush();
 }
 
-// d_i += w for both endpoints of every non-loop edge (float64 atomics).
+// d_i += w for both endpoints of every non-loop edge (float64 atomics).  Each
+// thread walks a run of kEdgeRun consecutive edges and adds a source's
+// weights once per run of equal sources, as the product does.
 __global__ __launch_bounds__(kBlock) void edge_degree_kernel(int64_t m, const int32_t *__restrict__ src,
                                                              const int32_t *__restrict__ dst,
                                                              const float *__restrict__ w, int64_t n,
                                                              double *__restrict__ degree,
                                                              unsigned long long *__restrict__ invalid) {
-  GRID_STRIDE(e, m) {
-    const int32_t i = src[e], j = dst[e];
-    const float wt = w ? w[e] : 1.f;
-    if (i < 0 || i >= n || j < 0 || j >= n || !(wt > 0.f) || !isfinite(wt)) {
-      atomicAdd(invalid, 1ull);
-      continue;
+  const int64_t runs = (m + kEdgeRun - 1) / kEdgeRun;
+  GRID_STRIDE(run, runs) {
+    int32_t cur = -1;
+    double acc = 0.0;
+    for (int r = 0; r < kEdgeRun; ++r) {
+      const int64_t e = run * kEdgeRun + r;
+      if (e >= m) break;
+      const int32_t i = src[e], j = dst[e];
+      const float wt = w ? w[e] : 1.f;
+      if (i < 0 || i >= n || j < 0 || j >= n || !(wt > 0.f) || !isfinite(wt)) {
+        atomicAdd(invalid, 1ull);
+        continue;
+      }
+      if (i == j) continue;
+      if (i != cur) {
+        if (cur >= 0) unsafeAtomicAdd(degree + cur, acc);
+        cur = i;
+        acc = 0.0;
+      }
+      acc += double(wt);
+      unsafeAtomicAdd(degree + j, double(wt));
     }
-    if (i == j) continue;
-    unsafeAtomicAdd(degree + i, double(wt));
-    unsafeAtomicAdd(degree + j, double(wt));
+    if (cur >= 0) unsafeAtomicAdd(degree + cur, acc);
   }
 }
 
@@ -143,7 +187,7 @@ sped_status launch_edge_apply_t(const EdgeGeom &g, int64_t m, const int32_t *src
                                 const float *w, const float *scale, int64_t n, int64_t k, const void *X,
                                 int64_t ldx, float *Y, int64_t ldy, float alpha, unsigned long long *invalid,
                                 hipStream_t s) {
-  const int64_t per_block = kBlock >> g.lgG;
+  const int64_t per_block = (kBlock >> g.lgG) * kEdgeRun;
   const int64_t blocks = (m + per_block - 1) / per_block;
   if (blocks > 0x7fffffff) return fail(SPED_E_UNSUPPORTED, "edge batch too large for one launch");
   const dim3 grid(unsigned(blocks), unsigned(g.ytiles));
@@ -341,8 +385,9 @@ extern "C" sped_status sped_stream_node_scales(int64_t n, int64_t m, const int32
   const int64_t bsz = std::min(batch, std::max<int64_t>(m, 1));
   SPED_TRY(stream_batches(m, src_h, dst_h, w_h, bsz, w.src, w.dst, w.w, s,
                           [&](int64_t, const int32_t *bs, const int32_t *bd, const float *bw, int64_t cnt) {
-                            hipLaunchKernelGGL(edge_degree_kernel, dim3(grid_blocks(cnt)), dim3(kBlock), 0, s, cnt,
-                                               bs, bd, bw, n, degree, w.invalid);
+                            const unsigned blocks = grid_blocks((cnt + kEdgeRun - 1) / kEdgeRun);
+                            hipLaunchKernelGGL(edge_degree_kernel, dim3(blocks), dim3(kBlock), 0, s, cnt, bs, bd, bw,
+                                               n, degree, w.invalid);
                             SPED_CHECK_HIP(hipGetLastError());
                             return SPED_OK;
                           }));
