@@ -707,6 +707,80 @@ def rmat26_step(sped, synth, torch, np, reps=5):
     return out
 
 
+def rmat_oracle_leg(sped, synth, torch, np, scale=22, runs=3):
+    """The oracle on the R-MAT workload.  Scale 26 does not fit the float64
+    oracle, so its one sparse step L X (64 columns) is timed on the scale-22
+    largest component (same generator and parameters), on the host's cores
+    (column slices on threads, median of `runs`), beside the GPU's step on the
+    same graph; the scale-26 figure is extrapolated by the ratio of stored
+    entries (the step's work is proportional to nnz x k), with scale 26 built
+    on the GPU in the same run to read its nnz and time its step."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import laplacian as olap
+
+    k = 64
+    one = sped.monomial([0.0, 1.0])
+
+    def gpu_step(L):
+        X = synth.gaussian_block_device(L.n, k, seed=2, dtype=torch.float32)
+        Y = torch.empty_like(X)
+        sped.apply_poly(L, one, X, out=Y)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            sped.apply_poly(L, one, X, out=Y)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return X, float(np.median(ts))
+
+    n, src, dst = synth.rmat_device(scale, 16, 0.57, 0.19, 0.19, seed=1)
+    src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
+    L = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    X, g_ms = gpu_step(L)
+    Xh = X.cpu().numpy().astype(np.float64)
+    del X
+    ref = olap.laplacian(n, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
+    print(f"[rmat-oracle] scale {scale} built: oracle and GPU", file=sys.stderr, flush=True)
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), k))
+    slices = [np.ascontiguousarray(Xh[:, c]) for c in np.array_split(np.arange(k), workers)]
+    times = []
+    with ThreadPoolExecutor(workers) as ex:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            parts = list(ex.map(lambda V: ref.L @ V, slices))
+            np.concatenate(parts, axis=1)
+            times.append(time.perf_counter() - t0)
+            print(f"[rmat-oracle] oracle step {len(times)}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+    o_s = float(np.median(times))
+    out = {"workload": f"R-MAT scale {scale} and 26, edge factor 16 (0.57, 0.19, 0.19), device draw; largest "
+                       f"component; sym-normalised L; one sparse step L X, k={k}",
+           f"scale{scale}": {"n_lcc": L.n, "nnz": L.nnz, "oracle_step_s_median": round(o_s, 3),
+                             "oracle_step_s_each": [round(t, 3) for t in times], "oracle_cores": workers,
+                             "gpu_step_ms_f32": round(g_ms, 3), "gpu_over_oracle": round(o_s * 1e3 / g_ms, 1)},
+           "host": _host_info()}
+    del L, ref, Xh, slices
+    torch.cuda.empty_cache()
+    n26, src, dst = synth.rmat_device(26, 16, 0.57, 0.19, 0.19, seed=1)
+    L = sped.Laplacian(n26, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    torch.cuda.empty_cache()
+    X, g26 = gpu_step(L)
+    ratio = L.nnz / out[f"scale{scale}"]["nnz"]
+    out["scale26"] = {"n_lcc": L.n, "nnz": L.nnz, "gpu_step_ms_f32": round(g26, 3),
+                      "oracle_step_s_extrapolated": round(o_s * ratio, 1), "nnz_ratio": round(ratio, 2),
+                      "gpu_over_oracle_extrapolated": round(o_s * ratio * 1e3 / g26, 1),
+                      "basis": f"scale-{scale} oracle median x stored-entry ratio (work ~ nnz x k)"}
+    del X, L
+    torch.cuda.empty_cache()
+    return out
+
+
 def reorder_leg(sped, synth, torch, np, graph="powerlaw4m", reps=10):
     """Node orders for gather locality (sped_laplacian_csr_ordered), timed
     apart from the solve: the build with each order against the plain build,
@@ -1061,6 +1135,8 @@ def main():
                     help="summarise the two counter databases into the committed traffic file")
     ap.add_argument("--sstep-sweep", action="store_true",
                     help="time the chain as single steps and as two-step launches on LDS row blocks")
+    ap.add_argument("--rmat-oracle", action="store_true",
+                    help="time the oracle's sparse step on R-MAT scale 22 and extrapolate to scale 26")
     ap.add_argument("--reorder", choices=["powerlaw4m", "rmat26"],
                     help="build with each node order and time one fused step per block width on each")
     ap.add_argument("--locality-sweep", action="store_true",
@@ -1114,6 +1190,9 @@ def main():
         return
     if args.rmat26_step:
         print(json.dumps({"rmat26_step": rmat26_step(sped, synth, torch, np)}), flush=True)
+        return
+    if args.rmat_oracle:
+        print(json.dumps({"rmat_oracle": rmat_oracle_leg(sped, synth, torch, np)}), flush=True)
         return
     if args.reorder:
         print(json.dumps({"reorder": reorder_leg(sped, synth, torch, np, args.reorder)}), flush=True)
