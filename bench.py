@@ -707,6 +707,88 @@ def rmat26_step(sped, synth, torch, np, reps=5):
     return out
 
 
+def _oracle_threaded(apply, X, runs):
+    """Median seconds of `apply` over column slices of X on up to 16 host
+    threads (scipy's sparse products release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    k = X.shape[1]
+    workers = max(1, min(16, len(os.sched_getaffinity(0)), k))
+    slices = [np.ascontiguousarray(X[:, c]) for c in np.array_split(np.arange(k), workers)]
+    times = []
+    with ThreadPoolExecutor(workers) as ex:
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            np.concatenate(list(ex.map(apply, slices)), axis=1)
+            times.append(time.perf_counter() - t0)
+            print(f"[oracle] run {len(times)}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+    return float(np.median(times)), [round(t, 3) for t in times], workers
+
+
+def oracle_workloads_leg(sped, synth, torch, np, runs=3):
+    """The float64 oracle, unchanged, on the power-law and PolyApply
+    workloads, on the host's cores (column slices on threads, median of
+    `runs`), beside the GPU's time for the same operation:
+    power-law: Chung-Lu n = 4e6, largest component, the degree-16 limit
+      product (I - L/16)^16 V on 64 columns (GPU: bf16 in and out, float32
+      between factors, as the solver's bf16 phase);
+    SBM 500k: the degree-12 polynomial sum_i theta_i (L - I)^i X on 50
+      columns by explicit powers (GPU: PolyApply's forward, float32)."""
+    from oracle import laplacian as olap
+    from oracle import poly as opoly
+    from paper_2207_14589_amd.autograd import poly_apply
+
+    def gpu_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {"host": _host_info()}
+    n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
+    src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
+    del src, dst
+    X = synth.gaussian_block_device(L.n, 64, seed=2, dtype=torch.bfloat16)
+    Y = torch.empty_like(X)
+    p = sped.transform("limit", 16)
+    g = gpu_ms(lambda: sped.apply_poly(L, p, X, out=Y))
+    Xh = X.float().cpu().numpy().astype(np.float64)
+    n_lcc, nnz = L.n, L.nnz
+    del L, X, Y
+    torch.cuda.empty_cache()
+    ref = olap.laplacian(n0, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
+    print("[oracle] power-law Laplacian built", file=sys.stderr, flush=True)
+    med, each, workers = _oracle_threaded(lambda V: opoly.apply_limit_product(ref.L, 16, V), Xh, runs)
+    out["power_law_4m_limit16_k64"] = {"n_lcc": n_lcc, "nnz": nnz, "oracle_s_median": round(med, 3),
+                                       "oracle_s_each": each, "oracle_cores": workers,
+                                       "gpu_ms_bf16": round(g, 3), "gpu_over_oracle": round(med * 1e3 / g, 1)}
+    del ref, Xh
+    n, s, d, _ = synth.sbm_from_degrees(500_000, 50, 22.8, 1.2, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym", walk_records=False)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    theta = torch.randn(13, generator=gen, dtype=torch.float64) * 0.3
+    X = synth.gaussian_block_device(L.n, 50, seed=6)
+    g = gpu_ms(lambda: poly_apply(theta, X, L, 1.0, 1.0))
+    Xh = X.cpu().numpy().astype(np.float64)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    pol = opoly.Poly(theta.numpy(), 1.0, 1.0)
+    med, each, workers = _oracle_threaded(lambda V: opoly.apply_terms(ref.L, pol, V), Xh, runs)
+    out["sbm500k_degree12_k50"] = {"n": L.n, "nnz": L.nnz, "oracle_s_median": round(med, 3), "oracle_s_each": each,
+                                   "oracle_cores": workers, "gpu_ms_f32": round(g, 3),
+                                   "gpu_over_oracle": round(med * 1e3 / g, 1)}
+    del L, X
+    torch.cuda.empty_cache()
+    return out
+
+
 def rmat_oracle_leg(sped, synth, torch, np, scale=22, runs=3):
     """The oracle on the R-MAT workload.  Scale 26 does not fit the float64
     oracle, so its one sparse step L X (64 columns) is timed on the scale-22
@@ -1135,6 +1217,8 @@ def main():
                     help="summarise the two counter databases into the committed traffic file")
     ap.add_argument("--sstep-sweep", action="store_true",
                     help="time the chain as single steps and as two-step launches on LDS row blocks")
+    ap.add_argument("--oracle-workloads", action="store_true",
+                    help="time the oracle on the power-law and PolyApply workloads beside the GPU")
     ap.add_argument("--rmat-oracle", action="store_true",
                     help="time the oracle's sparse step on R-MAT scale 22 and extrapolate to scale 26")
     ap.add_argument("--reorder", choices=["powerlaw4m", "rmat26"],
@@ -1190,6 +1274,9 @@ def main():
         return
     if args.rmat26_step:
         print(json.dumps({"rmat26_step": rmat26_step(sped, synth, torch, np)}), flush=True)
+        return
+    if args.oracle_workloads:
+        print(json.dumps({"oracle_workloads": oracle_workloads_leg(sped, synth, torch, np)}), flush=True)
         return
     if args.rmat_oracle:
         print(json.dumps({"rmat_oracle": rmat_oracle_leg(sped, synth, torch, np)}), flush=True)
