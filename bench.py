@@ -752,6 +752,21 @@ def oracle_workloads_leg(sped, synth, torch, np, runs=3):
         return a.elapsed_time(b) / reps
 
     out = {"host": _host_info()}
+    # the 2,000-node SBM: the oracle's plain and SPED (limit, l = 8) subspace
+    # iterations to the 1e-6 bound, one thread, against dense eigh
+    from oracle import solver as osol
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    _, U, _ = osol.dense_bottom_k(ref.dense(), 10)
+    V0 = synth.gaussian_block(n, 14, 2).astype(np.float32).astype(np.float64)
+    c1 = {"workload": "SBM n=2000, 10 blocks, p_in=0.05, p_out=0.0005, k=10 (+4 guard), tol 1e-6, float64, 1 thread"}
+    for name, app in (("plain", lambda V: ref.lambda_bound * V - ref.L @ V),
+                      ("sped_limit8", lambda V: opoly.apply_limit_product(ref.L, 8, V))):
+        t0 = time.perf_counter()
+        r = osol.subspace_iteration(ref.L, app, 10, V0, max_iters=5000, tol=1e-6, guard=4)
+        c1[name] = {"seconds": round(time.perf_counter() - t0, 3), "iters": r.iters, "converged": r.converged,
+                    "angle_vs_eigh": osol.max_principal_angle(U, r.Q)}
+    out["sbm2000_solve"] = c1
     n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
     src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
     L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
