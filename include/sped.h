@@ -158,10 +158,13 @@ typedef enum { SPED_ORDER_CUTHILL_MCKEE = 0, SPED_ORDER_DEGREE = 1 } sped_order;
 /*
  * sped_locality_order -- the position of each node of L in the order `method`.
  *  L           built by sped_laplacian_csr (its rowptr and col are read; the
- *              off-diagonal pattern must be symmetric)
+ *              off-diagonal pattern must be symmetric, with columns in [0, n))
  *  new_of_old  DEVICE int32 [L->n], written: a permutation of 0 .. n-1
- * One host synchronisation per search level.  The result is deterministic
- * (independent of the order in which the device's atomics land).
+ * Synchronises `stream` (once per search level, and before returning).  The
+ * result is deterministic (independent of the order in which the device's
+ * atomics land).  An unknown method or a NULL array returns SPED_E_INVALID
+ * before any launch; a search that reaches more nodes than L has (an
+ * adjacency that is not a valid CSR) returns SPED_E_INVALID.
  */
 sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_of_old, void *ws,
                                 size_t *ws_bytes, sped_stream_t stream);
@@ -169,11 +172,14 @@ sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_
 /*
  * sped_laplacian_csr_ordered -- sped_laplacian_csr, with the kept nodes
  * numbered in the order `method` computed on the built Laplacian: the graph
- * is built, ordered, relabelled and built again.  Arguments as for
- * sped_laplacian_csr; old_of_new (DEVICE int32 [n] or NULL) receives the
- * original id of each row of the result, so a block V given in original ids
- * enters as V[old_of_new] and results return by the inverse scatter.  The
- * workspace holds the larger of the build's and the order's needs plus 2m + 3n int32.
+ * is built, ordered, relabelled and built again (the second build takes the
+ * kept nodes only; edges of dropped components become ignored self-loops).
+ * Arguments, output buffers and errors as for sped_laplacian_csr, plus
+ * SPED_E_INVALID for an unknown method; old_of_new (DEVICE int32 [n] or
+ * NULL) receives the original id of each row of the result, so a block V
+ * given in original ids enters as V[old_of_new] and results return by the
+ * inverse scatter.  The workspace holds the larger of the build's and the
+ * order's needs plus 2m + 3n int32.  Synchronises `stream` before returning.
  */
 sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
                                        const float *w, int32_t kind, int32_t lcc_only, int32_t method,
