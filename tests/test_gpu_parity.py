@@ -1097,6 +1097,50 @@ def test_stream_laplacian_apply_parity(sped, kind, k, dt, batch):
     assert err < 1e-5, err
 
 
+@pytest.mark.parametrize("k", [32, 8, 72])
+def test_edge_apply_source_runs(sped, k):
+    """The edge-batch product walks runs of consecutive edges and adds a
+    source row once per run of equal sources: a source-sorted batch whose
+    sources repeat 1 to 40 times (runs crossing the walkers' boundaries),
+    with repeated pairs, self-loops and invalid edges (out-of-range endpoint,
+    zero weight) inside runs, against the float64 oracle over the valid
+    edges; every invalid edge counted once."""
+    from oracle import stream as ost
+    g = np.random.default_rng(k)
+    n = 3000
+    reps = g.integers(1, 41, 400)
+    src = np.repeat(g.choice(n, 400, replace=False), reps)
+    src.sort(kind="stable")
+    dst = g.integers(0, n, src.shape[0])
+    dst[::17] = src[::17]                      # self-loops
+    dst[5::23] = dst[4::23][: dst[5::23].shape[0]]
+    src[5::23] = src[4::23][: src[5::23].shape[0]]  # repeated pairs
+    w = g.uniform(0.1, 1.0, src.shape[0]).astype(np.float32)
+    bad_end = np.arange(3, src.shape[0], 41)
+    bad_w = np.arange(7, src.shape[0], 53)
+    bad_w = np.setdiff1d(bad_w, bad_end)
+    dst_bad = dst.copy()
+    dst_bad[bad_end] = n + 5
+    w_bad = w.copy()
+    w_bad[bad_w] = 0.0
+    _say(f"edge apply source runs k={k} m={src.shape[0]}")
+    scale = (1.0 / np.sqrt(g.uniform(1.0, 30.0, n))).astype(np.float32)
+    X = torch.from_numpy(synth.gaussian_block(n, k, 3).astype(np.float32)).cuda()
+    inv = torch.zeros(1, dtype=torch.int64, device="cuda")
+    Y = sped.edge_apply(n, torch.from_numpy(src.astype(np.int32)).cuda(),
+                        torch.from_numpy(dst_bad.astype(np.int32)).cuda(), X,
+                        w=torch.from_numpy(w_bad).cuda(), scale=torch.from_numpy(scale).cuda(), alpha=0.5,
+                        invalid=inv)
+    assert int(inv.item()) == bad_end.shape[0] + bad_w.shape[0]
+    ok = np.ones(src.shape[0], bool)
+    ok[bad_end] = False
+    ok[bad_w] = False
+    Yr = 0.5 * ost.edge_batch_apply(n, src[ok], dst[ok], w[ok].astype(np.float64), scale.astype(np.float64),
+                                    X.cpu().numpy().astype(np.float64))
+    err = np.abs(Y.cpu().numpy() - Yr).max() / np.abs(Yr).max()
+    assert err < 1e-5, err
+
+
 def test_stream_apply_matches_resident_laplacian(sped):
     """The streamed L X equals the resident CSR path's L X (the sparse step
     with the monomial p(L) = L) on the same graph."""
