@@ -150,8 +150,14 @@ def _ld(t):
     goes through here, so a host tensor is refused before any pointer is."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError("blocks must be CUDA tensors on the library's device")
-    if t.dim() != 2 or t.stride(1) != 1:
+    if t.dim() != 2:
         raise ValueError("blocks must be 2-D with unit column stride")
+    if t.shape[0] == 0:  # an empty block has no layout (torch may give it zero strides)
+        return max(int(t.shape[1]), 1)
+    if t.stride(1) != 1 and t.shape[1] > 1:
+        raise ValueError("blocks must be 2-D with unit column stride")
+    if t.shape[0] == 1:  # one row: its stride is not a layout either
+        return max(t.stride(0), int(t.shape[1]))
     return t.stride(0)
 
 

@@ -468,6 +468,25 @@ def test_gram_parity(sped, dt, ka, kb):
     np.testing.assert_array_equal(G, G2)   # fixed reduction order
 
 
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_gram_symmetric_width_sweep(sped, dt):
+    """Symmetric Grams at every width class the planner distinguishes
+    (1-32 narrow and column pairs, 33-80 on the narrow kernel with 3-5 tiles
+    a side, 81-128 wide) and row counts 0, 1, 17, 1000 and 100,003, against
+    float64 numpy; exactly symmetric."""
+    g = np.random.default_rng(11)
+    tdt = torch.float32 if dt == "f32" else torch.bfloat16
+    _say(f"gram symmetric width sweep {dt}")
+    for k in (1, 15, 16, 17, 31, 32, 33, 47, 48, 49, 56, 64, 65, 72, 80, 81, 96, 128):
+        for n in (0, 1, 17, 1000, 100_003):
+            A = torch.from_numpy(g.standard_normal((n, k)).astype(np.float32)).to(tdt).cuda()
+            S = sped.gram(A).cpu().numpy()
+            An = A.float().cpu().numpy().astype(np.float64)
+            R = An.T @ An
+            assert np.abs(S - R).max() <= 1e-12 * max(np.abs(R).max(), 1.0) + 1e-300, (k, n)
+            np.testing.assert_array_equal(S, S.T)
+
+
 @pytest.mark.parametrize("ld,k,off", [(40, 30, 2), (40, 30, 1), (33, 30, 2)])
 def test_gram_strided_operands(sped, ld, k, off):
     """Operands that are column slices of wider blocks: an even leading
