@@ -128,6 +128,23 @@ def test_laplacian_edge_cases(sped):
         sped.Laplacian(4, [0, 1], [1, 2], w=[1.0, -1.0])
 
 
+def test_empty_graph_products(sped):
+    """A 0-node Laplacian and its 0-row blocks: the polynomial chain, the
+    walk estimate and the Gram return empty results without error; on the
+    7-node edgeless graph p(L) X = p(0) X for the combinatorial L."""
+    _say("products on an empty graph")
+    L = sped.Laplacian(0, [], [], kind="sym")
+    X = torch.zeros(0, 8, dtype=torch.float32, device="cuda")
+    assert sped.apply_poly(L, sped.transform("limit", 4), X).shape == (0, 8)
+    assert sped.apply_poly_stochastic(L, sped.transform("limit", 4).monomial(), X, walks=4, seed=1).shape == (0, 8)
+    assert sped.gram(X).shape == (8, 8) and float(sped.gram(X).abs().max()) == 0.0
+    L7 = sped.Laplacian(7, [], [], kind="combinatorial")
+    X7 = torch.from_numpy(synth.gaussian_block(7, 8, 1).astype(np.float32)).cuda()
+    p = sped.transform("taylor_exp", 5)
+    Y = sped.apply_poly(L7, p, X7).cpu().numpy()
+    np.testing.assert_allclose(Y, p.monomial()[0] * X7.cpu().numpy(), rtol=1e-6, atol=1e-6)
+
+
 def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
