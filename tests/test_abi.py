@@ -323,3 +323,21 @@ def test_locality_order_validation(lib):
     assert need.value >= 2 * 200 * 4 + 3 * 100 * 4
     with pytest.raises(ValueError):
         sped.Laplacian(3, [0], [1], order="rcm")
+
+
+def test_polynomial_degree_limit(lib):
+    """Degree 1024 is the largest the chain takes; 1025 is refused on the
+    host (size query and transform) before any launch."""
+    need = ctypes.c_size_t(0)
+    c = sped.CSR()
+    c.n, c.nnz, c.kind = 100, 400, sped.SYM_NORMALIZED
+    c.rowptr = c.diag = c.scale = c.col = c.val = 16
+    for deg, want in ((1024, sped.OK), (1025, sped.E_INVALID)):
+        p = sped.Poly()
+        p.kind, p.degree = sped.POLY_LIMIT, deg
+        assert lib.sped_apply_poly(ctypes.byref(c), ctypes.byref(p), 8, 256, 8, 0, 512, 8, 0, None,
+                                   ctypes.byref(need), None) == want
+        out = np.zeros(deg + 1)
+        sh, sc = ctypes.c_double(), ctypes.c_double()
+        assert lib.sped_transform_coeffs(sped.T_LIMIT, deg, 2.0, 0.0, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                         ctypes.byref(sh), ctypes.byref(sc)) == want

@@ -128,6 +128,21 @@ def test_laplacian_edge_cases(sped):
         sped.Laplacian(4, [0, 1], [1, 2], w=[1.0, -1.0])
 
 
+def test_limit_chain_at_the_largest_degree(sped):
+    """The limit product at the largest degree the chain takes (l = 1024):
+    every factor I - L/1024 has its spectrum in [1 - 2/1024, 1], so float32
+    rounding adds up over the 1024 steps to about 1024 u; checked against
+    the oracle's float64 product at 3e-4 relative."""
+    _say("limit chain, degree 1024")
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    L = sped.Laplacian(n, s, d, kind="sym")
+    ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
+    X = synth.gaussian_block(n, 8, 4).astype(np.float32)
+    Y = sped.apply_poly(L, sped.transform("limit", 1024), torch.from_numpy(X).cuda()).cpu().numpy()
+    Yr = opoly.apply_limit_product(ref.L, 1024, X.astype(np.float64))
+    assert _rel(Y.astype(np.float64), Yr) < 3e-4
+
+
 def test_empty_graph_products(sped):
     """A 0-node Laplacian and its 0-row blocks: the polynomial chain, the
     walk estimate and the Gram return empty results without error; on the
