@@ -764,7 +764,7 @@ def rmat26_step(sped, synth, torch, np, reps=5):
     return out
 
 
-def _oracle_threaded(apply, X, runs):
+def _cpu_baseline_threaded(apply, X, runs):
     """Median seconds of `apply` over column slices of X on up to 16 host
     threads (scipy's sparse products release the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
@@ -784,9 +784,10 @@ def _oracle_threaded(apply, X, runs):
     return float(np.median(times)), [round(t, 3) for t in times], workers
 
 
-def oracle_workloads_leg(sped, synth, torch, np, runs=3):
-    """The float64 oracle, unchanged, on the power-law and PolyApply
-    workloads, on the host's cores (column slices on threads, median of
+def cpu_baseline_workloads_leg(sped, synth, torch, np, runs=3):
+    """cpu_baseline leg for the power-law and PolyApply workloads: the
+    float64 oracle, unchanged, timed as a reported baseline on the host's
+    cores (column slices on threads, median of
     `runs`), beside the GPU's time for the same operation:
     power-law: Chung-Lu n = 4e6, largest component, the degree-16 limit
       product (I - L/16)^16 V on 64 columns (GPU: bf16 in and out, float32
@@ -838,7 +839,7 @@ def oracle_workloads_leg(sped, synth, torch, np, runs=3):
     torch.cuda.empty_cache()
     ref = olap.laplacian(n0, src_h, dst_h, kind=olap.SYM_NORMALIZED, lcc=True)
     print("[oracle] power-law Laplacian built", file=sys.stderr, flush=True)
-    med, each, workers = _oracle_threaded(lambda V: opoly.apply_limit_product(ref.L, 16, V), Xh, runs)
+    med, each, workers = _cpu_baseline_threaded(lambda V: opoly.apply_limit_product(ref.L, 16, V), Xh, runs)
     out["power_law_4m_limit16_k64"] = {"n_lcc": n_lcc, "nnz": nnz, "oracle_s_median": round(med, 3),
                                        "oracle_s_each": each, "oracle_cores": workers,
                                        "gpu_ms_bf16": round(g, 3), "gpu_over_oracle": round(med * 1e3 / g, 1)}
@@ -852,7 +853,7 @@ def oracle_workloads_leg(sped, synth, torch, np, runs=3):
     Xh = X.cpu().numpy().astype(np.float64)
     ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
     pol = opoly.Poly(theta.numpy(), 1.0, 1.0)
-    med, each, workers = _oracle_threaded(lambda V: opoly.apply_terms(ref.L, pol, V), Xh, runs)
+    med, each, workers = _cpu_baseline_threaded(lambda V: opoly.apply_terms(ref.L, pol, V), Xh, runs)
     out["sbm500k_degree12_k50"] = {"n": L.n, "nnz": L.nnz, "oracle_s_median": round(med, 3), "oracle_s_each": each,
                                    "oracle_cores": workers, "gpu_ms_f32": round(g, 3),
                                    "gpu_over_oracle": round(med * 1e3 / g, 1)}
@@ -861,8 +862,9 @@ def oracle_workloads_leg(sped, synth, torch, np, runs=3):
     return out
 
 
-def rmat_oracle_leg(sped, synth, torch, np, scale=22, runs=3):
-    """The oracle on the R-MAT workload.  Scale 26 does not fit the float64
+def cpu_baseline_rmat_leg(sped, synth, torch, np, scale=22, runs=3):
+    """cpu_baseline leg for the R-MAT workload: the oracle, unchanged, timed
+    as a reported baseline.  Scale 26 does not fit the float64
     oracle, so its one sparse step L X (64 columns) is timed on the scale-22
     largest component (same generator and parameters), on the host's cores
     (column slices on threads, median of `runs`), beside the GPU's step on the
@@ -1289,10 +1291,10 @@ def main():
                     help="summarise the two counter databases into the committed traffic file")
     ap.add_argument("--sstep-sweep", action="store_true",
                     help="time the chain as single steps and as two-step launches on LDS row blocks")
-    ap.add_argument("--oracle-workloads", action="store_true",
-                    help="time the oracle on the power-law and PolyApply workloads beside the GPU")
-    ap.add_argument("--rmat-oracle", action="store_true",
-                    help="time the oracle's sparse step on R-MAT scale 22 and extrapolate to scale 26")
+    ap.add_argument("--cpu-baseline-workloads", action="store_true",
+                    help="cpu_baseline legs: time the oracle on the power-law and PolyApply workloads beside the GPU")
+    ap.add_argument("--cpu-baseline-rmat", action="store_true",
+                    help="cpu_baseline leg: time the oracle's sparse step on R-MAT scale 22, extrapolated to scale 26")
     ap.add_argument("--reorder", choices=["powerlaw4m", "rmat26"],
                     help="build with each node order and time one fused step per block width on each")
     ap.add_argument("--locality-sweep", action="store_true",
@@ -1347,11 +1349,11 @@ def main():
     if args.rmat26_step:
         print(json.dumps({"rmat26_step": rmat26_step(sped, synth, torch, np)}), flush=True)
         return
-    if args.oracle_workloads:
-        print(json.dumps({"oracle_workloads": oracle_workloads_leg(sped, synth, torch, np)}), flush=True)
+    if args.cpu_baseline_workloads:
+        print(json.dumps({"cpu_baseline_workloads": cpu_baseline_workloads_leg(sped, synth, torch, np)}), flush=True)
         return
-    if args.rmat_oracle:
-        print(json.dumps({"rmat_oracle": rmat_oracle_leg(sped, synth, torch, np)}), flush=True)
+    if args.cpu_baseline_rmat:
+        print(json.dumps({"cpu_baseline_rmat": cpu_baseline_rmat_leg(sped, synth, torch, np)}), flush=True)
         return
     if args.reorder:
         print(json.dumps({"reorder": reorder_leg(sped, synth, torch, np, args.reorder)}), flush=True)
@@ -1438,6 +1440,9 @@ def main():
                      "alg_bytes_per_launch": per_launch, "avg_launch_us": round(launch_s * 1e6, 3)},
         "step_breakdown": parts,
         "pLV_per_s": round(1e3 / chain_ms, 2),
+        # one timed step is one solver iteration (exact product, walk estimate,
+        # CholQR2, Rayleigh-Ritz)
+        "solver_iters_per_s": None if args.chain_only else round(1e3 / ms_per_step, 2),
         "walk_steps_per_s": (round(L.n * walks * ell / (parts["walk_estimate_ms"] * 1e-3), 1)
                              if "walk_estimate_ms" in parts else None),
         "setup": {"graph_gen_s": round(gen_s, 3), "laplacian_build_s": round(build_s, 3)},
