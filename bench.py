@@ -1445,6 +1445,10 @@ def main():
         "solver_iters_per_s": None if args.chain_only else round(1e3 / ms_per_step, 2),
         "walk_steps_per_s": (round(L.n * walks * ell / (parts["walk_estimate_ms"] * 1e-3), 1)
                              if "walk_estimate_ms" in parts else None),
+        # bytes a walk-step touches: one 32-byte entry record and one X row
+        # (each node's row is gathered once, when the walk leaves it)
+        "walk_touched_GBps": (round(L.n * walks * ell * (32 + 4 * k) / (parts["walk_estimate_ms"] * 1e-3) / 1e9, 1)
+                              if "walk_estimate_ms" in parts else None),
         "setup": {"graph_gen_s": round(gen_s, 3), "laplacian_build_s": round(build_s, 3)},
     }
     if not args.chain_only:
