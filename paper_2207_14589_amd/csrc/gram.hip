@@ -630,7 +630,10 @@ GramPlan gram_plan(int64_t n, int ka, int kb, bool sym) {
   const int TA = (ka + 15) / 16, TB = (kb + 15) / 16;
   GramPlan p;
   p.narrow = (TA <= 2 && TB <= 2) || (sym && TA <= 5 && TB <= 5);
-  const int64_t unit = p.narrow ? 1024 : 128;  // rows per block at least
+  // rows per block at least: one 64-row pass per wavefront keeps small
+  // Grams from walking many chunks in sequence on a few blocks (2,000 x 14:
+  // residual Gram 19.9 -> 7.7 us, symmetric 7.7 -> 4.3 us against 1024 rows)
+  const int64_t unit = p.narrow ? 256 : 128;
   const int64_t align = p.narrow ? 256 : 64;
   const int64_t cap = p.narrow ? kGramBlocks : kWideBlocks;
   int64_t nb = (n + unit - 1) / unit;

@@ -12,6 +12,7 @@
 // The host loop only reads 2(k + guard) doubles and 3 flags per check.
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -334,12 +335,17 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   RRWs rw;
   rw.H = c.take<double>(size_t(kb) * kb);
   rw.S = c.take<double>(size_t(kb) * kb);
-  rw.theta = c.take<double>(size_t(kb));
-  rw.resid = c.take<double>(size_t(kb));
   rw.G = c.take<double>(size_t(kb) * kb);
-  rw.norm2 = c.take<double>(1);
+  // what a check reads on the host (Ritz values, residual norms, the norm
+  // bound, the flags) sits in one block: one copy per check instead of four
+  // (each small copy into pageable memory waits on its own)
+  const size_t nchk = size_t(2) * kb + 3;
+  double *chk = c.take<double>(nchk);
+  rw.theta = chk;
+  rw.resid = chk ? chk + kb : nullptr;
+  rw.norm2 = chk ? chk + 2 * kb : nullptr;
   rw.partials = ow.partials;
-  int *flags = c.take<int>(4);
+  int *flags = chk ? reinterpret_cast<int *>(chk + 2 * kb + 1) : nullptr;  // 4 ints
   ow.flags = rw.flags = flags;
   double *jrel = c.take<double>(1);
   rw.jacobi_rel = jrel;
@@ -367,6 +373,15 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
   if (lazy) SPED_TRY(lazy_row_max(L, lz_max, s));  // graph-only, shared by every iteration
 
   std::vector<double> h_theta(kb), h_resid(kb);
+  // the checks' host copy lands in pinned host memory (a direct transfer,
+  // no staging through a pageable buffer); released on every return
+  struct PinnedChk {
+    double *p = nullptr;
+    ~PinnedChk() {
+      if (p) (void)hipHostFree(p);
+    }
+  } h_chk;
+  SPED_CHECK_HIP(hipHostMalloc(reinterpret_cast<void **>(&h_chk.p), sizeof(double) * nchk, hipHostMallocDefault));
   double h_norm2 = 0.0;
   int h_flags[4] = {0, 0, 0, 0};
   int t = 0;
@@ -506,11 +521,12 @@ extern "C" sped_status sped_bottomk_solve(const sped_csr *L, const sped_poly *p,
       else SPED_TRY(enqueue(dt, Q, W, check, stoch, s));
       if (check) {
         if (!mueg) std::swap(Q, W);  // Ritz vectors now in Q
-        SPED_CHECK_HIP(hipMemcpyAsync(h_theta.data(), rw.theta, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-        SPED_CHECK_HIP(hipMemcpyAsync(h_resid.data(), rw.resid, sizeof(double) * kb, hipMemcpyDeviceToHost, s));
-        SPED_CHECK_HIP(hipMemcpyAsync(&h_norm2, rw.norm2, sizeof(double), hipMemcpyDeviceToHost, s));
-        SPED_CHECK_HIP(hipMemcpyAsync(h_flags, flags, sizeof(h_flags), hipMemcpyDeviceToHost, s));
+        SPED_CHECK_HIP(hipMemcpyAsync(h_chk.p, chk, sizeof(double) * nchk, hipMemcpyDeviceToHost, s));
         SPED_CHECK_HIP(hipStreamSynchronize(s));
+        std::copy(h_chk.p, h_chk.p + kb, h_theta.begin());
+        std::copy(h_chk.p + kb, h_chk.p + 2 * kb, h_resid.begin());
+        h_norm2 = h_chk.p[2 * kb];
+        std::memcpy(h_flags, h_chk.p + 2 * kb + 1, sizeof(h_flags));
         if (h_flags[1]) return fail(SPED_E_NUMERIC, "Cholesky QR broke down after shifting");
         double rmax = 0.0;
         bool finite = std::isfinite(h_norm2);

@@ -540,12 +540,13 @@ def test_gram_strided_operands(sped, ld, k, off):
     np.testing.assert_array_equal(S, S.T)
 
 
-@pytest.mark.parametrize("k", [14, 56, 57, 70, 72, 90, 96])
+@pytest.mark.parametrize("k", [1, 2, 3, 8, 14, 15, 16, 17, 18, 56, 57, 70, 72, 90, 96])
 def test_orthonormalize_and_rr(sped, k):
     """CholQR2 (fused Cholesky and triangular inverse) and Rayleigh-Ritz
     (Jacobi eigensolver, odd widths padded) against the oracle's Householder
-    basis and dense Ritz pairs; widths 70 and 90 take the scalar-load product
-    with 5 and 6 column tiles, 72 and 96 the 4-wide one."""
+    basis and dense Ritz pairs; widths up to 16 take the one-wavefront
+    factorisations, 17 and up the 1024-thread ones; widths 70 and 90 take the
+    scalar-load product with 5 and 6 column tiles, 72 and 96 the 4-wide one."""
     _say(f"CholQR2 and Rayleigh-Ritz k={k}")
     n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
     L = sped.Laplacian(n, s, d, kind="sym")
