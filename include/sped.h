@@ -463,8 +463,10 @@ sped_status sped_rayleigh_ritz(const sped_csr *L, int64_t k, void *Q, int64_t ld
  *          of L on the span of its vectors)
  *  resid   HOST double [k] or NULL: final residual norms
  *  o, st   HOST options / statistics
- * Synchronous.  Returns SPED_E_NOT_CONVERGED (with outputs and stats filled)
- * when max_iters is reached first.  A start block that is rank deficient (a
+ * Synchronous: each check copies 2(k + guard) + 3 doubles (Ritz values,
+ * residual norms, norm bound, flags) into a small pinned host buffer that
+ * the call allocates and frees itself.  Returns SPED_E_NOT_CONVERGED (with
+ * outputs and stats filled) when max_iters is reached first.  A start block that is rank deficient (a
  * repeated or zero column) has those columns replaced by uniform random ones
  * (Philox keyed by seed) before the first iteration, counted in
  * st->reseeded; a start block that is not finite returns SPED_E_NUMERIC.
