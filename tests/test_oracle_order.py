@@ -1,7 +1,11 @@
 """Pins of the oracle's node orderings (oracle/order.py): a hand-worked
 Cuthill-McKee order, a declarative characterisation of the order checked on
 random graphs, breadth-first levels from scipy's own search, and the
-bandwidth bound every breadth-first order obeys."""
+bandwidth bound every breadth-first order obeys; for label propagation the
+published splitmix64 outputs, hand-worked oscillations (an edge, a star),
+cliques whose final label follows from two rounds of reasoning, the
+fixed-point condition counted independently, and the planted blocks of an
+SBM."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -172,3 +176,129 @@ def test_relabelled_laplacian_is_the_permuted_one():
     P = np.zeros((n, n))
     P[pos, np.arange(n)] = 1.0
     np.testing.assert_allclose(B, P @ A @ P.T, atol=1e-15)
+
+
+# ---------------------------------------------------------------- label propagation
+
+
+def test_mix64_is_splitmix64():
+    # splitmix64 started at state 0 adds the golden-ratio increment before
+    # each output; its published first outputs pin the constants and shifts
+    g = 0x9E3779B97F4A7C15
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    got = [oorder.mix64((g * i) & ((1 << 64) - 1)) for i in (1, 2, 3)]
+    assert got == want
+    assert oorder.mix64(0) == 0
+
+
+def _first_round_winner(ids):
+    """The member with the smallest round-0 tie-break key."""
+    return min(ids, key=lambda l: oorder.mix64(l ^ (1 << 32)))
+
+
+def test_label_propagation_single_edge_and_star_oscillate():
+    # K2: each end takes the other's label every round, so an even number of
+    # rounds gives the ids back and an odd number swaps them.
+    assert list(oorder.label_propagation(2, [0, 1, 2], [1, 0], rounds=16)) == [0, 1]
+    assert list(oorder.label_propagation(2, [0, 1, 2], [1, 0], rounds=15)) == [1, 0]
+    # Star, centre 0, leaves 1..5.  Round 0: the leaves see only label 0; the
+    # centre sees five labels once each and takes the round-0 winner a.
+    # Round 1: the centre sees 0 five times, the leaves see a.  From then on
+    # the two label sets swap every round, so after 16 rounds the centre is 0
+    # and the leaves are a.
+    src = np.zeros(5, np.int64)
+    dst = np.arange(1, 6)
+    rowptr, col = adjacency(6, src, dst)
+    a = _first_round_winner(range(1, 6))
+    assert list(oorder.label_propagation(6, rowptr, col)) == [0] + [a] * 5
+
+
+@pytest.mark.parametrize("sizes", [[4, 5, 6], [7, 4, 9, 5]])
+def test_label_propagation_cliques(sizes):
+    # In a clique of m >= 4 nodes, round 0 gives every member except the
+    # round-0 winner a (it cannot take its own label) the label a.  In round 1
+    # a member other than a sees a m - 2 >= 2 times and a's own label once,
+    # and a sees only a: every member ends with a, and the next round
+    # changes nothing.
+    src, dst, base = [], [], 0
+    for m in sizes:
+        for i in range(m):
+            for j in range(i + 1, m):
+                src.append(base + i)
+                dst.append(base + j)
+        base += m
+    n = base
+    rowptr, col = adjacency(n, np.array(src), np.array(dst))
+    lab, ran = oorder.label_propagation(n, rowptr, col, return_rounds=True)
+    base = 0
+    for m in sizes:
+        members = range(base, base + m)
+        assert set(lab[base:base + m]) == {_first_round_winner(members)}
+        base += m
+    assert ran == 3
+
+
+def test_label_propagation_fixed_point_and_planted_blocks():
+    """On the 10-block SBM the search stops before its cap; at that point
+    every node's label is one of the most frequent among its neighbours
+    (counted here with numpy, independently of the oracle's loops), and the
+    labels recover the planted blocks."""
+    n, s, d, blocks = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    rowptr, col = adjacency(n, s, d)
+    lab, ran = oorder.label_propagation(n, rowptr, col, return_rounds=True)
+    assert ran < oorder.LP_ROUNDS
+    rows = np.repeat(np.arange(n), np.diff(rowptr))
+    key = rows * n + lab[col]
+    uk, cnt = np.unique(key, return_counts=True)
+    top = np.zeros(n, np.int64)
+    np.maximum.at(top, uk // n, cnt)
+    mine = dict(zip(uk.tolist(), cnt.tolist()))
+    for v in range(n):
+        if rowptr[v + 1] > rowptr[v]:
+            assert mine.get(v * n + int(lab[v]), 0) == top[v]
+    # purity: each label's nodes lie in one planted block
+    for l in np.unique(lab):
+        assert len(np.unique(blocks[lab == l])) == 1
+    assert 10 <= len(np.unique(lab)) <= 14
+
+
+def test_label_order_properties():
+    n, s, d, _ = synth.sbm_bernoulli([60, 80, 50], 0.1, 0.005, seed=4)
+    n += 3  # isolated nodes keep their own labels
+    rowptr, col = adjacency(n, s, d)
+    lab = oorder.label_propagation(n, rowptr, col)
+    pos = oorder.label_order(n, rowptr, col)
+    assert sorted(pos.tolist()) == list(range(n))
+    order = np.argsort(pos)
+    keys = list(zip(lab[order].tolist(), order.tolist()))
+    assert keys == sorted(keys)  # grouped by label, ids increasing inside
+    assert all(lab[v] == v for v in range(n - 3, n))
+
+
+def test_label_propagation_empty_and_edgeless():
+    assert oorder.label_order(0, [0], []).shape == (0,)
+    np.testing.assert_array_equal(oorder.label_order(4, [0, 0, 0, 0, 0], []), np.arange(4))
+    np.testing.assert_array_equal(oorder.label_propagation(4, [0, 0, 0, 0, 0], []), np.arange(4))
+
+
+def test_label_propagation_pins_catch_plausible_mistakes(monkeypatch):
+    """Ties broken by the smallest label instead of the hash (every clique
+    would end at its smallest id) fail the clique pin above."""
+    sizes = [4, 5, 6]
+    src, dst, base = [], [], 0
+    for m in sizes:
+        for i in range(m):
+            for j in range(i + 1, m):
+                src.append(base + i)
+                dst.append(base + j)
+        base += m
+    rowptr, col = adjacency(base, np.array(src), np.array(dst))
+    want = []
+    base = 0
+    for m in sizes:
+        want += [_first_round_winner(range(base, base + m))] * m
+        base += m
+    assert list(oorder.label_propagation(base, rowptr, col)) == want
+    # smallest-label ties: every clique ends at its smallest id instead
+    monkeypatch.setattr(oorder, "mix64", lambda x: x & 0xFFFFFFFF)
+    assert list(oorder.label_propagation(base, rowptr, col)) != want
