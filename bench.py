@@ -955,7 +955,7 @@ def reorder_leg(sped, synth, torch, np, graph="powerlaw4m", reps=10):
                 "component")
     out = {"workload": desc + "; sym-normalised L; one fused step L X per width", "reps": reps}
     one = sped.monomial([0.0, 1.0])
-    for order in (None, "degree", "cuthill_mckee"):
+    for order in (None, "degree", "cuthill_mckee", "label_propagation"):
         # built twice: the first build's time includes mapping fresh device
         # memory for its workspace, the second reuses the allocator's blocks
         rec = {}
@@ -968,7 +968,7 @@ def reorder_leg(sped, synth, torch, np, graph="powerlaw4m", reps=10):
             rec[key] = round(time.perf_counter() - t0, 3)
         if order is None:
             out["n_lcc"], out["nnz"] = L.n, L.nnz
-            for method in ("degree", "cuthill_mckee"):
+            for method in ("degree", "cuthill_mckee", "label_propagation"):
                 sped.locality_order(L, method)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()

@@ -151,20 +151,33 @@ sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *src, const i
  *      each dequeued node by increasing (degree, id) (Cuthill and McKee,
  *      1969); nodes outside that node's component follow in increasing id.
  *  SPED_ORDER_DEGREE  decreasing degree, ties in increasing id.
+ *  SPED_ORDER_LABEL_PROPAGATION  nodes grouped by the communities found by
+ *      synchronous label propagation (Raghavan, Albert and Kumara, 2007):
+ *      labels start as the ids; each round, every node with neighbours takes
+ *      the label most frequent among its neighbours' labels of the previous
+ *      round (unweighted counts), ties going to the label with the smallest
+ *      splitmix64 output of (label XOR (round + 1) << 32), rounds from 0; at
+ *      most 16 rounds, stopping after one that changes no label.  Groups in
+ *      increasing label, ids increasing inside a group.
  * Degree = number of distinct neighbours (row length of L's off-diagonal part).
  */
-typedef enum { SPED_ORDER_CUTHILL_MCKEE = 0, SPED_ORDER_DEGREE = 1 } sped_order;
+typedef enum {
+  SPED_ORDER_CUTHILL_MCKEE = 0,
+  SPED_ORDER_DEGREE = 1,
+  SPED_ORDER_LABEL_PROPAGATION = 2
+} sped_order;
 
 /*
  * sped_locality_order -- the position of each node of L in the order `method`.
  *  L           built by sped_laplacian_csr (its rowptr and col are read; the
  *              off-diagonal pattern must be symmetric, with columns in [0, n))
  *  new_of_old  DEVICE int32 [L->n], written: a permutation of 0 .. n-1
- * Synchronises `stream` (once per search level, and before returning).  The
- * result is deterministic (independent of the order in which the device's
- * atomics land).  An unknown method or a NULL array returns SPED_E_INVALID
- * before any launch; a search that reaches more nodes than L has (an
- * adjacency that is not a valid CSR) returns SPED_E_INVALID.
+ * Synchronises `stream` (once per search level or propagation round, and
+ * before returning).  The result is deterministic (independent of the order
+ * in which the device's atomics land).  Label propagation's workspace holds
+ * two 8-byte keys per stored entry.  An unknown method or a NULL array
+ * returns SPED_E_INVALID before any launch; a search that reaches more nodes
+ * than L has (an adjacency that is not a valid CSR) returns SPED_E_INVALID.
  */
 sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_of_old, void *ws,
                                 size_t *ws_bytes, sped_stream_t stream);

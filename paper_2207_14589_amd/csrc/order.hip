@@ -16,6 +16,17 @@
 // radix sorts (by id, then by (key, degree)) fix the level's order.  The
 // result does not depend on the order of the atomics.  Nodes outside the
 // search's component follow in increasing id.
+//
+// Label propagation (Raghavan, Albert and Kumara 2007), synchronous: every
+// node starts with its id as label; a round gives every node with neighbours
+// the label most frequent among its stored neighbours' labels of the previous
+// round, ties going to the smallest splitmix64 output of (label XOR (round +
+// 1) << 32); at most kLpRounds rounds, stopping after a round that changes no
+// label.  A round sorts the (row, neighbour label) keys of all stored entries
+// (one radix sort; rows stay in their CSR ranges) and one thread per row
+// scans its sorted range for the longest run.  The order groups the nodes by
+// final label (increasing), ids increasing inside a group: one stable radix
+// sort of the labels with the ids as values.
 
 #include <hipcub/hipcub.hpp>
 
@@ -120,6 +131,68 @@ __global__ void degree_keys(int64_t n, const int64_t *__restrict__ rowptr, uint3
   ids[i] = int32_t(i);
 }
 
+constexpr int kLpRounds = 16;
+
+// The output function of splitmix64 (Steele, Lea and Flood, OOPSLA 2014).
+__device__ inline uint64_t mix64(uint64_t x) {
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+__global__ void iota_i32(int64_t n, int32_t *__restrict__ a) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i < n) a[i] = int32_t(i);
+}
+
+// (row << lbits) | label of the entry's neighbour, for every stored entry;
+// groups of 16 lanes per row, grid-stride over the rows
+constexpr int kLpGroup = 16;
+__global__ __launch_bounds__(kOB) void lp_keys(int64_t n, int lbits, const int64_t *__restrict__ rowptr,
+                                               const int32_t *__restrict__ col, const int32_t *__restrict__ lab,
+                                               uint64_t *__restrict__ keys) {
+  const int lig = threadIdx.x & (kLpGroup - 1);
+  const int64_t groups = int64_t(gridDim.x) * (kOB / kLpGroup);
+  for (int64_t r = int64_t(blockIdx.x) * (kOB / kLpGroup) + threadIdx.x / kLpGroup; r < n; r += groups) {
+    const int64_t end = rowptr[r + 1];
+    for (int64_t e = rowptr[r] + lig; e < end; e += kLpGroup)
+      keys[e] = (uint64_t(r) << lbits) | uint64_t(uint32_t(lab[col[e]]));
+  }
+}
+
+// One thread per row: the longest run of equal labels in the row's sorted
+// keys, ties by the smaller mix64(label ^ salt); rows without entries keep
+// their label.  *changed is set when any label moves.
+__global__ void lp_choose(int64_t n, int lbits, const int64_t *__restrict__ rowptr,
+                          const uint64_t *__restrict__ keys, const int32_t *__restrict__ lab,
+                          int32_t *__restrict__ nlab, uint64_t salt, int32_t *__restrict__ changed) {
+  const int64_t u = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (u >= n) return;
+  const uint64_t mask = (uint64_t(1) << lbits) - 1;
+  const int64_t b = rowptr[u], e = rowptr[u + 1];
+  int32_t best = lab[u];
+  if (e > b) {
+    int64_t best_cnt = 0;
+    uint64_t best_h = 0;
+    int64_t p = b;
+    while (p < e) {
+      const uint64_t l = keys[p] & mask;
+      int64_t q = p + 1;
+      while (q < e && (keys[q] & mask) == l) ++q;
+      const int64_t cnt = q - p;
+      const uint64_t h = mix64(l ^ salt);
+      if (cnt > best_cnt || (cnt == best_cnt && h < best_h)) {
+        best_cnt = cnt;
+        best_h = h;
+        best = int32_t(l);
+      }
+      p = q;
+    }
+  }
+  nlab[u] = best;
+  if (best != lab[u]) *changed = 1;
+}
+
 struct OrderWs {
   int32_t *pkey, *order, *cand, *candS, *ids2;
   uint64_t *k2, *k2s;
@@ -128,6 +201,10 @@ struct OrderWs {
   int32_t *ncand;
   int64_t *nsel;
   unsigned long long *best;
+  // label propagation only (NULL otherwise): entry keys and their sorted
+  // copy, the labels of two rounds
+  uint64_t *ek, *eks;
+  int32_t *lab, *nlab;
   void *temp;
   size_t temp_bytes;
 };
@@ -145,7 +222,21 @@ size_t order_temp_bytes(int64_t n) {
   return std::max(std::max(a, b), std::max(d, e));
 }
 
-OrderWs carve_order(Carver &c, int64_t n) {
+// keys of label propagation's entry sort: (row << lbits) | label
+inline int lp_label_bits(int64_t n) { return std::max(bits_for(uint64_t(n)), 1); }
+
+size_t lp_temp_bytes(int64_t n, int64_t nnz) {
+  size_t a = 0;
+  const int bits = 2 * lp_label_bits(n);
+  (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (uint64_t *)nullptr, (uint64_t *)nullptr,
+                                          nnz > 0 ? nnz : int64_t(1), 0, bits);
+  return a;
+}
+
+// With lp, the arrays of label propagation: the labels of two rounds (n
+// each, also when L has no entries) and two keys per stored entry (nnz_lp,
+// at least 1); the other methods need none of them.
+OrderWs carve_order(Carver &c, int64_t n, bool lp = false, int64_t nnz_lp = 0) {
   const int64_t m = n > 0 ? n : 1;
   OrderWs o;
   o.pkey = c.take<int32_t>(m);
@@ -161,7 +252,17 @@ OrderWs carve_order(Carver &c, int64_t n) {
   o.ncand = c.take<int32_t>(1);
   o.nsel = c.take<int64_t>(1);
   o.best = c.take<unsigned long long>(1);
+  o.ek = o.eks = nullptr;
+  o.lab = o.nlab = nullptr;
   o.temp_bytes = order_temp_bytes(n);
+  if (lp) {
+    const int64_t e = nnz_lp > 0 ? nnz_lp : 1;
+    o.ek = c.take<uint64_t>(e);
+    o.eks = c.take<uint64_t>(e);
+    o.lab = c.take<int32_t>(m);
+    o.nlab = c.take<int32_t>(m);
+    o.temp_bytes = std::max(o.temp_bytes, lp_temp_bytes(n, e));
+  }
   o.temp = c.take<char>(o.temp_bytes);
   return o;
 }
@@ -232,9 +333,50 @@ sped_status degree_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipS
   return SPED_OK;
 }
 
+sped_status label_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipStream_t s) {
+  const int64_t n = L->n, nnz = L->nnz;
+  if (!o.lab || !o.nlab || !o.ek || !o.eks) return fail(SPED_E_INVALID, "label propagation workspace not carved");
+  const int lbits = lp_label_bits(n);
+  int32_t *lab = o.lab, *nlab = o.nlab;
+  hipLaunchKernelGGL(iota_i32, dim3(oblocks(n)), dim3(kOB), 0, s, n, lab);
+  SPED_CHECK_HIP(hipGetLastError());
+  const unsigned kblocks = unsigned(std::min<int64_t>(8192, std::max<int64_t>(1, (n + kOB / kLpGroup - 1) /
+                                                                                   (kOB / kLpGroup))));
+  for (int r = 0; r < kLpRounds && nnz > 0; ++r) {
+    hipLaunchKernelGGL(lp_keys, dim3(kblocks), dim3(kOB), 0, s, n, lbits, L->rowptr, L->col, lab, o.ek);
+    SPED_CHECK_HIP(hipGetLastError());
+    size_t tb = o.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortKeys(o.temp, tb, o.ek, o.eks, nnz, 0, 2 * lbits, s));
+    SPED_CHECK_HIP(hipMemsetAsync(o.ncand, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(lp_choose, dim3(oblocks(n)), dim3(kOB), 0, s, n, lbits, L->rowptr, o.eks, lab, nlab,
+                       uint64_t(r + 1) << 32, o.ncand);
+    SPED_CHECK_HIP(hipGetLastError());
+    int32_t changed = 0;
+    SPED_CHECK_HIP(hipMemcpyAsync(&changed, o.ncand, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SPED_CHECK_HIP(hipStreamSynchronize(s));
+    if (!changed) break;  // nlab equals lab
+    std::swap(lab, nlab);
+  }
+  // stable sort of the labels with the ids (increasing) as values
+  hipLaunchKernelGGL(iota_i32, dim3(oblocks(n)), dim3(kOB), 0, s, n, o.cand);
+  SPED_CHECK_HIP(hipGetLastError());
+  size_t tb = o.temp_bytes;
+  SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(o.temp, tb, reinterpret_cast<const uint32_t *>(lab), o.k32s,
+                                                    o.cand, o.candS, n, 0, lbits, s));
+  hipLaunchKernelGGL(place_run, dim3(oblocks(n)), dim3(kOB), 0, s, n, int64_t(0), o.candS, pos, o.order);
+  SPED_CHECK_HIP(hipGetLastError());
+  SPED_CHECK_HIP(hipStreamSynchronize(s));
+  return SPED_OK;
+}
+
 sped_status run_order(const sped_csr *L, int32_t method, int32_t *pos, const OrderWs &o, hipStream_t s) {
   if (L->n == 0) return SPED_OK;
+  if (method == SPED_ORDER_LABEL_PROPAGATION) return label_order(L, pos, o, s);
   return method == SPED_ORDER_CUTHILL_MCKEE ? cuthill_mckee(L, pos, o, s) : degree_order(L, pos, o, s);
+}
+
+bool known_method(int32_t method) {
+  return method == SPED_ORDER_CUTHILL_MCKEE || method == SPED_ORDER_DEGREE || method == SPED_ORDER_LABEL_PROPAGATION;
 }
 
 // map[old_of_new1[i]] = pos[i] for the kept nodes; -1 elsewhere
@@ -281,11 +423,13 @@ using namespace sped;
 extern "C" sped_status sped_locality_order(const sped_csr *L, int32_t method, int32_t *new_of_old, void *ws,
                                            size_t *ws_bytes, sped_stream_t stream) {
   clear_error();
-  if (method != SPED_ORDER_CUTHILL_MCKEE && method != SPED_ORDER_DEGREE) return fail(SPED_E_INVALID, "method");
+  if (!known_method(method)) return fail(SPED_E_INVALID, "method");
   if (!L) return fail(SPED_E_INVALID, "L NULL");
   if (L->n < 0 || L->n >= (int64_t(1) << 31) - 1) return fail(SPED_E_INVALID, "n outside [0, 2^31 - 1)");
+  if (L->nnz < 0) return fail(SPED_E_INVALID, "nnz < 0");
   Carver c(ws);
-  const OrderWs o = carve_order(c, L->n);
+  const bool lp = method == SPED_ORDER_LABEL_PROPAGATION;
+  const OrderWs o = carve_order(c, L->n, lp, lp ? L->nnz : 0);
   bool query;
   SPED_TRY(check_ws(ws, ws_bytes, c.bytes(), &query));
   if (query) return SPED_OK;
@@ -298,17 +442,20 @@ extern "C" sped_status sped_laplacian_csr_ordered(int64_t n, int64_t m, const in
                                                   sped_csr *out, int32_t *old_of_new, void *ws, size_t *ws_bytes,
                                                   sped_stream_t stream) {
   clear_error();
-  if (method != SPED_ORDER_CUTHILL_MCKEE && method != SPED_ORDER_DEGREE) return fail(SPED_E_INVALID, "method");
+  if (!known_method(method)) return fail(SPED_E_INVALID, "method");
   if (n < 0 || n >= (int64_t(1) << 31) - 1) return fail(SPED_E_INVALID, "n outside [0, 2^31 - 1)");
   if (m < 0 || m > (int64_t(1) << 40)) return fail(SPED_E_INVALID, "m out of range");
   if (m > 0 && (!src || !dst)) return fail(SPED_E_INVALID, "src/dst NULL");
   if (kind != SPED_LAP_COMBINATORIAL && kind != SPED_LAP_SYM_NORMALIZED) return fail(SPED_E_INVALID, "kind");
   if (!out) return fail(SPED_E_INVALID, "out NULL");
   // region A serves the two builds and the order in turn; region B holds the
-  // relabelled edges and the maps between the three labellings
+  // relabelled edges and the maps between the three labellings.  The built
+  // Laplacian stores at most 2m entries, which bounds label propagation's
+  // entry arrays.
   const size_t a_bytes = std::max(build_ws_bytes(n, m, src, dst, kind), [&] {
     Carver t(nullptr);
-    carve_order(t, n);
+    const bool lp = method == SPED_ORDER_LABEL_PROPAGATION;
+    carve_order(t, n, lp, lp ? 2 * m : 0);
     return t.bytes();
   }());
   Carver c(ws);

@@ -183,7 +183,7 @@ def _call_ws(fn, where, args_before_ws, device, allow=()):
 
 
 # ------------------------------------------------------------------ Laplacian
-ORDERS = {"cuthill_mckee": 0, "cm": 0, "degree": 1}
+ORDERS = {"cuthill_mckee": 0, "cm": 0, "degree": 1, "label_propagation": 2, "lp": 2}
 
 
 class Laplacian:

@@ -306,10 +306,22 @@ def test_locality_order_validation(lib):
     need = ctypes.c_size_t(0)
     c = sped.CSR()
     c.n, c.nnz, c.kind = 100, 400, sped.SYM_NORMALIZED
-    assert lib.sped_locality_order(ctypes.byref(c), 2, None, None, ctypes.byref(need), None) == sped.E_INVALID
+    assert lib.sped_locality_order(ctypes.byref(c), 3, None, None, ctypes.byref(need), None) == sped.E_INVALID
     assert lib.sped_locality_order(None, 0, None, None, ctypes.byref(need), None) == sped.E_INVALID
     assert lib.sped_locality_order(ctypes.byref(c), 0, None, None, ctypes.byref(need), None) == sped.OK
     assert need.value >= 100 * (5 * 4 + 2 * 8)
+    # label propagation sorts two 8-byte keys per stored entry
+    assert lib.sped_locality_order(ctypes.byref(c), 2, None, None, ctypes.byref(need), None) == sped.OK
+    assert need.value >= 2 * 400 * 8 + 100 * (7 * 4 + 2 * 8)
+    c.nnz = -1
+    assert lib.sped_locality_order(ctypes.byref(c), 2, None, None, ctypes.byref(need), None) == sped.E_INVALID
+    # an entry-free Laplacian still needs the labels of two rounds (n int32
+    # each) and one key per entry array
+    c.n, c.nnz = 1000, 0
+    cm, lp = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.sped_locality_order(ctypes.byref(c), 0, None, None, ctypes.byref(cm), None) == sped.OK
+    assert lib.sped_locality_order(ctypes.byref(c), 2, None, None, ctypes.byref(lp), None) == sped.OK
+    assert lp.value >= cm.value + 2 * 1000 * 4 + 2 * 8
     out = sped.CSR()
     assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, sped.SYM_NORMALIZED, 1, 7, ctypes.byref(out), None,
                                           None, ctypes.byref(need), None) == sped.E_INVALID
@@ -321,6 +333,10 @@ def test_locality_order_validation(lib):
     assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, sped.SYM_NORMALIZED, 1, 0, ctypes.byref(out),
                                           None, None, ctypes.byref(need), None) == sped.OK
     assert need.value >= 2 * 200 * 4 + 3 * 100 * 4
+    # label propagation: room for the keys of the at most 2m stored entries
+    assert lib.sped_laplacian_csr_ordered(100, 200, 16, 16, None, sped.SYM_NORMALIZED, 1, 2, ctypes.byref(out),
+                                          None, None, ctypes.byref(need), None) == sped.OK
+    assert need.value >= 2 * (2 * 200) * 8 + 2 * 200 * 4 + 3 * 100 * 4
     with pytest.raises(ValueError):
         sped.Laplacian(3, [0], [1], order="rcm")
 

@@ -67,8 +67,19 @@ def graph(case):
 CASES = ["sbm_disconnected", "powerlaw", "grid", "rmat_hub", "forest", "edgeless", "single_edge"]
 
 
+def oracle_order(method, n, rowptr, col):
+    if method == "cuthill_mckee":
+        return oorder.cuthill_mckee(n, rowptr, col)
+    if method == "degree":
+        return oorder.degree_order(n, rowptr)
+    return oorder.label_order(n, rowptr, col)
+
+
+METHODS = ["cuthill_mckee", "degree", "label_propagation"]
+
+
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("method", ["cuthill_mckee", "degree"])
+@pytest.mark.parametrize("method", METHODS)
 def test_locality_order_matches_oracle(sped, case, method):
     n, s, d = graph(case)
     _say(f"locality order {method} {case} n={n} m={s.shape[0]}")
@@ -76,14 +87,13 @@ def test_locality_order_matches_oracle(sped, case, method):
     ref = olap.laplacian(n, s, d, kind=olap.SYM_NORMALIZED)
     rowptr, col, _ = ref.adjacency()
     got = sped.locality_order(L, method).cpu().numpy()
-    want = oorder.cuthill_mckee(n, rowptr, col) if method == "cuthill_mckee" else oorder.degree_order(n, rowptr)
-    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(got, oracle_order(method, n, rowptr, col))
 
 
 @pytest.mark.parametrize("case,lcc,kind", [("powerlaw", True, "sym"), ("rmat_hub", False, "combinatorial"),
                                            ("sbm_disconnected", True, "combinatorial"), ("grid", False, "sym"),
                                            ("forest", True, "sym")])
-@pytest.mark.parametrize("method", ["cuthill_mckee", "degree"])
+@pytest.mark.parametrize("method", METHODS)
 def test_ordered_build_is_the_relabelled_laplacian(sped, case, lcc, kind, method):
     n, s, d = graph(case)
     w = synth.random_weights(s.shape[0], 8).astype(np.float32).astype(np.float64)
@@ -92,8 +102,7 @@ def test_ordered_build_is_the_relabelled_laplacian(sped, case, lcc, kind, method
     L = sped.Laplacian(n, s, d, w, kind=kind, lcc=lcc, order=method)
     base = olap.laplacian(n, s, d, w, kind=okind, lcc=lcc)
     rowptr0, col0, _ = base.adjacency()
-    pos = oorder.cuthill_mckee(base.n, rowptr0, col0) if method == "cuthill_mckee" else \
-        oorder.degree_order(base.n, rowptr0)
+    pos = oracle_order(method, base.n, rowptr0, col0)
     # the kept component's edges, in its own ids, relabelled by the order
     keep_id = -np.ones(n, np.int64)
     keep_id[base.old_of_new] = np.arange(base.n)
@@ -130,7 +139,7 @@ def test_ordered_build_is_the_relabelled_laplacian(sped, case, lcc, kind, method
 
 
 def test_ordered_build_edge_cases(sped):
-    _say("ordered build: empty graph, self-loops only, invalid endpoint")
+    _say("ordered build: empty graph, self-loops only, invalid endpoint (all methods)")
     L = sped.Laplacian(6, [], [], kind="sym", order="cuthill_mckee")
     assert L.n == 6 and L.nnz == 0
     np.testing.assert_array_equal(L.old_of_new.cpu().numpy(), np.arange(6))
@@ -143,6 +152,16 @@ def test_ordered_build_edge_cases(sped):
     # lcc of an edgeless graph keeps one node
     L = sped.Laplacian(5, [], [], lcc=True, order="cuthill_mckee")
     assert L.n == 1
+    # label propagation on the same degenerate inputs
+    L = sped.Laplacian(6, [], [], kind="sym", order="label_propagation")
+    assert L.n == 6 and L.nnz == 0
+    np.testing.assert_array_equal(L.old_of_new.cpu().numpy(), np.arange(6))
+    L = sped.Laplacian(4, [1, 2], [1, 2], kind="combinatorial", order="label_propagation")
+    assert L.nnz == 0
+    L = sped.Laplacian(0, [], [], order="label_propagation")
+    assert L.n == 0
+    with pytest.raises(sped.SpedError):
+        sped.Laplacian(4, [0, 5], [1, 2], order="label_propagation")
 
 
 def test_solve_on_ordered_laplacian(sped):
