@@ -23,8 +23,11 @@
 // round, ties going to the smallest splitmix64 output of (label XOR (round +
 // 1) << 32); at most kLpRounds rounds, stopping after a round that changes no
 // label.  A round sorts the (row, neighbour label) keys of all stored entries
-// (one radix sort; rows stay in their CSR ranges) and one thread per row
-// scans its sorted range for the longest run.  The order groups the nodes by
+// (one radix sort; rows stay in their CSR ranges); each run of equal keys is
+// counted by the thread at its first entry, and three passes over the runs
+// take, per row, the largest count (atomicMax), the smallest tie-break key
+// among the runs of that count (atomicMin), and the label of the run that
+// holds both: the atomics' order does not matter.  The order groups the nodes by
 // final label (increasing), ids increasing inside a group: one stable radix
 // sort of the labels with the ids as values.
 
@@ -160,37 +163,65 @@ __global__ __launch_bounds__(kOB) void lp_keys(int64_t n, int lbits, const int64
   }
 }
 
-// One thread per row: the longest run of equal labels in the row's sorted
-// keys, ties by the smaller mix64(label ^ salt); rows without entries keep
-// their label.  *changed is set when any label moves.
-__global__ void lp_choose(int64_t n, int lbits, const int64_t *__restrict__ rowptr,
-                          const uint64_t *__restrict__ keys, const int32_t *__restrict__ lab,
-                          int32_t *__restrict__ nlab, uint64_t salt, int32_t *__restrict__ changed) {
+// Per node: no count yet, the largest tie-break key, the label kept.
+__global__ void lp_reset(int64_t n, const int32_t *__restrict__ lab, int32_t *__restrict__ nlab,
+                         int32_t *__restrict__ bestcnt, uint64_t *__restrict__ besth) {
   const int64_t u = int64_t(blockIdx.x) * kOB + threadIdx.x;
   if (u >= n) return;
-  const uint64_t mask = (uint64_t(1) << lbits) - 1;
-  const int64_t b = rowptr[u], e = rowptr[u + 1];
-  int32_t best = lab[u];
-  if (e > b) {
-    int64_t best_cnt = 0;
-    uint64_t best_h = 0;
-    int64_t p = b;
-    while (p < e) {
-      const uint64_t l = keys[p] & mask;
-      int64_t q = p + 1;
-      while (q < e && (keys[q] & mask) == l) ++q;
-      const int64_t cnt = q - p;
-      const uint64_t h = mix64(l ^ salt);
-      if (cnt > best_cnt || (cnt == best_cnt && h < best_h)) {
-        best_cnt = cnt;
-        best_h = h;
-        best = int32_t(l);
-      }
-      p = q;
-    }
+  nlab[u] = lab[u];
+  bestcnt[u] = 0;
+  besth[u] = ~uint64_t(0);
+}
+
+// The thread at the first entry of each run of equal sorted keys counts the
+// run and stores (count << 32 | label) in info[p] (0 elsewhere); the row's
+// largest count is taken with atomicMax.
+__global__ void lp_runs(int64_t nnz, int lbits, const uint64_t *__restrict__ keys, uint64_t *__restrict__ info,
+                        int32_t *__restrict__ bestcnt) {
+  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (p >= nnz) return;
+  const uint64_t k = keys[p];
+  if (p > 0 && keys[p - 1] == k) {
+    info[p] = 0;
+    return;
   }
-  nlab[u] = best;
-  if (best != lab[u]) *changed = 1;
+  int64_t q = p + 1;
+  while (q < nnz && keys[q] == k) ++q;
+  const uint64_t mask = (uint64_t(1) << lbits) - 1;
+  info[p] = (uint64_t(q - p) << 32) | (k & mask);
+  atomicMax(&bestcnt[k >> lbits], int32_t(q - p));
+}
+
+// Runs of the row's largest count: the smallest tie-break key (atomicMin).
+__global__ void lp_ties(int64_t nnz, int lbits, const uint64_t *__restrict__ keys,
+                        const uint64_t *__restrict__ info, const int32_t *__restrict__ bestcnt,
+                        unsigned long long *__restrict__ besth, uint64_t salt) {
+  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (p >= nnz) return;
+  const uint64_t v = info[p];
+  const int32_t cnt = int32_t(v >> 32);
+  if (cnt == 0) return;
+  const int64_t row = int64_t(keys[p] >> lbits);
+  if (cnt == bestcnt[row]) atomicMin(&besth[row], static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt)));
+}
+
+// The run holding both the largest count and the smallest key (one per row:
+// labels differ inside a row and mix64 is a bijection) sets the new label.
+__global__ void lp_pick(int64_t nnz, int lbits, const uint64_t *__restrict__ keys, const uint64_t *__restrict__ info,
+                        const int32_t *__restrict__ bestcnt, const uint64_t *__restrict__ besth,
+                        const int32_t *__restrict__ lab, int32_t *__restrict__ nlab, uint64_t salt,
+                        int32_t *__restrict__ changed) {
+  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (p >= nnz) return;
+  const uint64_t v = info[p];
+  const int32_t cnt = int32_t(v >> 32);
+  if (cnt == 0) return;
+  const int64_t row = int64_t(keys[p] >> lbits);
+  const uint64_t l = v & 0xFFFFFFFFull;
+  if (cnt == bestcnt[row] && mix64(l ^ salt) == besth[row]) {
+    nlab[row] = int32_t(l);
+    if (int32_t(l) != lab[row]) *changed = 1;
+  }
 }
 
 struct OrderWs {
@@ -347,9 +378,18 @@ sped_status label_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipSt
     SPED_CHECK_HIP(hipGetLastError());
     size_t tb = o.temp_bytes;
     SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortKeys(o.temp, tb, o.ek, o.eks, nnz, 0, 2 * lbits, s));
+    const uint64_t salt = uint64_t(r + 1) << 32;
+    // per-row maxima in arrays this method leaves free: the search keys
+    // (int32 [n]) and the 64-bit level keys (uint64 [n])
+    int32_t *bestcnt = o.pkey;
+    uint64_t *besth = o.k2;
     SPED_CHECK_HIP(hipMemsetAsync(o.ncand, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(lp_choose, dim3(oblocks(n)), dim3(kOB), 0, s, n, lbits, L->rowptr, o.eks, lab, nlab,
-                       uint64_t(r + 1) << 32, o.ncand);
+    hipLaunchKernelGGL(lp_reset, dim3(oblocks(n)), dim3(kOB), 0, s, n, lab, nlab, bestcnt, besth);
+    hipLaunchKernelGGL(lp_runs, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt);
+    hipLaunchKernelGGL(lp_ties, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt,
+                       reinterpret_cast<unsigned long long *>(besth), salt);
+    hipLaunchKernelGGL(lp_pick, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt, besth, lab,
+                       nlab, salt, o.ncand);
     SPED_CHECK_HIP(hipGetLastError());
     int32_t changed = 0;
     SPED_CHECK_HIP(hipMemcpyAsync(&changed, o.ncand, sizeof(int32_t), hipMemcpyDeviceToHost, s));
