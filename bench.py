@@ -1226,11 +1226,10 @@ def power_law_bf16(sped, synth, torch, np):
     symmetric normalised L; a 64-column bf16 block.  Times the degree-16
     limit application (bf16 in and out, float32 intermediates, as the
     solver's bf16 phase uses it) and one all-bf16 fused step, with the
-    algorithmic bytes of each."""
+    algorithmic bytes of each, on the generator's ids and again on the
+    label-propagation numbering (the ordered build timed apart)."""
     n0, src, dst = synth.chung_lu_device(4_000_000, 2.1, 16.0, 256, 0.95, seed=1)
     L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False)
-    del src, dst
-    torch.cuda.empty_cache()
     k, ell = 64, 16
     X = synth.gaussian_block_device(L.n, k, seed=2, dtype=torch.bfloat16)
     Y = torch.empty_like(X)
@@ -1253,12 +1252,30 @@ def power_law_bf16(sped, synth, torch, np):
     idx = 8 * (L.n + 1) + L.nnz * 8 + 4 * L.n
     step_bytes = idx + L.n * k * (2 + 2)                      # bf16 U in, bf16 O out
     chain_bytes = ell * idx + L.n * k * (2 + 4 + (ell - 2) * 8 + 4 + 2)  # bf16 X, f32 between, bf16 Y
-    return {"workload": "Chung-Lu n=4e6 (device draw), exponent 2.1, mean degree 16, 256 communities; "
-                        "largest component; sym-normalised L; k=64 bf16",
-            "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree, "medium_rows": L.n_medium,
-            "heavy_rows": L.n_heavy, "xcd_rows": L.xcd_rows,
-            "chain_ms": round(chain_ms, 4), "chain_GBps": round(chain_bytes / (chain_ms * 1e-3) / 1e9, 1),
-            "bf16_step_us": round(step_ms * 1e3, 2), "bf16_step_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1)}
+    out = {"workload": "Chung-Lu n=4e6 (device draw), exponent 2.1, mean degree 16, 256 communities; "
+                       "largest component; sym-normalised L; k=64 bf16",
+           "n_lcc": L.n, "nnz": L.nnz, "max_degree": L.max_degree, "medium_rows": L.n_medium,
+           "heavy_rows": L.n_heavy, "xcd_rows": L.xcd_rows,
+           "chain_ms": round(chain_ms, 4), "chain_GBps": round(chain_bytes / (chain_ms * 1e-3) / 1e9, 1),
+           "bf16_step_us": round(step_ms * 1e3, 2), "bf16_step_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1)}
+    # the same graph numbered by label propagation (same operator, rows permuted)
+    del L, X, Y
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = sped.Laplacian(n0, src, dst, kind="sym", lcc=True, walk_records=False, order="label_propagation")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del src, dst
+    X = synth.gaussian_block_device(L.n, k, seed=2, dtype=torch.bfloat16)
+    Y = torch.empty_like(X)
+    chain_ms = timed(lambda: sped.apply_poly(L, p, X, out=Y), 5)
+    step_ms = timed(lambda: sped.apply_poly(L, one, X, out=Y), 20)
+    out["label_propagation_ids"] = {
+        "ordered_build_s": round(build_s, 3),
+        "chain_ms": round(chain_ms, 4), "chain_GBps": round(chain_bytes / (chain_ms * 1e-3) / 1e9, 1),
+        "bf16_step_us": round(step_ms * 1e3, 2), "bf16_step_GBps": round(step_bytes / (step_ms * 1e-3) / 1e9, 1)}
+    return out
 
 
 def main():
