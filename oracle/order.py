@@ -94,6 +94,15 @@ def mix64(x: int) -> int:
     return x ^ (x >> 31)
 
 
+def mix64_np(x) -> np.ndarray:
+    """mix64 on an array of 64-bit words (numpy's uint64 products wrap)."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        x = (x ^ (x >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        x = (x ^ (x >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return x ^ (x >> np.uint64(31))
+
+
 def label_propagation(n: int, rowptr, col, rounds: int = LP_ROUNDS, return_rounds: bool = False):
     """Labels after synchronous label propagation (readings in the module
     docstring); a node's label is the id of some node.  With return_rounds,
@@ -123,9 +132,37 @@ def label_propagation(n: int, rowptr, col, rounds: int = LP_ROUNDS, return_round
     return (lab, ran) if return_rounds else lab
 
 
-def label_order(n: int, rowptr, col, rounds: int = LP_ROUNDS) -> np.ndarray:
-    """Nodes sorted by (label after label propagation, id)."""
-    lab = label_propagation(n, rowptr, col, rounds)
+def label_propagation_np(n: int, rowptr, col, rounds: int = LP_ROUNDS) -> np.ndarray:
+    """The same rounds as `label_propagation`, with numpy doing the counting
+    (for graphs too large for the plain loops): each (node, neighbour label)
+    pair is counted with np.unique, and each node keeps the pair of largest
+    count, then smallest tie-break key.  Pinned against the loops on small
+    graphs."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    lab = np.arange(n, dtype=np.int64)
+    for r in range(rounds):
+        salt = (r + 1) << 32
+        pairs, counts = np.unique(rows * n + lab[col], return_counts=True) if n else (np.zeros(0, np.int64),) * 2
+        node, cand = pairs // max(n, 1), pairs % max(n, 1)
+        keys = mix64_np(cand.astype(np.uint64) ^ np.uint64(salt))
+        # per node: largest count first, then smallest key
+        pick = np.lexsort((keys, -counts, node))
+        first = np.ones(pick.shape[0], dtype=bool)
+        first[1:] = node[pick][1:] != node[pick][:-1]
+        new = lab.copy()
+        new[node[pick][first]] = cand[pick][first]
+        if np.array_equal(new, lab):
+            break
+        lab = new
+    return lab
+
+
+def label_order(n: int, rowptr, col, rounds: int = LP_ROUNDS, fast: bool = False) -> np.ndarray:
+    """Nodes sorted by (label after label propagation, id); fast=True counts
+    with numpy (label_propagation_np)."""
+    lab = (label_propagation_np if fast else label_propagation)(n, rowptr, col, rounds)
     order = sorted(range(n), key=lambda v: (int(lab[v]), v))
     new_of_old = np.empty(n, dtype=np.int64)
     for pos, v in enumerate(order):

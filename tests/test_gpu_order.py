@@ -164,10 +164,11 @@ def test_ordered_build_edge_cases(sped):
         sped.Laplacian(4, [0, 5], [1, 2], order="label_propagation")
 
 
-def test_solve_on_ordered_laplacian(sped):
-    """The bottom-10 span solved on a Cuthill-McKee-numbered Laplacian, mapped
-    back through old_of_new, is the dense-eigh span of the original graph
-    (SBM n=2000, 10 blocks, plus an isolated pair outside the largest
+@pytest.mark.parametrize("method", METHODS)
+def test_solve_on_ordered_laplacian(sped, method):
+    """The bottom-10 span solved on a Laplacian numbered by each order,
+    mapped back through old_of_new, is the dense-eigh span of the original
+    graph (SBM n=2000, 10 blocks, plus an isolated pair outside the largest
     component), and k-means labels map back the same way."""
     from oracle import kmeans as okm
     from oracle import solver as osol
@@ -175,8 +176,8 @@ def test_solve_on_ordered_laplacian(sped):
     s = np.concatenate([s, [n]])
     d = np.concatenate([d, [n + 1]])
     n_all = n + 2
-    _say("bottom-10 solve on the ordered Laplacian, mapped back")
-    L = sped.Laplacian(n_all, s, d, kind="sym", lcc=True, order="cuthill_mckee")
+    _say(f"bottom-10 solve on the {method}-ordered Laplacian, mapped back")
+    L = sped.Laplacian(n_all, s, d, kind="sym", lcc=True, order=method)
     base = olap.laplacian(n_all, s, d, kind=olap.SYM_NORMALIZED, lcc=True)
     assert L.n == base.n == n
     lam, U, _ = osol.dense_bottom_k(base.dense(), 10)

@@ -235,11 +235,12 @@ def test_rmat_scale20_walks_on_hub_rows(sped):
 
 
 def test_rmat_scale18_locality_orders(sped):
-    """Both node orders on an R-MAT scale-18 largest component (hubs of
-    thousands of neighbours, ~10 search levels) equal the oracle's exactly;
-    the ordered build numbers its rows in that order."""
+    """The node orders on an R-MAT scale-18 largest component (hubs of
+    thousands of neighbours, ~10 search levels, label runs of every length)
+    equal the oracle's exactly (label propagation against its numpy-counting
+    form); the ordered build numbers its rows in that order."""
     from oracle import order as oorder
-    _say("R-MAT scale 18, largest component: Cuthill-McKee and degree orders, ordered build")
+    _say("R-MAT scale 18, largest component: Cuthill-McKee, degree and label-propagation orders, ordered build")
     n, src, dst = synth.rmat_device(18, 16, 0.57, 0.19, 0.19, seed=5)
     src_h, dst_h = src.cpu().numpy(), dst.cpu().numpy()
     L = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False)
@@ -248,7 +249,9 @@ def test_rmat_scale18_locality_orders(sped):
     assert L.n == ref.n
     _say(f"  n_lcc={L.n} nnz={L.nnz} max_degree={L.max_degree}")
     for method, want in (("cuthill_mckee", oorder.cuthill_mckee(ref.n, rowptr, col)),
-                         ("degree", oorder.degree_order(ref.n, rowptr))):
+                         ("degree", oorder.degree_order(ref.n, rowptr)),
+                         ("label_propagation", oorder.label_order(ref.n, rowptr, col, fast=True))):
+        _say(f"  {method}")
         got = sped.locality_order(L, method).cpu().numpy()
         np.testing.assert_array_equal(got, want)
         Lo = sped.Laplacian(n, src, dst, kind="sym", lcc=True, walk_records=False, order=method)

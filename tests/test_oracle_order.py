@@ -302,3 +302,31 @@ def test_label_propagation_pins_catch_plausible_mistakes(monkeypatch):
     # smallest-label ties: every clique ends at its smallest id instead
     monkeypatch.setattr(oorder, "mix64", lambda x: x & 0xFFFFFFFF)
     assert list(oorder.label_propagation(base, rowptr, col)) != want
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_label_propagation_numpy_form_matches_the_loops(seed):
+    """Brute force: the numpy-counting form equals the plain loops, round
+    for round, on small random graphs (several components, isolated nodes,
+    ties, 2-cycles) and for every round cap."""
+    g = np.random.default_rng(seed)
+    n = int(g.integers(5, 60))
+    m = int(g.integers(0, 3 * n))
+    src, dst = g.integers(0, n, m), g.integers(0, n, m)
+    rowptr, col = adjacency(n, src, dst)
+    for rounds in (1, 2, 5, oorder.LP_ROUNDS):
+        np.testing.assert_array_equal(oorder.label_propagation_np(n, rowptr, col, rounds),
+                                      oorder.label_propagation(n, rowptr, col, rounds))
+    np.testing.assert_array_equal(oorder.label_order(n, rowptr, col, fast=True), oorder.label_order(n, rowptr, col))
+
+
+def test_label_propagation_numpy_form_on_the_planted_graph():
+    n, s, d, _ = synth.sbm_bernoulli([200] * 10, 0.05, 0.0005, seed=1)
+    rowptr, col = adjacency(n, s, d)
+    np.testing.assert_array_equal(oorder.label_propagation_np(n, rowptr, col), oorder.label_propagation(n, rowptr, col))
+
+
+def test_mix64_array_form():
+    g = np.random.default_rng(3)
+    x = g.integers(0, 2 ** 63, 1000, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(1)
+    np.testing.assert_array_equal(oorder.mix64_np(x), np.array([oorder.mix64(int(v)) for v in x], dtype=np.uint64))
