@@ -19,8 +19,9 @@ solver     Block subspace iteration / Oja with Householder QR, Rayleigh-Ritz,
            subspace error and principal angles (Sec. 5.2).
 kmeans     Lloyd's k-means with k-means++ seeding on the embedding (Sec. 1).
 grad       Gradient of p_theta(L) X with respect to theta and X.
-order      Node orders for gather locality (Cuthill-McKee, degree); the
-           paper fixes none, so these follow their textbook definitions.
+order      Node orders for gather locality (Cuthill-McKee, degree, label
+           propagation with splitmix64 tie-breaks); the paper fixes none, so
+           these follow their published definitions.
 
 Parity status: every function is pinned by a `-m "not gpu"` test in
 tests/test_oracle_*.py; none is "parity unpinned".
