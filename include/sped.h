@@ -158,7 +158,8 @@ sped_status sped_laplacian_csr(int64_t n, int64_t m, const int32_t *src, const i
  *      round (unweighted counts), ties going to the label with the smallest
  *      splitmix64 output of (label XOR (round + 1) << 32), rounds from 0; at
  *      most 16 rounds, stopping after one that changes no label.  Groups in
- *      increasing label, ids increasing inside a group.
+ *      increasing label; inside a group decreasing degree, then increasing
+ *      id.
  * Degree = number of distinct neighbours (row length of L's off-diagonal part).
  */
 typedef enum {

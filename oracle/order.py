@@ -17,7 +17,8 @@ here, each as plainly as it can be written:
 * Label-propagation order: nodes grouped by the communities that synchronous
   label propagation (Raghavan, Albert and Kumara, "Near linear time algorithm
   to detect community structures in large-scale networks", Phys. Rev. E 76,
-  2007) finds, groups in increasing label, ids increasing inside a group.
+  2007) finds, groups in increasing label; inside a group decreasing
+  degree, then increasing id (a community's hubs share cache lines).
   Readings: every node starts with its own id as label; in each round every
   node with neighbours takes, from the previous round's labels, the label
   most frequent among its stored neighbours (unweighted counts); ties go to
@@ -160,10 +161,12 @@ def label_propagation_np(n: int, rowptr, col, rounds: int = LP_ROUNDS) -> np.nda
 
 
 def label_order(n: int, rowptr, col, rounds: int = LP_ROUNDS, fast: bool = False) -> np.ndarray:
-    """Nodes sorted by (label after label propagation, id); fast=True counts
-    with numpy (label_propagation_np)."""
+    """Nodes sorted by (label after label propagation, decreasing degree,
+    id); fast=True counts with numpy (label_propagation_np)."""
     lab = (label_propagation_np if fast else label_propagation)(n, rowptr, col, rounds)
-    order = sorted(range(n), key=lambda v: (int(lab[v]), v))
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    deg = [int(rowptr[v + 1] - rowptr[v]) for v in range(n)]
+    order = sorted(range(n), key=lambda v: (int(lab[v]), -deg[v], v))
     new_of_old = np.empty(n, dtype=np.int64)
     for pos, v in enumerate(order):
         new_of_old[v] = pos

@@ -28,8 +28,9 @@
 // take, per row, the largest count (atomicMax), the smallest tie-break key
 // among the runs of that count (atomicMin), and the label of the run that
 // holds both: the atomics' order does not matter.  The order groups the nodes by
-// final label (increasing), ids increasing inside a group: one stable radix
-// sort of the labels with the ids as values.
+// final label (increasing), inside a group by decreasing degree, then
+// increasing id: one stable radix sort of (label, ~degree) keys with the ids
+// as values.
 
 #include <hipcub/hipcub.hpp>
 
@@ -224,6 +225,15 @@ __global__ void lp_pick(int64_t nnz, int lbits, const uint64_t *__restrict__ key
   }
 }
 
+// (label << 32) | ~degree, and the ids 0 .. n-1 as values
+__global__ void lp_order_keys(int64_t n, const int64_t *__restrict__ rowptr, const int32_t *__restrict__ lab,
+                              uint64_t *__restrict__ keys, int32_t *__restrict__ ids) {
+  const int64_t i = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (i >= n) return;
+  keys[i] = (uint64_t(uint32_t(lab[i])) << 32) | uint64_t(~uint32_t(rowptr[i + 1] - rowptr[i]));
+  ids[i] = int32_t(i);
+}
+
 struct OrderWs {
   int32_t *pkey, *order, *cand, *candS, *ids2;
   uint64_t *k2, *k2s;
@@ -397,12 +407,12 @@ sped_status label_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipSt
     if (!changed) break;  // nlab equals lab
     std::swap(lab, nlab);
   }
-  // stable sort of the labels with the ids (increasing) as values
-  hipLaunchKernelGGL(iota_i32, dim3(oblocks(n)), dim3(kOB), 0, s, n, o.cand);
+  // stable sort of (label, ~degree) with the ids (increasing) as values;
+  // the 64-bit key arrays are free again after the rounds
+  hipLaunchKernelGGL(lp_order_keys, dim3(oblocks(n)), dim3(kOB), 0, s, n, L->rowptr, lab, o.k2, o.cand);
   SPED_CHECK_HIP(hipGetLastError());
   size_t tb = o.temp_bytes;
-  SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(o.temp, tb, reinterpret_cast<const uint32_t *>(lab), o.k32s,
-                                                    o.cand, o.candS, n, 0, lbits, s));
+  SPED_CHECK_HIP(hipcub::DeviceRadixSort::SortPairs(o.temp, tb, o.k2, o.k2s, o.cand, o.candS, n, 0, 32 + lbits, s));
   hipLaunchKernelGGL(place_run, dim3(oblocks(n)), dim3(kOB), 0, s, n, int64_t(0), o.candS, pos, o.order);
   SPED_CHECK_HIP(hipGetLastError());
   SPED_CHECK_HIP(hipStreamSynchronize(s));

@@ -270,8 +270,9 @@ def test_label_order_properties():
     pos = oorder.label_order(n, rowptr, col)
     assert sorted(pos.tolist()) == list(range(n))
     order = np.argsort(pos)
-    keys = list(zip(lab[order].tolist(), order.tolist()))
-    assert keys == sorted(keys)  # grouped by label, ids increasing inside
+    deg = np.diff(rowptr)
+    keys = list(zip(lab[order].tolist(), (-deg[order]).tolist(), order.tolist()))
+    assert keys == sorted(keys)  # grouped by label; decreasing degree, then id inside
     assert all(lab[v] == v for v in range(n - 3, n))
 
 
