@@ -1249,6 +1249,26 @@ def stream_apply_leg(sped, torch, np, L, n, s, d, Q):
             "resident_sparse_step_ms": round(resident_ms, 4), "max_rel_diff_vs_resident": rel}
 
 
+def copy_rate_leg(sped, torch, np, reps=10):
+    """The achievable HBM rate on this machine: the library's plain copy kernel
+    over 512 MiB (read + write bytes / time, median of `reps` launches)."""
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    sped.stream_copy(a, b)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sped.stream_copy(a, b)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * COPY_BYTES / (float(np.median(ts)) * 1e-3) / 1e9
+
+
 def ordered_chain_leg(sped, torch, np, n, s, d, Q, ell, per_launch, reps=10):
     """The headline's exact chain on the same SBM numbered by label
     propagation (the optional order, built and timed apart; `value` stays on
@@ -1498,6 +1518,7 @@ def main():
         parts["cholqr2_ms"] = round(float(np.mean([e[2].elapsed_time(e[3]) for e in evs])), 4)
         parts["rayleigh_ritz_ms"] = round(float(np.mean([e[3].elapsed_time(e[4]) for e in evs])), 4)
     per_launch = spmm_step_bytes(L.n, L.nnz, k)
+    copy_GBps = copy_rate_leg(sped, torch, np)
     app_bytes = ell * per_launch
     value = app_bytes / (chain_ms * 1e-3) / 1e9
     launch_s = chain_ms * 1e-3 / ell
@@ -1514,7 +1535,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "spmm_light (fused sparse step)",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": per_launch, "avg_launch_us": round(launch_s * 1e6, 3)},
+                     "alg_bytes_per_launch": per_launch, "avg_launch_us": round(launch_s * 1e6, 3),
+                     # the rate a plain 512 MiB copy reaches on this machine, beside the spec peak
+                     "copy_GBps": round(copy_GBps, 1), "frac_of_copy": round(achieved / copy_GBps, 4)},
         "step_breakdown": parts,
         "pLV_per_s": round(1e3 / chain_ms, 2),
         # one timed step is one solver iteration (exact product, walk estimate,
