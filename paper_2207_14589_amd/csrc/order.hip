@@ -23,11 +23,13 @@
 // round, ties going to the smallest splitmix64 output of (label XOR (round +
 // 1) << 32); at most kLpRounds rounds, stopping after a round that changes no
 // label.  A round sorts the (row, neighbour label) keys of all stored entries
-// (one radix sort; rows stay in their CSR ranges); each run of equal keys is
-// counted by the thread at its first entry, and three passes over the runs
-// take, per row, the largest count (atomicMax), the smallest tie-break key
-// among the runs of that count (atomicMin), and the label of the run that
-// holds both: the atomics' order does not matter.  The order groups the nodes by
+// (one radix sort; rows stay in their CSR ranges); an inclusive max-scan of
+// the run-start positions gives every entry the start of its run, so the
+// thread at each run's last entry knows the run's length without walking
+// it; three passes over the runs then take, per row, the largest count
+// (atomicMax), the smallest tie-break key among the runs of that count
+// (atomicMin), and the label of the run that holds both: the atomics' order
+// does not matter.  The order groups the nodes by
 // final label (increasing), inside a group by decreasing degree, then
 // increasing id: one stable radix sort of (label, ~degree) keys with the ids
 // as values.
@@ -174,23 +176,32 @@ __global__ void lp_reset(int64_t n, const int32_t *__restrict__ lab, int32_t *__
   besth[u] = ~uint64_t(0);
 }
 
-// The thread at the first entry of each run of equal sorted keys counts the
-// run and stores (count << 32 | label) in info[p] (0 elsewhere); the row's
-// largest count is taken with atomicMax.
-__global__ void lp_runs(int64_t nnz, int lbits, const uint64_t *__restrict__ keys, uint64_t *__restrict__ info,
-                        int32_t *__restrict__ bestcnt) {
+__device__ inline bool run_start(const uint64_t *__restrict__ keys, int64_t p) {
+  return p == 0 || keys[p - 1] != keys[p];
+}
+
+// info[p] = p at the first entry of each run of equal sorted keys, 0
+// elsewhere; an inclusive max-scan then leaves each entry its run's start.
+__global__ void lp_mark(int64_t nnz, const uint64_t *__restrict__ keys, uint64_t *__restrict__ info) {
+  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  if (p < nnz) info[p] = run_start(keys, p) ? uint64_t(p) : 0;
+}
+
+// The thread at the last entry of each run reads the run's start from the
+// scanned info, stores (count << 32 | label) at info[start] (the only slot
+// of the run read later: the passes below read run starts only) and takes
+// the row's largest count with atomicMax.
+__global__ void lp_count(int64_t nnz, int lbits, const uint64_t *__restrict__ keys, uint64_t *__restrict__ info,
+                         int32_t *__restrict__ bestcnt) {
   const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
   if (p >= nnz) return;
   const uint64_t k = keys[p];
-  if (p > 0 && keys[p - 1] == k) {
-    info[p] = 0;
-    return;
-  }
-  int64_t q = p + 1;
-  while (q < nnz && keys[q] == k) ++q;
+  if (p + 1 < nnz && keys[p + 1] == k) return;  // not the run's last entry
+  const int64_t start = int64_t(info[p]);
+  const int64_t cnt = p - start + 1;
   const uint64_t mask = (uint64_t(1) << lbits) - 1;
-  info[p] = (uint64_t(q - p) << 32) | (k & mask);
-  atomicMax(&bestcnt[k >> lbits], int32_t(q - p));
+  info[start] = (uint64_t(cnt) << 32) | (k & mask);
+  atomicMax(&bestcnt[k >> lbits], int32_t(cnt));
 }
 
 // Runs of the row's largest count: the smallest tie-break key (atomicMin).
@@ -198,10 +209,9 @@ __global__ void lp_ties(int64_t nnz, int lbits, const uint64_t *__restrict__ key
                         const uint64_t *__restrict__ info, const int32_t *__restrict__ bestcnt,
                         unsigned long long *__restrict__ besth, uint64_t salt) {
   const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (p >= nnz) return;
+  if (p >= nnz || !run_start(keys, p)) return;
   const uint64_t v = info[p];
   const int32_t cnt = int32_t(v >> 32);
-  if (cnt == 0) return;
   const int64_t row = int64_t(keys[p] >> lbits);
   if (cnt == bestcnt[row]) atomicMin(&besth[row], static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt)));
 }
@@ -213,10 +223,9 @@ __global__ void lp_pick(int64_t nnz, int lbits, const uint64_t *__restrict__ key
                         const int32_t *__restrict__ lab, int32_t *__restrict__ nlab, uint64_t salt,
                         int32_t *__restrict__ changed) {
   const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (p >= nnz) return;
+  if (p >= nnz || !run_start(keys, p)) return;
   const uint64_t v = info[p];
   const int32_t cnt = int32_t(v >> 32);
-  if (cnt == 0) return;
   const int64_t row = int64_t(keys[p] >> lbits);
   const uint64_t l = v & 0xFFFFFFFFull;
   if (cnt == bestcnt[row] && mix64(l ^ salt) == besth[row]) {
@@ -267,11 +276,12 @@ size_t order_temp_bytes(int64_t n) {
 inline int lp_label_bits(int64_t n) { return std::max(bits_for(uint64_t(n)), 1); }
 
 size_t lp_temp_bytes(int64_t n, int64_t nnz) {
-  size_t a = 0;
+  size_t a = 0, b = 0;
   const int bits = 2 * lp_label_bits(n);
-  (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (uint64_t *)nullptr, (uint64_t *)nullptr,
-                                          nnz > 0 ? nnz : int64_t(1), 0, bits);
-  return a;
+  const int64_t items = nnz > 0 ? nnz : int64_t(1);
+  (void)hipcub::DeviceRadixSort::SortKeys(nullptr, a, (uint64_t *)nullptr, (uint64_t *)nullptr, items, 0, bits);
+  (void)hipcub::DeviceScan::InclusiveScan(nullptr, b, (uint64_t *)nullptr, hipcub::Max(), items);
+  return std::max(a, b);
 }
 
 // With lp, the arrays of label propagation: the labels of two rounds (n
@@ -395,7 +405,11 @@ sped_status label_order(const sped_csr *L, int32_t *pos, const OrderWs &o, hipSt
     uint64_t *besth = o.k2;
     SPED_CHECK_HIP(hipMemsetAsync(o.ncand, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(lp_reset, dim3(oblocks(n)), dim3(kOB), 0, s, n, lab, nlab, bestcnt, besth);
-    hipLaunchKernelGGL(lp_runs, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt);
+    hipLaunchKernelGGL(lp_mark, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, o.eks, o.ek);
+    SPED_CHECK_HIP(hipGetLastError());
+    tb = o.temp_bytes;
+    SPED_CHECK_HIP(hipcub::DeviceScan::InclusiveScan(o.temp, tb, o.ek, hipcub::Max(), nnz, s));
+    hipLaunchKernelGGL(lp_count, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt);
     hipLaunchKernelGGL(lp_ties, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt,
                        reinterpret_cast<unsigned long long *>(besth), salt);
     hipLaunchKernelGGL(lp_pick, dim3(oblocks(nnz)), dim3(kOB), 0, s, nnz, lbits, o.eks, o.ek, bestcnt, besth, lab,
