@@ -201,7 +201,12 @@ __global__ void lp_count(int64_t nnz, int lbits, const uint64_t *__restrict__ ke
   const int64_t cnt = p - start + 1;
   const uint64_t mask = (uint64_t(1) << lbits) - 1;
   info[start] = (uint64_t(cnt) << 32) | (k & mask);
-  atomicMax(&bestcnt[k >> lbits], int32_t(cnt));
+  // a hub's row has thousands of runs: read first, so that only counts above
+  // the current maximum reach the atomic (a stale read only costs an atomic
+  // that changes nothing)
+  int32_t *slot = &bestcnt[k >> lbits];
+  if (int32_t(cnt) > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(slot, int32_t(cnt));
 }
 
 // Runs of the row's largest count: the smallest tie-break key (atomicMin).
@@ -213,7 +218,10 @@ __global__ void lp_ties(int64_t nnz, int lbits, const uint64_t *__restrict__ key
   const uint64_t v = info[p];
   const int32_t cnt = int32_t(v >> 32);
   const int64_t row = int64_t(keys[p] >> lbits);
-  if (cnt == bestcnt[row]) atomicMin(&besth[row], static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt)));
+  if (cnt != bestcnt[row]) return;
+  const unsigned long long h = static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt));
+  // as above: only keys below the current minimum reach the atomic
+  if (h < __hip_atomic_load(&besth[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&besth[row], h);
 }
 
 // The run holding both the largest count and the smallest key (one per row:
