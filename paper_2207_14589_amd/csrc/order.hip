@@ -187,41 +187,82 @@ __global__ void lp_mark(int64_t nnz, const uint64_t *__restrict__ keys, uint64_t
   if (p < nnz) info[p] = run_start(keys, p) ? uint64_t(p) : 0;
 }
 
-// The thread at the last entry of each run reads the run's start from the
-// scanned info, stores (count << 32 | label) at info[start] (the only slot
-// of the run read later: the passes below read run starts only) and takes
-// the row's largest count with atomicMax.
-__global__ void lp_count(int64_t nnz, int lbits, const uint64_t *__restrict__ keys, uint64_t *__restrict__ info,
-                         int32_t *__restrict__ bestcnt) {
-  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (p >= nnz) return;
-  const uint64_t k = keys[p];
-  if (p + 1 < nnz && keys[p + 1] == k) return;  // not the run's last entry
-  const int64_t start = int64_t(info[p]);
-  const int64_t cnt = p - start + 1;
-  const uint64_t mask = (uint64_t(1) << lbits) - 1;
-  info[start] = (uint64_t(cnt) << 32) | (k & mask);
-  // a hub's row has thousands of runs: read first, so that only counts above
-  // the current maximum reach the atomic (a stale read only costs an atomic
-  // that changes nothing)
-  int32_t *slot = &bestcnt[k >> lbits];
-  if (int32_t(cnt) > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(slot, int32_t(cnt));
+// Lanes of a wavefront cover consecutive sorted entries, so the lanes of one
+// row are contiguous: an inclusive segmented scan over lanes of equal row
+// leaves the row's maximum (minimum) in its last lane, which alone touches
+// the row's slot.  Every lane takes part (inactive ones with the neutral
+// value and a row id of their own).
+__device__ inline int32_t seg_max_i32(int32_t v, int64_t row, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t vo = __shfl_up(v, off, 64);
+    const int64_t ro = __shfl_up(row, off, 64);
+    if (lane >= off && ro == row) v = max(v, vo);
+  }
+  return v;
+}
+__device__ inline unsigned long long seg_min_u64(unsigned long long v, int64_t row, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned long long vo = __shfl_up(v, off, 64);
+    const int64_t ro = __shfl_up(row, off, 64);
+    if (lane >= off && ro == row && vo < v) v = vo;
+  }
+  return v;
+}
+__device__ inline bool seg_last(int64_t row, int lane) {
+  const int64_t rn = __shfl_down(row, 1, 64);
+  return lane == 63 || rn != row;
 }
 
-// Runs of the row's largest count: the smallest tie-break key (atomicMin).
-__global__ void lp_ties(int64_t nnz, int lbits, const uint64_t *__restrict__ keys,
-                        const uint64_t *__restrict__ info, const int32_t *__restrict__ bestcnt,
-                        unsigned long long *__restrict__ besth, uint64_t salt) {
+// The thread at the last entry of each run reads the run's start from the
+// scanned info, stores (count << 32 | label) at info[start] (the only slot
+// of the run read later: the passes below read run starts only); the row's
+// largest count goes to bestcnt through one atomicMax per row and wavefront,
+// skipped when a read shows it would change nothing (a hub's row has
+// thousands of runs, all of count 1 in the first round).
+__global__ __launch_bounds__(kOB) void lp_count(int64_t nnz, int lbits, const uint64_t *__restrict__ keys,
+                                                uint64_t *__restrict__ info, int32_t *__restrict__ bestcnt) {
   const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
-  if (p >= nnz || !run_start(keys, p)) return;
-  const uint64_t v = info[p];
-  const int32_t cnt = int32_t(v >> 32);
-  const int64_t row = int64_t(keys[p] >> lbits);
-  if (cnt != bestcnt[row]) return;
-  const unsigned long long h = static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt));
-  // as above: only keys below the current minimum reach the atomic
-  if (h < __hip_atomic_load(&besth[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMin(&besth[row], h);
+  const int lane = threadIdx.x & 63;
+  int32_t cnt = 0;
+  int64_t row = -1 - int64_t(lane);  // distinct for lanes past the end
+  if (p < nnz) {
+    const uint64_t k = keys[p];
+    row = int64_t(k >> lbits);
+    if (p + 1 >= nnz || keys[p + 1] != k) {  // the run's last entry
+      const int64_t start = int64_t(info[p]);
+      cnt = int32_t(p - start + 1);
+      const uint64_t mask = (uint64_t(1) << lbits) - 1;
+      info[start] = (uint64_t(cnt) << 32) | (k & mask);
+    }
+  }
+  const int32_t m = seg_max_i32(cnt, row, lane);
+  if (p < nnz && seg_last(row, lane) && m > 0) {
+    int32_t *slot = &bestcnt[row];
+    if (m > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(slot, m);
+  }
+}
+
+// Runs of the row's largest count: the smallest tie-break key, one guarded
+// atomicMin per row and wavefront as in lp_count.
+__global__ __launch_bounds__(kOB) void lp_ties(int64_t nnz, int lbits, const uint64_t *__restrict__ keys,
+                                               const uint64_t *__restrict__ info,
+                                               const int32_t *__restrict__ bestcnt,
+                                               unsigned long long *__restrict__ besth, uint64_t salt) {
+  const int64_t p = int64_t(blockIdx.x) * kOB + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  unsigned long long h = ~0ull;
+  int64_t row = -1 - int64_t(lane);
+  if (p < nnz) {
+    row = int64_t(keys[p] >> lbits);
+    if (run_start(keys, p)) {
+      const uint64_t v = info[p];
+      if (int32_t(v >> 32) == bestcnt[row]) h = static_cast<unsigned long long>(mix64((v & 0xFFFFFFFFull) ^ salt));
+    }
+  }
+  const unsigned long long m = seg_min_u64(h, row, lane);
+  if (p < nnz && seg_last(row, lane) && m != ~0ull &&
+      m < __hip_atomic_load(&besth[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMin(&besth[row], m);
 }
 
 // The run holding both the largest count and the smallest key (one per row:
